@@ -1,0 +1,176 @@
+"""Benchmark of the parallel-tempering hot path on one MI355X.
+
+One step = one pass of the whole hot path over the batch: one sweep of every
+replica (1 heat-bath + 3 overrelaxation lattice sweeps, energy fused), one
+replica-exchange pass over all neighbouring temperature pairs, and the overlap /
+energy measurement.  Default workload: L = 16, 64 disorder samples x 2 chains x
+24 temperatures (beta geometric 1..8), FP32 spins with FP64 energies, Gaussian
+couplings and random unit spins from a fixed seed, inputs resident in HBM.
+
+Prints one JSON line:  value = site-updates/ns over the timed steps; roofline =
+the sweep kernel's algorithmic rate against the chip peak (durations from HIP
+events on the launch stream); cpu_baseline = the FP64 oracle on the host cores
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the chip's unit counts
+HBM_PEAK_GBS = 8000.0
+N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
+VALU_PEAK_TOPS = N_CU * LANES_PER_CU * CLOCK_GHZ / 1e3  # 39.3 T lane-instructions/s
+
+# Algorithmic VALU operations per site update (one add/mul/FMA/compare/select, one
+# transcendental or one integer op each = 1; derived in DESIGN.md, "Roofline").
+OPS_LOCAL_FIELD = 18          # 6 neighbours x 3 components, one FMA each
+OPS_OVERRELAX = 12            # s.S, |S|^2, 2(s.S)/S^2, f S - s
+OPS_HEATBATH = 45             # field norm and direction, R, w, c, sin(theta), frame, sin/cos(phi), s'
+OPS_PHILOX_PER_BLOCK = 10 * 8  # 10 rounds x (2 mul-lo, 2 mul-hi, 3 xor, key add)
+
+WORKLOADS = {
+    "plain-pt-L16-S64-C2-R24": dict(L=16, S=64, C=2, R=24, bmin=1.0, bmax=8.0, prec="fp32",
+                                    n_hb=1, n_or=3, seed=0x100642470002),
+    "plain-pt-L4-S1-C2-R8-fp64": dict(L=4, S=1, C=2, R=8, bmin=1.0, bmax=6.0, prec="fp64",
+                                      n_hb=1, n_or=3, seed=0x100642470001),
+}
+DEFAULT = "plain-pt-L16-S64-C2-R24"
+
+
+def algorithmic_ops_per_update(n_hb, n_or, prec):
+    per_hb = OPS_LOCAL_FIELD + OPS_HEATBATH + OPS_PHILOX_PER_BLOCK / (2 if prec == "fp32" else 1)
+    per_or = OPS_LOCAL_FIELD + OPS_OVERRELAX
+    return (n_hb * per_hb + n_or * per_or) / (n_hb + n_or)
+
+
+def hbm_bytes_per_launch(w, n_sweeps=1):
+    """Algorithmic HBM bytes of one LDS-resident sweep launch: every replica read and
+    written once, the couplings of every sample read once."""
+    t = 4 if w["prec"] == "fp32" else 8
+    N = w["L"] ** 3
+    slots = w["S"] * w["C"] * w["R"]
+    return slots * 2 * 3 * N * t + w["S"] * 3 * N * t
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    from oracle import hsgref
+    S = min(2, w["S"])
+    betas = hsgref.geometric_betas(w["bmin"], w["bmax"], w["R"])
+    ens = hsgref.RefEnsemble(w["L"], S, w["C"], betas, w["seed"], prec=w["prec"])
+    ens.init_couplings()
+    ens.init_spins()
+    per = S * w["C"] * w["R"] * w["L"] ** 3 * (w["n_hb"] + w["n_or"])
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        ens.sweep(1, w["n_hb"], w["n_or"])
+        ens.swap(0)
+        ens.measure()
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or n >= 100000:
+            break
+    return {"value": n * per / dt / 1e9, "unit": "site-updates/ns",
+            "cores": int(hsgref.lib().hsgref_num_threads()), "kind": "oracle",
+            "sample": "%d of %d samples x %d chains x %d temps, L=%d, %d steps (sweep + exchange + "
+                      "measurement), %.1f s" % (S, w["S"], w["C"], w["R"], w["L"], n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: every (sample, chain) is an independent Markov chain, "
+              "so N GPUs would each run 1/N of the samples with no communication; run it with "
+              "--gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1006_4247_amd as hsg
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    betas = hsg.geometric_betas(w["bmin"], w["bmax"], w["R"])
+    ens = hsg.Ensemble(w["L"], w["S"], w["C"], betas, w["seed"], precision=w["prec"], device=dev)
+    ens.init_couplings()
+    ens.init_spins()
+    stream = torch.cuda.current_stream(dev)
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        ens.sweep(1, w["n_hb"], w["n_or"])
+        if evs is not None:
+            evs[1].record(stream)
+        ens.swap(0)
+        ens.measure()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ens.check()
+    elapsed = t1 - t0
+    sweep_ms = np.array([a.elapsed_time(b) for a, b in events])
+    stats1 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
+    acc = (stats1[:, 1] - stats0[:, 1]).astype(np.float64)
+    att = (stats1[:, 0] - stats0[:, 0]).astype(np.float64)
+
+    N = w["L"] ** 3
+    slots = w["S"] * w["C"] * w["R"]
+    upd_per_step = slots * N * (w["n_hb"] + w["n_or"])
+    value = args.steps * upd_per_step / (elapsed * 1e9)
+    avg_launch_s = float(sweep_ms.mean()) / 1e3
+    ops = algorithmic_ops_per_update(w["n_hb"], w["n_or"], w["prec"]) * upd_per_step
+    alu_achieved = ops / avg_launch_s / 1e12
+    hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
+    roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_resident (one sweep of every replica per launch)",
+                "avg_launch_ms": round(avg_launch_s * 1e3, 5),
+                "hbm_algorithmic_GBs": round(hbm_achieved, 1),
+                "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
+                "sweep_site_updates_per_ns": round(upd_per_step / avg_launch_s / 1e9, 2)}
+    line = {
+        "metric": "site-updates/ns & HBM roofline %; accepted swaps per GPU-s vs plain PT",
+        "value": round(value, 3), "unit": "site-updates/ns", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": w["prec"].replace("fp", "f"),
+        "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % w["seed"],
+        "config": {"workload": args.workload, "L": w["L"], "samples": w["S"], "chains": w["C"],
+                   "temperatures": w["R"], "beta": [w["bmin"], w["bmax"]], "sweep": "%d HB + %d OR" % (w["n_hb"], w["n_or"]),
+                   "exchange": "all neighbour pairs, ascending, every step", "measure": "every step"},
+        "roofline": roofline,
+        "swap_acceptance_per_pair": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
+        "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * hsgpt.h -- C ABI of the MI355X (gfx950) library for the parallel-tempering hot
+ * path of the three-dimensional Heisenberg spin glass, the method studied in
+ * Hasenbusch & Schaefer, "Speeding up parallel tempering simulations"
+ * (arXiv:1006.4247).
+ *
+ * Model (paper Sec. I, Eq. (2)): O(3) unit spins s_x on an L^3 periodic simple
+ * cubic lattice, H = -sum_<xy> J_xy s_x.s_y with quenched Gaussian J_xy.
+ *
+ * General conventions
+ *  - Every pointer inside hsg_ensemble is a DEVICE pointer owned by the caller;
+ *    the library never allocates, frees or retains caller memory.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL = the default stream) except hsg_check, which synchronises it.
+ *  - Argument errors are found before any launch: the call returns
+ *    HSG_ERR_INVALID and hsg_last_error() says why; nothing was enqueued.
+ *  - A launch failure returns HSG_ERR_DEVICE with the HIP error string.
+ *  - Numerical trouble seen by a kernel (a non-finite spin or energy, a spin
+ *    whose norm left 1 by more than the precision's tolerance, a protocol
+ *    length outside [0, anneal_K_max], a temperature label outside [0, R)) is
+ *    latched in *guard (bits 1, 2, 4) and reported by hsg_check as
+ *    HSG_ERR_NUMERIC.  Out-of-range values are clamped before use, so a
+ *    corrupted label or protocol length never addresses outside its ensemble.
+ *  - Calls on one ensemble must not overlap in time (use one stream per
+ *    ensemble); distinct ensembles may be driven from distinct threads.
+ *
+ * Lattice and layouts
+ *  - site x = i + L(j + L k), 0 <= i,j,k < L; L even, 2 <= L <= 64.
+ *  - parity p(x) = (i+j+k) mod 2: p = 0 is the white sublattice W, p = 1 the
+ *    black one B (paper Sec. III.A).  Index inside a sublattice:
+ *    h = floor(i/2) + (L/2)(j + L k), 0 <= h < N/2, N = L^3.
+ *  - spins:      [S][C][R][3][2][N/2] of T (component, parity, h); T = double
+ *                (HSG_FP64) or float (HSG_FP32).  Slot r of chain c of sample s
+ *                holds one physical configuration.
+ *  - couplings:  [S][3][2][N/2] of T: J(x, mu) joins x and x + e_mu, stored at
+ *                the parity and index of x.
+ *  - betas:      [R] double, strictly ascending (not checked).
+ *  - per slot:   temp_of_slot, rt_state int32, energy double, sweep_ctr uint32,
+ *                rt_trips int64, all [S][C][R]; slot_of_temp int32 [S][C][R]
+ *                is indexed by temperature.
+ *  - per chain:  swap_ctr uint32 [S][C]; per pair: swap_stats int64
+ *                [S][C][R-1][2] (attempts, accepts).
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed
+ * (low word, high word); counters (c0, c1, c2, c3):
+ *    couplings (x, mu, sample_base + s, 1<<24)
+ *    spin init (x, 0, slot_g, 2<<24)
+ *    heat-bath (h or h mod N/4, sweep_ctr[slot], slot_g, 3<<24 | hs<<16)
+ *    exchange  (pair i, swap_ctr[chain], chain_base + s C + c, 4<<24)
+ * with slot_g = slot_base + (s C + c) R + r and hs = 2*(heat-bath sweep) + parity.
+ * 52-bit uniforms ((w0<<20 | w1>>12) + 1/2) 2^-52 serve FP64 and all
+ * initialisation and exchange decisions; FP32 heat-bath uses 23-bit uniforms
+ * ((w>>9) + 1/2) 2^-23, one block per site pair (h, h + N/4).
+ */
+#ifndef HSGPT_H
+#define HSGPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSG_ABI_VERSION 1
+
+typedef enum {
+    HSG_OK = 0,
+    HSG_ERR_INVALID = 1,
+    HSG_ERR_DEVICE = 2,
+    HSG_ERR_NUMERIC = 3,
+    HSG_ERR_UNSUPPORTED = 4
+} hsg_status;
+
+typedef enum { HSG_FP64 = 0, HSG_FP32 = 1 } hsg_precision;
+
+/* One size class: S samples (coupling sets) x C chains x R temperatures. */
+typedef struct hsg_ensemble {
+    int32_t L, n_samples, n_chains, n_temps;
+    int32_t precision; /* hsg_precision */
+    int32_t reserved0;
+    uint32_t sample_base, chain_base, slot_base; /* global stream offsets */
+    uint32_t reserved1;
+    uint64_t seed;
+    /* state */
+    void* spins;
+    void* couplings;
+    const double* betas;
+    int32_t* temp_of_slot;
+    int32_t* slot_of_temp;
+    double* energy;
+    uint32_t* sweep_ctr;
+    uint32_t* swap_ctr;
+    int64_t* swap_stats;
+    int32_t* rt_state;
+    int64_t* rt_trips;
+    int32_t* guard;
+    /* annealed exchange (may be NULL unless hsg_anneal_swap is called) */
+    const int32_t* anneal_K;      /* [R-1] protocol lengths, 0..anneal_K_max */
+    const double* anneal_lambda;  /* [R-1][anneal_K_max] interior betas, or NULL = linear */
+    int32_t anneal_K_max;
+    int32_t reserved2;
+    void* scratch;                /* hsg_scratch_bytes() bytes, 256-byte aligned: needed by
+                                     hsg_anneal_swap and by sweeps on the streaming path */
+    double* work;                 /* [S][C][R-1][2] W_up, W_down of the last call */
+    /* measurement outputs (may be NULL unless hsg_measure is called) */
+    double* Q;      /* [S][R][3][3] */
+    double* chi;    /* [S][R]       */
+    double* e_temp; /* [S][C][R]    */
+} hsg_ensemble;
+
+/* Tuning knobs of the sweep kernels (0 = library default). */
+typedef struct hsg_tuning {
+    int32_t path;           /* 0 auto, 1 LDS-resident lattice, 2 streaming half-sweeps */
+    int32_t block_threads;  /* threads per workgroup */
+    int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */
+    int32_t reserved;
+} hsg_tuning;
+
+int hsg_abi_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* hsg_last_error(void);
+
+/* Bytes of device scratch one ensemble needs for hsg_anneal_swap. */
+size_t hsg_scratch_bytes(const hsg_ensemble* ens);
+
+/* Draw J_xy ~ N(0,1) for every sample (paper Sec. I: Gaussian couplings of zero
+ * mean and unit width), Box-Muller cosine branch from two 52-bit uniforms,
+ * computed in FP64 and rounded to T. */
+hsg_status hsg_init_couplings(const hsg_ensemble* ens, int n_ens, void* stream);
+
+/* Start every slot: uniform unit spins (z = 2 r1 - 1, azimuth 2 pi r2), or the
+ * cold start (1,0,0) of the paper's Sec. IV.C if cold != 0.  Resets labels to
+ * the identity, counters, statistics, round-trip state (slot 0 starts at the
+ * highest temperature) and the guard, and computes every slot's energy. */
+hsg_status hsg_init_spins(const hsg_ensemble* ens, int n_ens, int cold, void* stream);
+
+/* n_sweeps sweeps of every slot at its own temperature betas[temp_of_slot].
+ * One sweep = n_hb heat-bath lattice sweeps then n_or overrelaxation lattice
+ * sweeps, each as the W then the B half-sweep (paper Sec. III.C; checkerboard
+ * order instead of the paper's typewriter order, same stationary law).
+ * Heat-bath: new spin along S_x with density ~ exp(beta S_x.s); overrelaxation:
+ * s' = 2 (s.S)/S^2 S - s (identity if S = 0).  Leaves energy[] = H of the
+ * final configurations (fused into the last half-sweep) and advances
+ * sweep_ctr by n_sweeps.  n_sweeps >= 0, n_hb in [0,127], n_or >= 0. */
+hsg_status hsg_sweep(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                     void* stream);
+hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb,
+                           int n_or, const hsg_tuning* tuning, void* stream);
+
+/* H = -sum over bonds J s.s (Eq. (2)) of every slot, from scratch, in FP64.
+ * H_out: device array of sum_e S_e C_e R_e doubles, ensembles in order, slot
+ * layout [S][C][R]; NULL writes ens[e].energy instead. */
+hsg_status hsg_energy(const hsg_ensemble* ens, int n_ens, double* H_out, void* stream);
+
+/* Replica exchange, Eq. (1): for each selected pair i of every chain the
+ * configurations at beta_i and beta_{i+1} exchange temperature labels iff
+ * ln u < (beta_{i+1} - beta_i)(H_{i+1} - H_i).  pairing 0: all pairs in
+ * ascending order; 1: even i; 2: odd i.  Updates labels, swap_stats,
+ * round-trip state (paper Sec. IV.B) and swap_ctr. */
+hsg_status hsg_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* stream);
+
+/* Annealed exchange of the pairs i with i mod 2 == parity (a nonequilibrium-
+ * switch exchange, the prior art the paper cites in Sec. I).  With
+ * a = beta_i < l_1 < ... < l_K < b = beta_{i+1} (K = anneal_K[i]; l_k from
+ * anneal_lambda or linear), the configuration x at a takes K sweeps at
+ * l_1..l_K in forward order and y at b takes K sweeps at l_K..l_1 in adjoint
+ * (reversed) order, each sweep of n_hb heat-bath and n_or overrelaxation
+ * lattice sweeps; W_up = sum_k (l_{k+1}-l_k) H(x_k), W_dn likewise downwards.
+ * Accept iff ln u < -(W_up + W_dn): the annealed states take the exchanged
+ * temperatures; otherwise both configurations keep their states.  K = 0 is
+ * Eq. (1) exactly.  Needs anneal_K, scratch (hsg_scratch_bytes) and work. */
+hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n_hb, int n_or,
+                           void* stream);
+
+/* Overlap (paper Sec. II): Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between the
+ * chain-0 and chain-1 configurations at each temperature, chi = Q:Q / N, and
+ * e_temp = H/N by temperature (the paper's E is -e).  Q and chi need C >= 2. */
+hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream);
+
+/* Synchronise `stream`, then report the guards: HSG_ERR_NUMERIC if any is set. */
+hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream);
+
+/* --- learned annealing schedule: a 2-hidden-layer MLP (FP32) ---------------
+ * Layout of `params` (floats): W1[H][I], b1[H], W2[H][H], b2[H], W3[O][H], b3[O]
+ * with tanh hidden activations and a linear output.  x: [B][I], y: [B][O];
+ * 1 <= I, O <= 64, 1 <= H <= 256.  `acts` ([B][4H] floats, caller-owned) keeps
+ * the two hidden activations (written by the forward pass) and the two layer
+ * errors (written by the backward pass).  The backward pass reads dy [B][O]
+ * (dLoss/dy per sample) and overwrites dparams (same layout as params) with
+ * the gradient summed over the batch in a fixed order.  Adam: m, v same layout
+ * as params; step t >= 1 (bias correction). */
+hsg_status hsg_mlp_forward(const float* params, int I, int H, int O, const float* x, int B,
+                           float* acts, float* y, void* stream);
+hsg_status hsg_mlp_backward(const float* params, int I, int H, int O, const float* x, int B,
+                            float* acts, const float* dy, float* dparams, void* stream);
+hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
+                        float beta1, float beta2, float eps, int t, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSGPT_H */

@@ -1,0 +1,279 @@
+// C ABI of the hsgpt library: argument validation (before any launch),
+// thread-local error reporting and dispatch to the kernel launchers.
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+hsg_status fail(hsg_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+hsg_status ok() {
+    g_err[0] = '\0';
+    return HSG_OK;
+}
+
+hsg_status device(hipError_t err, const char* what) {
+    if (err == hipSuccess) return ok();
+    return fail(HSG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(err));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+enum Need : unsigned { kState = 1u, kAnneal = 2u, kMeasure = 4u, kScratch = 8u };
+
+hsg_status check_shape(const hsg_ensemble& e, int idx) {
+    if (e.L < 2 || e.L > 64 || (e.L & 1))
+        return fail(HSG_ERR_INVALID, "ensemble %d: L = %d must be even and in [2, 64]", idx, e.L);
+    if (e.n_samples < 1 || e.n_chains < 1 || e.n_temps < 2)
+        return fail(HSG_ERR_INVALID, "ensemble %d: need n_samples >= 1, n_chains >= 1, n_temps >= 2 (got %d, %d, %d)",
+                    idx, e.n_samples, e.n_chains, e.n_temps);
+    if (e.precision != HSG_FP64 && e.precision != HSG_FP32)
+        return fail(HSG_ERR_INVALID, "ensemble %d: unknown precision %d", idx, e.precision);
+    const long long slots = static_cast<long long>(e.n_samples) * e.n_chains * e.n_temps;
+    if (slots * e.L * e.L * e.L * 3 > (1LL << 40) || slots > (1LL << 30))
+        return fail(HSG_ERR_INVALID, "ensemble %d: too many sites", idx);
+    return HSG_OK;
+}
+
+hsg_status check_one(const hsg_ensemble& e, int idx, unsigned need) {
+    hsg_status st = check_shape(e, idx);
+    if (st != HSG_OK) return st;
+    const void* must[] = {e.spins, e.couplings, e.betas, e.temp_of_slot, e.slot_of_temp, e.energy,
+                          e.sweep_ctr, e.swap_ctr, e.swap_stats, e.rt_state, e.rt_trips, e.guard};
+    const char* names[] = {"spins", "couplings", "betas", "temp_of_slot", "slot_of_temp", "energy",
+                           "sweep_ctr", "swap_ctr", "swap_stats", "rt_state", "rt_trips", "guard"};
+    for (int k = 0; k < 12; ++k)
+        if (!must[k]) return fail(HSG_ERR_INVALID, "ensemble %d: %s is NULL", idx, names[k]);
+    if (!aligned(e.spins, 16) || !aligned(e.couplings, 16))
+        return fail(HSG_ERR_INVALID, "ensemble %d: spins and couplings must be 16-byte aligned", idx);
+    if (!aligned(e.betas, 8) || !aligned(e.energy, 8) || !aligned(e.swap_stats, 8) || !aligned(e.rt_trips, 8))
+        return fail(HSG_ERR_INVALID, "ensemble %d: double/int64 arrays must be 8-byte aligned", idx);
+    if (need & kAnneal) {
+        if (!e.anneal_K || !e.work)
+            return fail(HSG_ERR_INVALID, "ensemble %d: annealed exchange needs anneal_K and work", idx);
+        if (e.anneal_K_max < 0 || e.anneal_K_max > 4096)
+            return fail(HSG_ERR_INVALID, "ensemble %d: anneal_K_max = %d outside [0, 4096]", idx, e.anneal_K_max);
+        if (e.anneal_lambda && e.anneal_K_max == 0)
+            return fail(HSG_ERR_INVALID, "ensemble %d: anneal_lambda given with anneal_K_max = 0", idx);
+    }
+    if ((need & (kAnneal | kScratch)) && (!e.scratch || !aligned(e.scratch, 256)))
+        return fail(HSG_ERR_INVALID, "ensemble %d: scratch (hsg_scratch_bytes bytes, 256-byte aligned) is required", idx);
+    if (need & kMeasure) {
+        if (!e.e_temp) return fail(HSG_ERR_INVALID, "ensemble %d: e_temp is NULL", idx);
+        if (e.n_chains >= 2 && (!e.Q || !e.chi))
+            return fail(HSG_ERR_INVALID, "ensemble %d: Q and chi are required with n_chains >= 2", idx);
+    }
+    return HSG_OK;
+}
+
+hsg_status check_all(const hsg_ensemble* ens, int n_ens, unsigned need) {
+    if (!ens || n_ens < 1) return fail(HSG_ERR_INVALID, "need at least one ensemble (ens=%p, n_ens=%d)",
+                                       static_cast<const void*>(ens), n_ens);
+    for (int i = 0; i < n_ens; ++i) {
+        hsg_status s = check_one(ens[i], i, need);
+        if (s != HSG_OK) return s;
+    }
+    return HSG_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+bool use_resident(const hsg_ensemble& e, const hsg_tuning* t) {
+    const int path = t ? t->path : 0;
+    if (path == 2) return false;
+    return hsg::resident_supported(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsg_abi_version(void) { return HSG_ABI_VERSION; }
+
+const char* hsg_last_error(void) { return g_err; }
+
+size_t hsg_scratch_bytes(const hsg_ensemble* ens) {
+    if (!ens || check_shape(*ens, 0) != HSG_OK) return 0;
+    return hsg::scratch_layout(*ens).total;
+}
+
+hsg_status hsg_init_couplings(const hsg_ensemble* ens, int n_ens, void* stream) {
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_init_couplings(ens[i], as_stream(stream));
+        if (err != hipSuccess) return device(err, "init_couplings");
+    }
+    return ok();
+}
+
+hsg_status hsg_init_spins(const hsg_ensemble* ens, int n_ens, int cold, void* stream) {
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_init_spins(ens[i], cold, as_stream(stream));
+        if (err != hipSuccess) return device(err, "init_spins");
+    }
+    return ok();
+}
+
+hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                           const hsg_tuning* tuning, void* stream) {
+    if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
+        return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
+                    n_sweeps, n_hb, n_or);
+    if (tuning && (tuning->path < 0 || tuning->path > 2 || tuning->block_threads < 0 ||
+                   tuning->replicas_per_block < 0))
+        return fail(HSG_ERR_INVALID, "bad tuning values");
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        if (tuning && tuning->path == 1 && !hsg::resident_supported(ens[i]))
+            return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the LDS-resident path", i, ens[i].L);
+        if (!use_resident(ens[i], tuning)) {
+            s = check_one(ens[i], i, kScratch);
+            if (s != HSG_OK) return s;
+        }
+    }
+    if (n_sweeps == 0) return ok();
+    for (int i = 0; i < n_ens; ++i) {
+        const int nt = tuning ? tuning->block_threads : 0;
+        hipError_t err;
+        if (use_resident(ens[i], tuning)) {
+            err = hsg::launch_resident(ens[i], n_sweeps, n_hb, n_or, 0, 0, nt, as_stream(stream));
+        } else {
+            const int rb = tuning ? tuning->replicas_per_block : 0;
+            err = hsg::launch_stream_sweeps(ens[i], n_sweeps, n_hb, n_or, nt, rb, as_stream(stream));
+        }
+        if (err == hipErrorInvalidValue)
+            return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: no kernel instance for block_threads = %d", i, nt);
+        if (err != hipSuccess) return device(err, "sweep");
+    }
+    return ok();
+}
+
+hsg_status hsg_sweep(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                     void* stream) {
+    return hsg_sweep_tuned(ens, n_ens, n_sweeps, n_hb, n_or, nullptr, stream);
+}
+
+hsg_status hsg_energy(const hsg_ensemble* ens, int n_ens, double* H_out, void* stream) {
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    if (H_out && !aligned(H_out, 8)) return fail(HSG_ERR_INVALID, "H_out must be 8-byte aligned");
+    size_t off = 0;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_energy(ens[i], H_out ? H_out + off : nullptr, as_stream(stream));
+        if (err != hipSuccess) return device(err, "energy");
+        off += static_cast<size_t>(ens[i].n_samples) * ens[i].n_chains * ens[i].n_temps;
+    }
+    return ok();
+}
+
+hsg_status hsg_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* stream) {
+    if (pairing < 0 || pairing > 2) return fail(HSG_ERR_INVALID, "pairing must be 0, 1 or 2 (got %d)", pairing);
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_swap(ens[i], pairing, as_stream(stream));
+        if (err != hipSuccess) return device(err, "swap");
+    }
+    return ok();
+}
+
+hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n_hb, int n_or,
+                           void* stream) {
+    if (parity < 0 || parity > 1) return fail(HSG_ERR_INVALID, "parity must be 0 or 1 (got %d)", parity);
+    if (n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
+        return fail(HSG_ERR_INVALID, "need 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1");
+    hsg_status s = check_all(ens, n_ens, kState | kAnneal);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err;
+        if (hsg::resident_supported(ens[i]))
+            err = hsg::launch_resident(ens[i], 0, n_hb, n_or, 1, parity, 0, as_stream(stream));
+        else
+            err = hsg::launch_stream_anneal(ens[i], parity, n_hb, n_or, 0, as_stream(stream));
+        if (err != hipSuccess) return device(err, "anneal legs");
+        err = hsg::launch_anneal_decide(ens[i], parity, as_stream(stream));
+        if (err != hipSuccess) return device(err, "anneal decision");
+    }
+    return ok();
+}
+
+hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream) {
+    hsg_status s = check_all(ens, n_ens, kState | kMeasure);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_measure(ens[i], as_stream(stream));
+        if (err != hipSuccess) return device(err, "measure");
+    }
+    return ok();
+}
+
+hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream) {
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    hipError_t err = hipStreamSynchronize(as_stream(stream));
+    if (err != hipSuccess) return device(err, "check: stream synchronize");
+    for (int i = 0; i < n_ens; ++i) {
+        int32_t g = 0;
+        err = hipMemcpy(&g, ens[i].guard, sizeof(g), hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return device(err, "check: read guard");
+        if (g != 0)
+            return fail(HSG_ERR_NUMERIC, "ensemble %d: guard = %d (%s%s%s)", i, g,
+                        (g & 1) ? "non-finite or non-unit spin or energy; " : "",
+                        (g & 2) ? "protocol length outside [0, anneal_K_max]; " : "",
+                        (g & 4) ? "temperature label outside [0, R)" : "");
+    }
+    return ok();
+}
+
+static hsg_status mlp_check(int I, int H, int O, int B) {
+    if (I < 1 || I > 64 || O < 1 || O > 64 || H < 1 || H > 256 || B < 0)
+        return fail(HSG_ERR_INVALID, "MLP sizes out of range (I=%d H=%d O=%d B=%d)", I, H, O, B);
+    return HSG_OK;
+}
+
+hsg_status hsg_mlp_forward(const float* params, int I, int H, int O, const float* x, int B,
+                           float* acts, float* y, void* stream) {
+    hsg_status s = mlp_check(I, H, O, B);
+    if (s != HSG_OK) return s;
+    if (!params || (B > 0 && (!x || !acts || !y))) return fail(HSG_ERR_INVALID, "MLP forward: NULL pointer");
+    return device(hsg::launch_mlp_forward(params, I, H, O, x, B, acts, y, as_stream(stream)), "mlp_forward");
+}
+
+hsg_status hsg_mlp_backward(const float* params, int I, int H, int O, const float* x, int B,
+                            float* acts, const float* dy, float* dparams, void* stream) {
+    hsg_status s = mlp_check(I, H, O, B);
+    if (s != HSG_OK) return s;
+    if (!params || !dparams || (B > 0 && (!x || !acts || !dy)))
+        return fail(HSG_ERR_INVALID, "MLP backward: NULL pointer");
+    return device(hsg::launch_mlp_backward(params, I, H, O, x, B, acts, dy, dparams, as_stream(stream)),
+                  "mlp_backward");
+}
+
+hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
+                        float beta1, float beta2, float eps, int t, void* stream) {
+    if (!params || !grad || !m || !v || n < 0 || t < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(HSG_ERR_INVALID, "MLP adam: bad arguments");
+    if (n == 0) return ok();
+    return device(hsg::launch_mlp_adam(params, grad, m, v, n, lr, beta1, beta2, eps, t, as_stream(stream)),
+                  "mlp_adam");
+}
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// Initialisation, energy, replica-exchange and measurement kernels.
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace hsg {
+
+// ---------------------------------------------------------------- initialisation
+// J(x, mu) ~ N(0,1) (paper Sec. I), Box-Muller cosine branch in FP64 from two
+// 52-bit uniforms of the block (x, mu, sample, 1<<24); stored at [s][mu][p(x)][h(x)].
+template <typename T>
+__global__ void k_init_couplings(hsg_ensemble e) {
+    const int L = e.L;
+    const int N = L * L * L, NH = N / 2;
+    const size_t total = static_cast<size_t>(e.n_samples) * N * 3;
+    const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int mu = static_cast<int>(id % 3);
+    const int x = static_cast<int>((id / 3) % N);
+    const int s = static_cast<int>(id / (3 * static_cast<size_t>(N)));
+    const Words w = philox(static_cast<uint32_t>(x), static_cast<uint32_t>(mu), e.sample_base + s,
+                           kTagCoupling << 24, key_lo(e.seed), key_hi(e.seed));
+    const double r1 = u01_52(w.w0, w.w1), r2 = u01_52(w.w2, w.w3);
+    const double gval = sqrt(-2.0 * log(r1)) * cos(2.0 * 3.14159265358979323846 * r2);
+    const int i = x % L, row = x / L, j = row % L, k = row / L;
+    const int p = (i + j + k) & 1;
+    const int h = i / 2 + (L / 2) * row;
+    T* J = static_cast<T*>(e.couplings) + static_cast<size_t>(s) * 3 * N;
+    J[(mu * 2 + p) * NH + h] = static_cast<T>(gval);
+}
+
+// Uniform unit spins: z = 2 r1 - 1, azimuth 2 pi r2 (block (x, 0, slot, 2<<24));
+// cold start (1, 0, 0).
+template <typename T>
+__global__ void k_init_spins(hsg_ensemble e, int cold) {
+    const int L = e.L;
+    const int N = L * L * L, NH = N / 2;
+    const size_t n_slots = static_cast<size_t>(e.n_samples) * e.n_chains * e.n_temps;
+    const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= n_slots * N) return;
+    const int x = static_cast<int>(id % N);
+    const size_t slot = id / N;
+    double v0 = 1.0, v1 = 0.0, v2 = 0.0;
+    if (!cold) {
+        const Words w = philox(static_cast<uint32_t>(x), 0u, e.slot_base + static_cast<uint32_t>(slot),
+                               kTagInit << 24, key_lo(e.seed), key_hi(e.seed));
+        const double r1 = u01_52(w.w0, w.w1), r2 = u01_52(w.w2, w.w3);
+        const double z = 2.0 * r1 - 1.0;
+        const double rho = 2.0 * sqrt(r1 * (1.0 - r1));
+        const double phi = 2.0 * 3.14159265358979323846 * r2;
+        v0 = rho * cos(phi);
+        v1 = rho * sin(phi);
+        v2 = z;
+    }
+    const int i = x % L, row = x / L, j = row % L, k = row / L;
+    const int p = (i + j + k) & 1;
+    const int h = i / 2 + (L / 2) * row;
+    T* s = static_cast<T*>(e.spins) + slot * 3 * N;
+    s[(0 * 2 + p) * NH + h] = static_cast<T>(v0);
+    s[(1 * 2 + p) * NH + h] = static_cast<T>(v1);
+    s[(2 * 2 + p) * NH + h] = static_cast<T>(v2);
+}
+
+__global__ void k_reset_state(hsg_ensemble e) {
+    const int R = e.n_temps;
+    const int n_chains = e.n_samples * e.n_chains;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id == 0) *e.guard = 0;
+    if (id >= n_chains * R) return;
+    const int r = id % R, ch = id / R;
+    e.temp_of_slot[id] = r;
+    e.slot_of_temp[id] = r;
+    e.sweep_ctr[id] = 0u;
+    e.rt_state[id] = r == 0 ? 1 : 0;
+    e.rt_trips[id] = 0;
+    if (r < R - 1) {
+        e.swap_stats[(static_cast<size_t>(ch) * (R - 1) + r) * 2] = 0;
+        e.swap_stats[(static_cast<size_t>(ch) * (R - 1) + r) * 2 + 1] = 0;
+    }
+    if (r == 0) e.swap_ctr[ch] = 0u;
+}
+
+// ---------------------------------------------------------------- energy
+// H = -sum_{x in W} s_x . S_x in FP64 (equal to the bond sum of Eq. (2): every
+// bond has exactly one white end).  One workgroup per slot.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_energy(hsg_ensemble e, double* out) {
+    __shared__ double red[NT / 64];
+    const int L = e.L;
+    const int N = L * L * L, NH = N / 2;
+    const int slot = blockIdx.x;
+    const int C = e.n_chains, R = e.n_temps;
+    const int smp = slot / (C * R);
+    const T* s = static_cast<const T*>(e.spins) + static_cast<size_t>(slot) * 3 * N;
+    const T* J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    double acc = 0.0;
+    for (int h = threadIdx.x; h < NH; h += NT) {
+        const Nbr nb = neighbours<0>(h, 0, L);
+        double S[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            const double jp = J[(mu * 2 + 0) * NH + h];
+            const double jm = J[(mu * 2 + 1) * NH + nb.n[2 * mu + 1]];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S[a] += jp * static_cast<double>(s[(a * 2 + 1) * NH + nb.n[2 * mu]]);
+                S[a] += jm * static_cast<double>(s[(a * 2 + 1) * NH + nb.n[2 * mu + 1]]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc += static_cast<double>(s[(a * 2 + 0) * NH + h]) * S[a];
+    }
+    const double tot = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) {
+        const double H = -tot;
+        if (!isfinite(H)) atomicOr(e.guard, 1);
+        if (out)
+            out[slot] = H;
+        else
+            e.energy[slot] = H;
+    }
+}
+
+// ---------------------------------------------------------------- exchange
+__device__ __forceinline__ void roundtrip_update(int R, const int* tos, int* st, long long* trips) {
+    for (int r = 0; r < R; ++r) {
+        const int T = tos[r];  // range-checked by the caller's labels
+        if (T == 0) {
+            if (st[r] == 2) trips[r] += 1;
+            st[r] = 1;
+        } else if (T == R - 1) {
+            if (st[r] == 1) st[r] = 2;
+        }
+    }
+}
+
+// x = sot[i], y = sot[i + 1] (already range-checked by the caller)
+__device__ __forceinline__ void relabel(int* tos, int* sot, int i, int x, int y) {
+    sot[i] = y;
+    sot[i + 1] = x;
+    tos[x] = i + 1;
+    tos[y] = i;
+}
+
+__device__ __forceinline__ double swap_uniform(const hsg_ensemble& e, int i, uint32_t n, uint32_t cg) {
+    const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
+    return u01_52(w.w0, w.w1);
+}
+
+// Eq. (1): accept iff ln u < (beta_{i+1} - beta_i)(H_{i+1} - H_i).  One thread per chain.
+__global__ void k_swap(hsg_ensemble e, int pairing) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_chains) return;
+    const int R = e.n_temps;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    const double* en = e.energy + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    for (int i = 0; i < R - 1; ++i) {
+        if (pairing == 1 && (i & 1)) continue;
+        if (pairing == 2 && !(i & 1)) continue;
+        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+        const double delta = (e.betas[i + 1] - e.betas[i]) * (en[y] - en[x]);
+        const double u = swap_uniform(e, i, n, cg);
+        st[2 * i] += 1;
+        if (log(u) < delta) {
+            relabel(tos, sot, i, x, y);
+            st[2 * i + 1] += 1;
+        }
+    }
+    e.swap_ctr[ch] = n + 1u;
+    roundtrip_update(R, tos, e.rt_state + static_cast<size_t>(ch) * R,
+                     reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R);
+}
+
+// Annealed exchange decision: accept iff ln u < -(W_up + W_dn); the annealed
+// states (candidate buffer) replace the accepted slots, energies follow.
+__global__ void k_anneal_decide(hsg_ensemble e, int parity) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_chains) return;
+    const int R = e.n_temps;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const double* cen = reinterpret_cast<const double*>(scr + sl.cand_energy);
+    int* flags = reinterpret_cast<int*>(scr + sl.flags);
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    double* en = e.energy + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    for (int r = 0; r < R; ++r) flags[ch * R + r] = 0;
+    for (int i = parity; i < R - 1; i += 2) {
+        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+        int K = e.anneal_K[i];
+        K = K < 0 ? 0 : (K > e.anneal_K_max ? e.anneal_K_max : K);
+        const double wsum = W[2 * i] + W[2 * i + 1];
+        const double u = swap_uniform(e, i, n, cg);
+        st[2 * i] += 1;
+        if (log(u) < -wsum) {
+            en[x] = cen[ch * R + x];
+            en[y] = cen[ch * R + y];
+            if (K > 0) {
+                flags[ch * R + x] = 1;
+                flags[ch * R + y] = 1;
+            }
+            relabel(tos, sot, i, x, y);
+            st[2 * i + 1] += 1;
+        }
+    }
+    e.swap_ctr[ch] = n + 1u;
+    roundtrip_update(R, tos, e.rt_state + static_cast<size_t>(ch) * R,
+                     reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R);
+}
+
+template <typename T>
+__global__ void k_anneal_copyback(hsg_ensemble e) {
+    const int slot = blockIdx.x;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const int* flags = reinterpret_cast<const int*>(scr + sl.flags);
+    if (!flags[slot]) return;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
+    uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
+    const size_t nv = 3 * N * sizeof(T) / 16;
+    for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+}
+
+// ---------------------------------------------------------------- measurement
+// Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between chains 0 and 1 at temperature b,
+// chi = Q:Q / N (paper Sec. II); e = H/N by temperature.  Workgroup per (sample, b).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e) {
+    __shared__ double red[NT / 64];
+    __shared__ double qs[9];
+    const int N = e.L * e.L * e.L;
+    const int R = e.n_temps, C = e.n_chains;
+    const int smp = blockIdx.x / R, b = blockIdx.x % R;
+    for (int c = threadIdx.x; c < C; c += NT) {
+        const int slot = (smp * C + c) * R + label(e.slot_of_temp[(smp * C + c) * R + b], R, e.guard);
+        e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = e.energy[slot] / static_cast<double>(N);
+    }
+    if (C < 2 || e.Q == nullptr) return;  // uniform over the block
+    const int s1 = (smp * C + 0) * R + label(e.slot_of_temp[(smp * C + 0) * R + b], R, e.guard);
+    const int s2 = (smp * C + 1) * R + label(e.slot_of_temp[(smp * C + 1) * R + b], R, e.guard);
+    const T* a = static_cast<const T*>(e.spins) + static_cast<size_t>(s1) * 3 * N;
+    const T* c = static_cast<const T*>(e.spins) + static_cast<size_t>(s2) * 3 * N;
+    double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = threadIdx.x; x < N; x += NT) {
+        const double a0 = a[x], a1 = a[N + x], a2 = a[2 * N + x];
+        const double c0 = c[x], c1 = c[N + x], c2 = c[2 * N + x];
+        q[0] += a0 * c0; q[1] += a0 * c1; q[2] += a0 * c2;
+        q[3] += a1 * c0; q[4] += a1 * c1; q[5] += a1 * c2;
+        q[6] += a2 * c0; q[7] += a2 * c1; q[8] += a2 * c2;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double t = block_sum<NT>(q[k], red);
+        if (threadIdx.x == 0) qs[k] = t;
+    }
+    if (threadIdx.x == 0) {
+        double chi = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = qs[k];
+            chi += qs[k] * qs[k];
+        }
+        e.chi[static_cast<size_t>(smp) * R + b] = chi / static_cast<double>(N);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned nblk(size_t n, unsigned t) { return static_cast<unsigned>((n + t - 1) / t); }
+
+hipError_t launch_init_couplings(const hsg_ensemble& e, hipStream_t st) {
+    const size_t total = static_cast<size_t>(e.n_samples) * e.L * e.L * e.L * 3;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_init_couplings<double>, dim3(nblk(total, 256)), dim3(256), 0, st, e);
+    else
+        hipLaunchKernelGGL(k_init_couplings<float>, dim3(nblk(total, 256)), dim3(256), 0, st, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_spins(const hsg_ensemble& e, int cold, hipStream_t st) {
+    const size_t n_slots = static_cast<size_t>(e.n_samples) * e.n_chains * e.n_temps;
+    const size_t total = n_slots * e.L * e.L * e.L;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_init_spins<double>, dim3(nblk(total, 256)), dim3(256), 0, st, e, cold);
+    else
+        hipLaunchKernelGGL(k_init_spins<float>, dim3(nblk(total, 256)), dim3(256), 0, st, e, cold);
+    hipLaunchKernelGGL(k_reset_state, dim3(nblk(n_slots, 256)), dim3(256), 0, st, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return launch_energy(e, nullptr, st);
+}
+
+hipError_t launch_energy(const hsg_ensemble& e, double* out, hipStream_t st) {
+    const int n_slots = e.n_samples * e.n_chains * e.n_temps;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL((k_energy<double, 256>), dim3(n_slots), dim3(256), 0, st, e, out);
+    else
+        hipLaunchKernelGGL((k_energy<float, 256>), dim3(n_slots), dim3(256), 0, st, e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st) {
+    const int n_chains = e.n_samples * e.n_chains;
+    hipLaunchKernelGGL(k_swap, dim3(nblk(n_chains, 64)), dim3(64), 0, st, e, pairing);
+    return hipGetLastError();
+}
+
+hipError_t launch_anneal_decide(const hsg_ensemble& e, int parity, hipStream_t st) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int n_slots = n_chains * e.n_temps;
+    hipLaunchKernelGGL(k_anneal_decide, dim3(nblk(n_chains, 64)), dim3(64), 0, st, e, parity);
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_anneal_copyback<double>, dim3(n_slots), dim3(256), 0, st, e);
+    else
+        hipLaunchKernelGGL(k_anneal_copyback<float>, dim3(n_slots), dim3(256), 0, st, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st) {
+    const int blocks = e.n_samples * e.n_temps;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL((k_measure<double, 256>), dim3(blocks), dim3(256), 0, st, e);
+    else
+        hipLaunchKernelGGL((k_measure<float, 256>), dim3(blocks), dim3(256), 0, st, e);
+    return hipGetLastError();
+}
+
+}  // namespace hsg

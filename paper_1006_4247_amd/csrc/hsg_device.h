@@ -1,0 +1,264 @@
+// Device-side building blocks of the hsgpt library (gfx950, wave64).
+//
+//  * Philox4x32-10 counter-based generator (Salmon et al., SC'11)
+//  * uniform maps (23-bit binary32, 52-bit binary64, both open intervals)
+//  * sublattice index arithmetic of the W/B checkerboard (paper Sec. III.A)
+//  * single-site heat-bath and overrelaxation updates (paper Sec. III.C)
+//  * deterministic wave64 + LDS block reductions in FP64
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hsgpt.h"
+
+namespace hsg {
+
+constexpr uint32_t kTagCoupling = 1u;
+constexpr uint32_t kTagInit = 2u;
+constexpr uint32_t kTagHeatbath = 3u;
+constexpr uint32_t kTagSwap = 4u;
+
+// ---------------------------------------------------------------- Philox4x32-10
+struct Words {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float u01_23(uint32_t w) {
+    return (static_cast<float>(w >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
+}
+
+__device__ __forceinline__ double u01_52(uint32_t hi, uint32_t lo) {
+    const uint64_t m = (static_cast<uint64_t>(hi) << 20) | static_cast<uint64_t>(lo >> 12);
+    return (static_cast<double>(m) + 0.5) * 2.220446049250313080847263336181640625e-16;  // 2^-52
+}
+
+__host__ __device__ __forceinline__ uint32_t key_lo(uint64_t seed) {
+    return static_cast<uint32_t>(seed & 0xFFFFFFFFull);
+}
+__host__ __device__ __forceinline__ uint32_t key_hi(uint64_t seed) {
+    return static_cast<uint32_t>(seed >> 32);
+}
+
+// ---------------------------------------------------------------- lattice
+// Sublattice index h = floor(i/2) + (L/2)(j + L k).  Neighbours of (h, parity p)
+// in the other sublattice, order +x, -x, +y, -y, +z, -z.
+struct Nbr {
+    int n[6];
+};
+
+template <int LT>
+__device__ __forceinline__ Nbr neighbours(int h, int p, int Lrt) {
+    const int L = LT > 0 ? LT : Lrt;
+    const int HL = L / 2;
+    const int ih = h % HL;
+    const int row = h / HL;  // j + L k
+    const int j = row % L;
+    const int k = row / L;
+    const int o = (p + j + k) & 1;  // i = 2 ih + o
+    int ixp = ih + o;
+    if (ixp == HL) ixp = 0;
+    int ixm = ih - 1 + o;
+    if (ixm < 0) ixm = HL - 1;
+    const int jp = (j == L - 1) ? 0 : j + 1;
+    const int jm = (j == 0) ? L - 1 : j - 1;
+    const int kp = (k == L - 1) ? 0 : k + 1;
+    const int km = (k == 0) ? L - 1 : k - 1;
+    Nbr r;
+    r.n[0] = row * HL + ixp;
+    r.n[1] = row * HL + ixm;
+    r.n[2] = (jp + L * k) * HL + ih;
+    r.n[3] = (jm + L * k) * HL + ih;
+    r.n[4] = (j + L * kp) * HL + ih;
+    r.n[5] = (j + L * km) * HL + ih;
+    return r;
+}
+
+// ---------------------------------------------------------------- math wrappers
+__device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ void d_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void d_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// ---------------------------------------------------------------- single-site updates
+// Heat-bath (paper Sec. III.C).  With R = beta |S| the component c of the new
+// spin along n = S/|S| has density ~ exp(R c) on [-1, 1]; inverting its
+// distribution function gives 1 - c = -log1p((1 - r1) expm1(-2R)) / R, which
+// equals the paper's ln(z + (1/z - z) r1)/R, z = exp(-R), without overflow or
+// cancellation.  R == 0 (beta = 0 or S = 0): c uniform, 1 - c = 2 (1 - r1).
+// The orthogonal part sqrt(1 - c^2) (sin phi e1 + cos phi e2), phi = 2 pi r2,
+// uses the branch-free frame of Duff et al. (JCGT 2017), sign +1 iff n_z >= 0.
+//
+// (w, c, sin theta) are always evaluated in binary64, also for binary32 spins:
+// for large R and small r1 the argument of log1p approaches -1 and binary32
+// would lose the small r1 to the rounding of 1 - r1 (errors ~1e-8/(r1 R)).
+__device__ __forceinline__ void heatbath_angles(double R, double r1, double& c, double& st) {
+    double w;
+    if (R >= 1e-300) {
+        w = -log1p((1.0 - r1) * expm1(-2.0 * R)) / R;
+    } else {
+        w = 2.0 * (1.0 - r1);
+    }
+    c = 1.0 - w;
+    st = sqrt(w * (2.0 - w));
+}
+
+template <typename T>
+__device__ __forceinline__ void heatbath(T Sx, T Sy, T Sz, T beta, T r1, T r2, T& ox, T& oy,
+                                         T& oz) {
+    const T ss = Sx * Sx + Sy * Sy + Sz * Sz;
+    T nx = T(0), ny = T(0), nz = T(1), nrm = T(0);
+    if (ss > T(0)) {
+        const T inv = d_rsqrt(ss);
+        nx = Sx * inv;
+        ny = Sy * inv;
+        nz = Sz * inv;
+        nrm = ss * inv;
+    }
+    double cd, std_;
+    heatbath_angles(static_cast<double>(beta) * static_cast<double>(nrm), static_cast<double>(r1), cd, std_);
+    const T c = static_cast<T>(cd);
+    const T st = static_cast<T>(std_);
+    const T sgn = nz >= T(0) ? T(1) : T(-1);
+    const T a = T(-1) / (sgn + nz);
+    const T b = nx * ny * a;
+    const T e1x = T(1) + sgn * nx * nx * a, e1y = sgn * b, e1z = -sgn * nx;
+    const T e2x = b, e2y = sgn + ny * ny * a, e2z = -ny;
+    T sp, cp;
+    d_sincospi(T(2) * r2, &sp, &cp);
+    ox = c * nx + st * (sp * e1x + cp * e2x);
+    oy = c * ny + st * (sp * e1y + cp * e2y);
+    oz = c * nz + st * (sp * e1z + cp * e2z);
+}
+
+// Overrelaxation (paper Sec. III.C): reflection about S; identity if S = 0.
+template <typename T>
+__device__ __forceinline__ void overrelax(T sx, T sy, T sz, T Sx, T Sy, T Sz, T& ox, T& oy,
+                                          T& oz) {
+    const T ss = Sx * Sx + Sy * Sy + Sz * Sz;
+    if (ss > T(0)) {
+        const T f = T(2) * (sx * Sx + sy * Sy + sz * Sz) / ss;
+        ox = f * Sx - sx;
+        oy = f * Sy - sy;
+        oz = f * Sz - sz;
+    } else {
+        ox = sx;
+        oy = sy;
+        oz = sz;
+    }
+}
+
+template <typename T>
+struct NormTol;
+template <>
+struct NormTol<float> {
+    static constexpr double value = 1e-4;
+};
+template <>
+struct NormTol<double> {
+    static constexpr double value = 1e-10;
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum: fixed butterfly inside each wave, then wave partials
+// added in wave order by thread 0.  `red` holds >= NT/64 doubles of LDS.  The
+// result is valid in thread 0 only.  Contains __syncthreads().
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < (NT + 63) / 64; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- ensemble helpers
+// Labels read from device memory index arrays: an out-of-range value latches
+// the guard (bit 4) and is clamped, so it can never address outside a chain.
+__device__ __forceinline__ int label(int v, int R, int* guard) {
+    if (v < 0 || v >= R) {
+        atomicOr(guard, 4);
+        v = v < 0 ? 0 : R - 1;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t heatbath_c3(int hs) {
+    return (kTagHeatbath << 24) | ((static_cast<uint32_t>(hs) & 0xFFu) << 16);
+}
+
+// Scratch layout (bytes, each region aligned to 256):
+//   candidate spins [slots][3][2][N/2] T | candidate energy [slots] double |
+//   accept flags [slots] int32 | partial sums [slots][max_tiles] double |
+//   work accumulators [slots] double
+struct ScratchLayout {
+    size_t cand, cand_energy, flags, partial, wacc, total;
+    int max_tiles;
+};
+
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+__host__ __device__ inline ScratchLayout scratch_layout(const hsg_ensemble& e) {
+    ScratchLayout s;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    const size_t slots = static_cast<size_t>(e.n_samples) * e.n_chains * e.n_temps;
+    const size_t tsz = e.precision == HSG_FP64 ? 8 : 4;
+    s.max_tiles = static_cast<int>((N / 4 + 63) / 64);
+    if (s.max_tiles < 1) s.max_tiles = 1;
+    size_t off = 0;
+    s.cand = off;
+    off += align256(slots * 3 * N * tsz);
+    s.cand_energy = off;
+    off += align256(slots * 8);
+    s.flags = off;
+    off += align256(slots * 4);
+    s.partial = off;
+    off += align256(slots * static_cast<size_t>(s.max_tiles) * 8);
+    s.wacc = off;
+    off += align256(slots * 8);
+    s.total = off;
+    return s;
+}
+
+}  // namespace hsg

@@ -1,0 +1,42 @@
+// Internal launcher interface between the C ABI (abi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/hsgpt.h"
+
+namespace hsg {
+
+// Largest dynamic LDS a workgroup may use on this device (bytes).
+size_t max_block_lds();
+
+// LDS-resident path: true if one replica of `e` fits in a workgroup's LDS and
+// an instantiation for e.L exists.
+bool resident_supported(const hsg_ensemble& e);
+// Regular sweeps (anneal = 0) or the annealing legs of one parity (anneal = 1).
+hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
+                           int parity, int block_threads, hipStream_t st);
+
+// Streaming path: one launch per half-sweep, any even L.
+hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
+                                int block_threads, int replicas_per_block, hipStream_t st);
+hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int n_or,
+                                int block_threads, hipStream_t st);
+
+// Initialisation, energy, exchange, measurement.
+hipError_t launch_init_couplings(const hsg_ensemble& e, hipStream_t st);
+hipError_t launch_init_spins(const hsg_ensemble& e, int cold, hipStream_t st);
+hipError_t launch_energy(const hsg_ensemble& e, double* out, hipStream_t st);
+hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st);
+hipError_t launch_anneal_decide(const hsg_ensemble& e, int parity, hipStream_t st);
+hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st);
+
+// MLP
+hipError_t launch_mlp_forward(const float* p, int I, int H, int O, const float* x, int B,
+                              float* acts, float* y, hipStream_t st);
+hipError_t launch_mlp_backward(const float* p, int I, int H, int O, const float* x, int B,
+                               float* acts, const float* dy, float* dp, hipStream_t st);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr,
+                           float b1, float b2, float eps, int t, hipStream_t st);
+
+}  // namespace hsg

@@ -1,0 +1,354 @@
+// Streaming sweep kernels: one launch per half-sweep, for lattices whose
+// replica does not fit in one workgroup's LDS (L = 24, 32, ...).
+//
+// Grid x = tiles of NT site pairs (h, h + N/4) of the updated sublattice,
+// grid y = groups of RB replicas of one sample.  A thread loads its sites'
+// couplings once and reuses them for the RB replicas; neighbour spins of the
+// other sublattice come through L1/L2 (each is read by six sites).  The energy
+// of the last half-sweep of a sweep is reduced per tile into scratch and
+// summed over tiles in a fixed order by a finalize kernel (deterministic).
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace hsg {
+
+struct StreamArgs {
+    int hb[2], par[2], hs[2];  // per leg (regular sweeps use index 0)
+    int step;                  // sweep index within the call / annealing step k
+    int want;                  // 1: last half-sweep of a sweep, reduce energy
+    int anneal, parity;        // annealing legs of pairs with i mod 2 == parity
+    int n_tiles;
+};
+
+struct LegInfo {
+    int slot, leg, ipair, K, ch;
+};
+
+__device__ __forceinline__ LegInfo leg_of_block(const hsg_ensemble& e, int b, int parity) {
+    const int R = e.n_temps;
+    const int npp = (R - parity) / 2;
+    LegInfo li;
+    li.leg = b & 1;
+    const int rest = b >> 1;
+    li.ch = rest / npp;
+    li.ipair = parity + 2 * (rest % npp);
+    li.slot = li.ch * R + label(e.slot_of_temp[li.ch * R + li.ipair + li.leg], R, e.guard);
+    int K = e.anneal_K[li.ipair];
+    if (K < 0) K = 0;
+    if (K > e.anneal_K_max) K = e.anneal_K_max;
+    li.K = K;
+    return li;
+}
+
+__device__ __forceinline__ double proto(const hsg_ensemble& e, int ipair, int K, int k) {
+    const double a = e.betas[ipair], b = e.betas[ipair + 1];
+    if (k <= 0) return a;
+    if (k >= K + 1) return b;
+    if (e.anneal_lambda) return e.anneal_lambda[static_cast<size_t>(ipair) * e.anneal_K_max + (k - 1)];
+    return a + static_cast<double>(k) * (b - a) / static_cast<double>(K + 1);
+}
+
+template <typename T, int LT, int NT, int RB>
+__global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a) {
+    const int L = LT > 0 ? LT : e.L;
+    const int N = L * L * L, NH = N / 2, NQ = N / 4;
+    __shared__ double red[(NT + 63) / 64];
+    const int C = e.n_chains, R = e.n_temps;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const int tile = blockIdx.x;
+    const int q = tile * NT + static_cast<int>(threadIdx.x);
+    const bool active = q < NQ;
+
+    int slot0, leg = 0, K = 0, ipair = 0;
+    if (!a.anneal) {
+        slot0 = blockIdx.y * RB;
+    } else {
+        const LegInfo li = leg_of_block(e, blockIdx.y, a.parity);
+        if (a.step >= li.K) return;  // uniform over the block
+        slot0 = li.slot;
+        leg = li.leg;
+        K = li.K;
+        ipair = li.ipair;
+    }
+    const int hb = a.hb[leg], P = a.par[leg], hs = a.hs[leg];
+    const int smp = slot0 / (C * R);
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    T* base = a.anneal ? reinterpret_cast<T*>(scr + sl.cand) : static_cast<T*>(e.spins);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const uint32_t c3 = heatbath_c3(hs);
+
+    int nb[2][6];
+    T jr[2][6];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int h = (active ? q : 0) + half * NQ;
+        const Nbr n = neighbours<LT>(h, P, L);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) nb[half][d] = n.n[d];
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            jr[half][2 * mu] = J[(mu * 2 + P) * NH + h];
+            jr[half][2 * mu + 1] = J[(mu * 2 + (1 - P)) * NH + n.n[2 * mu + 1]];
+        }
+    }
+
+    for (int rb = 0; rb < RB; ++rb) {
+        const int slot = slot0 + rb;
+        if (!a.anneal && slot >= (slot0 / (C * R) + 1) * (C * R)) break;  // uniform
+        double beta_d;
+        if (a.anneal) {
+            const int kk = a.step;  // sweep at protocol point k+1 (up) / K-k (down)
+            beta_d = leg == 0 ? proto(e, ipair, K, kk + 1) : proto(e, ipair, K, K - kk);
+        } else {
+            beta_d = e.betas[label(e.temp_of_slot[slot], R, e.guard)];
+        }
+        const T beta = static_cast<T>(beta_d);
+        const uint32_t g = e.slot_base + static_cast<uint32_t>(slot);
+        const uint32_t tsw = e.sweep_ctr[slot] + static_cast<uint32_t>(a.step);
+        T* sp = base + static_cast<size_t>(slot) * 3 * N;
+        const T* __restrict__ o0 = sp + (0 * 2 + (1 - P)) * NH;
+        const T* __restrict__ o1 = sp + (1 * 2 + (1 - P)) * NH;
+        const T* __restrict__ o2 = sp + (2 * 2 + (1 - P)) * NH;
+        T* w0 = sp + (0 * 2 + P) * NH;
+        T* w1 = sp + (1 * 2 + P) * NH;
+        T* w2 = sp + (2 * 2 + P) * NH;
+        double acc = 0.0;
+        bool bad = false;
+        if (active) {
+            Words wq{0, 0, 0, 0};
+            if (sizeof(T) == 4 && hb) wq = philox(static_cast<uint32_t>(q), tsw, g, c3, k0, k1);
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int h = q + half * NQ;
+                T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const int idx = nb[half][d];
+                    Sx = fma(jr[half][d], o0[idx], Sx);
+                    Sy = fma(jr[half][d], o1[idx], Sy);
+                    Sz = fma(jr[half][d], o2[idx], Sz);
+                }
+                T ox, oy, oz;
+                if (hb) {
+                    T r1, r2;
+                    if (sizeof(T) == 4) {
+                        r1 = static_cast<T>(u01_23(half ? wq.w2 : wq.w0));
+                        r2 = static_cast<T>(u01_23(half ? wq.w3 : wq.w1));
+                    } else {
+                        const Words wd = philox(static_cast<uint32_t>(h), tsw, g, c3, k0, k1);
+                        r1 = static_cast<T>(u01_52(wd.w0, wd.w1));
+                        r2 = static_cast<T>(u01_52(wd.w2, wd.w3));
+                    }
+                    heatbath<T>(Sx, Sy, Sz, beta, r1, r2, ox, oy, oz);
+                } else {
+                    overrelax<T>(w0[h], w1[h], w2[h], Sx, Sy, Sz, ox, oy, oz);
+                }
+                w0[h] = ox;
+                w1[h] = oy;
+                w2[h] = oz;
+                if (a.want) {
+                    const double dx = ox, dy = oy, dz = oz;
+                    acc += dx * static_cast<double>(Sx) + dy * static_cast<double>(Sy) +
+                           dz * static_cast<double>(Sz);
+                    const double n2 = dx * dx + dy * dy + dz * dz;
+                    if (!(fabs(n2 - 1.0) <= NormTol<T>::value)) bad = true;
+                }
+            }
+        }
+        if (a.want) {
+            if (bad) atomicOr(e.guard, 1);
+            const double tot = block_sum<NT>(acc, red);
+            if (threadIdx.x == 0)
+                reinterpret_cast<double*>(scr + sl.partial)[static_cast<size_t>(slot) * sl.max_tiles + tile] = -tot;
+        }
+    }
+}
+
+// Sum the per-tile energies of every slot in tile order.  Regular: energy[] and
+// (on the last sweep of the call) sweep_ctr += n_sweeps.  Annealing: the
+// candidate energy of each active leg.
+__global__ void k_stream_finalize(hsg_ensemble e, int n_tiles, int anneal, int parity, int step,
+                                  int ctr_add) {
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const double* part = reinterpret_cast<const double*>(scr + sl.partial);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int slot;
+    if (!anneal) {
+        const int n_slots = e.n_samples * e.n_chains * e.n_temps;
+        if (b >= n_slots) return;
+        slot = b;
+    } else {
+        const int n_legs = e.n_samples * e.n_chains * ((e.n_temps - parity) / 2) * 2;
+        if (b >= n_legs) return;
+        const LegInfo li = leg_of_block(e, b, parity);
+        if (step >= li.K) return;
+        slot = li.slot;
+    }
+    double H = 0.0;
+    for (int t = 0; t < n_tiles; ++t) H += part[static_cast<size_t>(slot) * sl.max_tiles + t];
+    if (!isfinite(H)) atomicOr(e.guard, 1);
+    if (!anneal) {
+        e.energy[slot] = H;
+        e.sweep_ctr[slot] += static_cast<uint32_t>(ctr_add);
+    } else {
+        reinterpret_cast<double*>(scr + sl.cand_energy)[slot] = H;
+    }
+}
+
+// Annealing bookkeeping, one thread per leg.
+//  phase 0: copy nothing, W = 0, candidate energy = current energy
+//  phase 1 (step k): W += (next - cur) * H(candidate) for legs with k <= K
+//  phase 2: work[] = W, sweep_ctr += K
+__global__ void k_stream_anneal_book(hsg_ensemble e, int parity, int phase, int step) {
+    const int n_legs = e.n_samples * e.n_chains * ((e.n_temps - parity) / 2) * 2;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_legs) return;
+    const LegInfo li = leg_of_block(e, b, parity);
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    double* wacc = reinterpret_cast<double*>(scr + sl.wacc);
+    double* cen = reinterpret_cast<double*>(scr + sl.cand_energy);
+    if (phase == 0) {
+        wacc[li.slot] = 0.0;
+        cen[li.slot] = e.energy[li.slot];
+        const int raw = e.anneal_K[li.ipair];
+        if (raw < 0 || raw > e.anneal_K_max) atomicOr(e.guard, 2);
+    } else if (phase == 1) {
+        if (step > li.K) return;
+        const double cur = li.leg == 0 ? proto(e, li.ipair, li.K, step) : proto(e, li.ipair, li.K, li.K + 1 - step);
+        const double nxt = li.leg == 0 ? proto(e, li.ipair, li.K, step + 1) : proto(e, li.ipair, li.K, li.K - step);
+        wacc[li.slot] += (nxt - cur) * cen[li.slot];
+    } else {
+        e.work[(static_cast<size_t>(li.ch) * (e.n_temps - 1) + li.ipair) * 2 + li.leg] = wacc[li.slot];
+        e.sweep_ctr[li.slot] += static_cast<uint32_t>(li.K);
+    }
+}
+
+// Copy each leg's configuration into the candidate buffer (legs with K > 0).
+template <typename T>
+__global__ void k_stream_anneal_copy(hsg_ensemble e, int parity) {
+    const LegInfo li = leg_of_block(e, blockIdx.x, parity);
+    if (li.K == 0) return;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    const ScratchLayout sl = scratch_layout(e);
+    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) + li.slot * 3 * N);
+    uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<T*>(static_cast<unsigned char*>(e.scratch) + sl.cand) + li.slot * 3 * N);
+    const size_t nv = 3 * N * sizeof(T) / 16;
+    for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+}
+
+// ---------------------------------------------------------------- dispatch
+template <typename T, int LT, int NT, int RB>
+static hipError_t launch_half(const hsg_ensemble& e, const StreamArgs& a, int gy, hipStream_t st) {
+    hipLaunchKernelGGL((k_stream_half<T, LT, NT, RB>), dim3(a.n_tiles, gy), dim3(NT), 0, st, e, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int RB>
+static hipError_t half_L(const hsg_ensemble& e, const StreamArgs& a, int gy, hipStream_t st) {
+    switch (e.L) {
+    case 24: return launch_half<T, 24, NT, RB>(e, a, gy, st);
+    case 32: return launch_half<T, 32, NT, RB>(e, a, gy, st);
+    default: return launch_half<T, 0, NT, RB>(e, a, gy, st);
+    }
+}
+
+template <typename T>
+static hipError_t half_any(const hsg_ensemble& e, const StreamArgs& a, int gy, int nt, int rb,
+                           hipStream_t st) {
+    if (nt == 256 && rb == 1) return half_L<T, 256, 1>(e, a, gy, st);
+    if (nt == 256 && rb == 2) return half_L<T, 256, 2>(e, a, gy, st);
+    if (nt == 256 && rb == 4) return half_L<T, 256, 4>(e, a, gy, st);
+    if (nt == 128 && rb == 1) return half_L<T, 128, 1>(e, a, gy, st);
+    if (nt == 128 && rb == 4) return half_L<T, 128, 4>(e, a, gy, st);
+    if (nt == 512 && rb == 1) return half_L<T, 512, 1>(e, a, gy, st);
+    if (nt == 64 && rb == 1) return half_L<T, 64, 1>(e, a, gy, st);
+    return hipErrorInvalidValue;
+}
+
+static hipError_t half_prec(const hsg_ensemble& e, const StreamArgs& a, int gy, int nt, int rb,
+                            hipStream_t st) {
+    if (e.precision == HSG_FP64) return half_any<double>(e, a, gy, nt, rb, st);
+    return half_any<float>(e, a, gy, nt, rb, st);
+}
+
+hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
+                                int block_threads, int replicas_per_block, hipStream_t st) {
+    const int nt = block_threads > 0 ? block_threads : 256;
+    int rb = replicas_per_block > 0 ? replicas_per_block : 1;
+    const int CR = e.n_chains * e.n_temps;
+    if (CR % rb != 0) rb = 1;
+    const int NQ = e.L * e.L * e.L / 4;
+    StreamArgs a{};
+    a.n_tiles = (NQ + nt - 1) / nt;
+    const int n_slots = e.n_samples * CR;
+    const int gy = n_slots / rb;
+    const int nhalf = 2 * (n_hb + n_or);
+    for (int k = 0; k < n_sweeps; ++k) {
+        for (int pos = 0; pos < nhalf; ++pos) {
+            a.hb[0] = a.hb[1] = pos < 2 * n_hb;
+            a.par[0] = a.par[1] = pos & 1;
+            a.hs[0] = a.hs[1] = pos;
+            a.step = k;
+            a.want = (pos == nhalf - 1);
+            hipError_t err = half_prec(e, a, gy, nt, rb, st);
+            if (err != hipSuccess) return err;
+        }
+        const int last = (k == n_sweeps - 1);
+        hipLaunchKernelGGL(k_stream_finalize, dim3((n_slots + 255) / 256), dim3(256), 0, st, e,
+                           a.n_tiles, 0, 0, k, last ? n_sweeps : 0);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int n_or,
+                                int block_threads, hipStream_t st) {
+    const int nt = block_threads > 0 ? block_threads : 256;
+    const int R = e.n_temps;
+    const int n_legs = e.n_samples * e.n_chains * ((R - parity) / 2) * 2;
+    if (n_legs == 0) return hipSuccess;
+    const int NQ = e.L * e.L * e.L / 4;
+    const int nhalf = 2 * (n_hb + n_or);
+    const int lb = (n_legs + 255) / 256;
+    hipLaunchKernelGGL(k_stream_anneal_book, dim3(lb), dim3(256), 0, st, e, parity, 0, 0);
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_stream_anneal_copy<double>, dim3(n_legs), dim3(256), 0, st, e, parity);
+    else
+        hipLaunchKernelGGL(k_stream_anneal_copy<float>, dim3(n_legs), dim3(256), 0, st, e, parity);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int Kmax = e.anneal_K_max;
+    StreamArgs a{};
+    a.anneal = 1;
+    a.parity = parity;
+    a.n_tiles = (NQ + nt - 1) / nt;
+    for (int k = 0; k <= Kmax; ++k) {
+        hipLaunchKernelGGL(k_stream_anneal_book, dim3(lb), dim3(256), 0, st, e, parity, 1, k);
+        if (k == Kmax) break;
+        for (int s = 0; s < nhalf; ++s) {
+            const int up = s, dn = nhalf - 1 - s;  // forward / adjoint positions
+            a.hb[0] = up < 2 * n_hb;
+            a.par[0] = up & 1;
+            a.hs[0] = up;
+            a.hb[1] = dn < 2 * n_hb;
+            a.par[1] = dn & 1;
+            a.hs[1] = dn;
+            a.step = k;
+            a.want = (s == nhalf - 1);
+            err = half_prec(e, a, n_legs, nt, 1, st);
+            if (err != hipSuccess) return err;
+        }
+        hipLaunchKernelGGL(k_stream_finalize, dim3(lb), dim3(256), 0, st, e, a.n_tiles, 1, parity,
+                           k, 0);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_stream_anneal_book, dim3(lb), dim3(256), 0, st, e, parity, 2, 0);
+    return hipGetLastError();
+}
+
+}  // namespace hsg

@@ -1,0 +1,260 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs and the same Philox streams.
+
+Bars (tests/gpu_pair.py): after one lattice sweep of one kind (the paper's unit
+of a sweep) FP32 spins <= 1e-5 and FP64 <= 1e-12 per component, with only
+ill-conditioned sites of the oracle's own trajectory admitted beyond it;
+composite steps (1 heat-bath + n overrelaxation lattice sweeps) on quantiles,
+because overrelaxation amplifies last-bit differences chaotically; integer state
+(labels, counters, statistics, round trips) bit-exact; energies within the
+rigorous bound implied by the spin differences.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from gpu_pair import LATTICE_BAR, compare_states, make_pair, snapshot
+from oracle import hsgref
+
+import paper_1006_4247_amd as hsg
+
+pytestmark = pytest.mark.gpu
+SEED = 0x100642470001
+
+
+def _betas(R, lo=0.5, hi=4.0):
+    return hsgref.geometric_betas(lo, hi, R)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L", [2, 4, 8, 16])
+def test_init_couplings_and_spins(L, prec):
+    S, C, R = 3, 2, 3
+    ref = hsgref.RefEnsemble(L, S, C, _betas(R), SEED, prec=prec, sample_base=5, slot_base=40)
+    ref.init_couplings()
+    ref.init_spins()
+    g = hsg.Ensemble(L, S, C, _betas(R), SEED, precision=prec, sample_base=5, slot_base=40)
+    g.init_couplings()
+    g.init_spins()
+    torch.cuda.synchronize()
+    J = g.couplings_natural()
+    s = g.spins_natural()
+    if prec == "fp64":
+        assert np.max(np.abs(J - ref.J)) <= 1e-14 * max(1.0, np.abs(ref.J).max())
+        assert np.max(np.abs(s - ref.spins)) <= 1e-15
+    else:
+        # the same FP64 value rounded to binary32: equal, or one ulp apart on a rounding tie
+        ulp = np.spacing(np.abs(ref.J).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(J - ref.J) <= ulp)
+        assert np.max(np.abs(s - ref.spins)) <= 6e-8
+    st = g.host_state()
+    assert np.array_equal(st["temp_of_slot"], ref.temp_of_slot)
+    assert np.array_equal(st["rt_state"], ref.rt_state)
+    e_tol = 1e-12 * ref.N if prec == "fp64" else 1e-5 * ref.N
+    assert np.max(np.abs(st["energy"] - ref.energy)) <= e_tol
+
+
+def _set_counters(gpu, ref, base):
+    """Start both sides at a nonzero per-slot sweep counter (exercises the Philox counter)."""
+    ctr = (base + np.arange(ref.sweep_ctr.size, dtype=np.uint32) * 7).reshape(ref.sweep_ctr.shape)
+    ref.sweep_ctr[...] = ctr
+    gpu.sweep_ctr.copy_(torch.from_numpy(ctr.view(np.int32)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 12, 14, 16])
+@pytest.mark.parametrize("kind", ["hb", "or", "hb+3or"])
+def test_sweep_parity_resident(L, prec, kind):
+    S, C, R = 2, 2, 3
+    n_hb, n_or = {"hb": (1, 0), "or": (0, 1), "hb+3or": (1, 3)}[kind]
+    gpu, ref = make_pair(L, S, C, _betas(R, 1.0, 8.0), SEED + L, prec=prec)
+    _set_counters(gpu, ref, 1000 + L)
+    before = snapshot(ref)
+    gpu.sweep(1, n_hb, n_or, tuning={"path": 1})
+    ref.sweep(1, n_hb, n_or)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, prec, mode="composite" if kind == "hb+3or" else "lattice",
+                   before=before, n_hb=n_hb, n_or=n_or, what="L=%d %s %s" % (L, prec, kind))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("path", [1, 2])
+def test_multi_sweep_launch_equals_repeated_launches(prec, path):
+    """n sweeps in one launch are bitwise the n single-sweep launches (counters t0 + k).
+    (Oracle parity is checked per sweep: the dynamics amplifies last-bit differences
+    chaotically over several sweeps, so multi-sweep trajectories are compared GPU to GPU.)"""
+    L, S, C, R = 8, 1, 2, 3
+    a, _ = make_pair(L, S, C, _betas(R), SEED + 50, prec=prec)
+    b, _ = make_pair(L, S, C, _betas(R), SEED + 50, prec=prec)
+    tune = {"path": path, "block_threads": 128 if path == 1 else 64}
+    a.sweep(3, 1, 3, tuning=tune)
+    for _ in range(3):
+        b.sweep(1, 1, 3, tuning=tune)
+    torch.cuda.synchronize()
+    sa, sb = a.host_state(), b.host_state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L,nt,rb", [(4, 64, 1), (8, 128, 4), (10, 64, 1), (16, 256, 2),
+                                     (24, 256, 1), (24, 256, 2), (32, 256, 4)])
+@pytest.mark.parametrize("kind", ["hb", "or", "hb+3or"])
+def test_sweep_parity_streaming(L, nt, rb, prec, kind):
+    S, C, R = 1, 2, 2
+    n_hb, n_or = {"hb": (1, 0), "or": (0, 1), "hb+3or": (1, 3)}[kind]
+    gpu, ref = make_pair(L, S, C, _betas(R, 1.0, 8.0), SEED + 100 + L, prec=prec)
+    _set_counters(gpu, ref, 5)
+    before = snapshot(ref)
+    gpu.sweep(1, n_hb, n_or, tuning={"path": 2, "block_threads": nt, "replicas_per_block": rb})
+    ref.sweep(1, n_hb, n_or)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, prec, mode="composite" if kind == "hb+3or" else "lattice",
+                   before=before, n_hb=n_hb, n_or=n_or,
+                   what="L=%d %s streaming %s" % (L, prec, kind))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_hb,n_or", [(2, 0), (2, 1), (1, 5)])
+def test_sweep_compositions(n_hb, n_or, prec):
+    L, S, C, R = 6, 1, 2, 3
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 7, prec=prec)
+    before = snapshot(ref)
+    gpu.sweep(1, n_hb, n_or)
+    ref.sweep(1, n_hb, n_or)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, prec, mode="lattice" if n_or == 0 else "composite", before=before,
+                   n_hb=n_hb, n_or=n_or, what="composition %d+%d" % (n_hb, n_or))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L", [2, 4, 8, 12])
+def test_energy_standalone(L, prec):
+    S, C, R = 2, 2, 2
+    N = L ** 3
+    J = inputs.gaussian_couplings(L, S, 3, np.float32 if prec == "fp32" else np.float64)
+    s = inputs.unit_spins((S, C, R), N, 4, np.float32 if prec == "fp32" else np.float64)
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED, prec=prec, J=J, spins=s)
+    H = gpu.energy_from_scratch().cpu().numpy()
+    assert np.max(np.abs(H - ref.energy)) <= 1e-12 * N
+
+
+@pytest.mark.parametrize("pairing", [0, 1, 2])
+def test_swap_parity(pairing):
+    S, C, R = 3, 4, 9
+    gpu, ref = make_pair(2, S, C, _betas(R, 0.3, 5.0), SEED, prec="fp64")
+    for rnd in range(40):
+        en = inputs.synthetic_energies(S, C, R, 1000 + rnd, scale=2.0)
+        ref.energy[...] = en
+        gpu.energy.copy_(torch.from_numpy(en))
+        p = pairing if pairing else (rnd % 3)
+        ref.swap(p)
+        gpu.swap(p)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, "fp64", check_energy=False, what="swap")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_measure_parity(prec):
+    L, S, C, R = 4, 2, 2, 3
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 3, prec=prec)
+    perm = np.array([2, 0, 1], dtype=np.int32)
+    inv = np.argsort(perm).astype(np.int32)
+    ref.temp_of_slot[0, 1] = perm
+    ref.slot_of_temp[0, 1] = inv
+    gpu.temp_of_slot[0, 1] = torch.from_numpy(perm).to(gpu.device)
+    gpu.slot_of_temp[0, 1] = torch.from_numpy(inv).to(gpu.device)
+    Q, chi, e = gpu.measure()
+    rQ, rchi, re = ref.measure()
+    assert np.max(np.abs(Q.cpu().numpy() - rQ)) <= 1e-10
+    assert np.max(np.abs(chi.cpu().numpy() - rchi)) <= 1e-10
+    assert np.max(np.abs(e.cpu().numpy() - re)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,L", [("fp64", 4), ("fp32", 8), ("fp64", 24), ("fp32", 24)])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("legs", ["hb", "hb+3or"])
+def test_anneal_parity(prec, L, parity, legs):
+    """One annealed exchange from an oracle-given state with K = 1 and K = 0 pairs mixed.
+    Legs of one heat-bath lattice sweep meet the lattice-sweep bar; composite legs the
+    composite bars."""
+    S, C, R = 2, 2, 5
+    n_hb, n_or = (1, 0) if legs == "hb" else (1, 3)
+    K = np.array([1, 0, 1, 1], dtype=np.int32)
+    betas = _betas(R, 1.0, 1.5)
+    gpu, ref = make_pair(L, S, C, betas, SEED + 9 + parity, prec=prec, K_max=2)
+    _set_counters(gpu, ref, 77)
+    gpu.set_schedule(K)
+    gpu.anneal_swap(parity, n_hb, n_or)
+    w_ref = ref.anneal_swap(parity, K, n_hb=n_hb, n_or=n_or)
+    torch.cuda.synchronize()
+    w_gpu = gpu.work.cpu().numpy()
+    sel = np.zeros(R - 1, dtype=bool)
+    sel[parity::2] = True
+    dbeta = np.diff(betas)[None, None, :, None]
+    if legs == "hb":
+        # |dW| <= |dlambda| * (2 sqrt(3) max|ds| sum|J| + rounding)
+        wtol = 1e-9 if prec == "fp64" else (2 * np.sqrt(3) * LATTICE_BAR[prec] * np.abs(ref.J).sum() + 5e-6 * ref.N)
+    else:
+        wtol = 1e-9 if prec == "fp64" else 2e-3 * ref.N
+    dw = np.abs(w_gpu - w_ref)[..., sel, :]
+    assert np.all(dw <= wtol * dbeta[..., sel, :] + 1e-12), dw.max()
+    compare_states(gpu, ref, prec, mode="lattice" if legs == "hb" else "composite",
+                   check_energy=(legs == "hb"), n_hb=n_hb, n_or=n_or,
+                   what="anneal L=%d %s parity %d %s" % (L, prec, parity, legs))
+    assert ref.stats[..., 1].sum() > 0  # some exchanges were accepted
+    gpu.check()
+
+
+@pytest.mark.parametrize("L", [4, 24])
+def test_anneal_parity_longer_protocol_fp64(L):
+    """K = 3 in FP64 with an explicit protocol table: works and decisions agree."""
+    S, C, R = 1, 2, 4
+    K = np.array([3, 2, 3], dtype=np.int32)
+    betas = _betas(R, 0.5, 2.0)
+    lam = np.zeros((R - 1, 3))
+    for i in range(R - 1):
+        u = (np.arange(1, K[i] + 1) / (K[i] + 1)) ** 1.5
+        lam[i, :K[i]] = betas[i] + (betas[i + 1] - betas[i]) * u
+    gpu, ref = make_pair(L, S, C, betas, SEED + 31, prec="fp64", K_max=3)
+    gpu.set_schedule(K, lam)
+    gpu.anneal_swap(0, 1, 2)
+    w_ref = ref.anneal_swap(0, K, lam, n_hb=1, n_or=2)
+    torch.cuda.synchronize()
+    w_gpu = gpu.work.cpu().numpy()
+    assert np.max(np.abs(w_gpu[..., 0::2, :] - w_ref[..., 0::2, :])) <= 1e-7
+    st = gpu.host_state()
+    for k in ["temp_of_slot", "stats", "sweep_ctr", "swap_ctr", "rt_state"]:
+        assert np.array_equal(st[k], getattr(ref, k if k != "stats" else "stats")), k
+    assert np.max(np.abs(st["spins"] - ref.spins)) <= 1e-7
+
+
+def test_anneal_K0_equals_swap_on_gpu():
+    L, S, C, R = 4, 2, 2, 6
+    a, _ = make_pair(L, S, C, _betas(R), SEED + 11, prec="fp32", K_max=0)
+    b, _ = make_pair(L, S, C, _betas(R), SEED + 11, prec="fp32", K_max=0)
+    b.set_schedule(np.zeros(R - 1, dtype=np.int32))
+    for it in range(6):
+        a.sweep(1, 1, 3)
+        b.sweep(1, 1, 3)
+        a.swap(1 + it % 2)
+        b.anneal_swap(it % 2)
+    torch.cuda.synchronize()
+    sa, sb = a.host_state(), b.host_state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_guard_trips_on_nan_and_reports():
+    """A non-finite coupling makes the fused energy non-finite: the guard latches and
+    hsg_check reports HSG_ERR_NUMERIC.  (A non-finite spin alone is overwritten by the
+    next heat-bath, which treats a non-finite field like a zero field.)"""
+    L, S, C, R = 4, 1, 1, 2
+    gpu, _ = make_pair(L, S, C, _betas(R), SEED, prec="fp32")
+    gpu.check()
+    gpu.couplings[0, 1, 1, 3] = float("nan")
+    gpu.sweep(1, 1, 3)
+    with pytest.raises(hsg.HsgError) as ei:
+        gpu.check()
+    assert ei.value.code == 3
