@@ -84,6 +84,25 @@ def cpu_baseline(w, budget_s):
                       "measurement), %.1f s" % (S, w["S"], w["C"], w["R"], w["L"], n, dt)}
 
 
+def copy_probe(torch, mib, reps=10):
+    """Plain device-to-device copy of `mib` MiB: prints the achieved bandwidth (read + write)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        b.copy_(a)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    print(json.dumps({"copy_probe_bytes_per_launch": 2 * n * 4, "read_bytes": n * 4,
+                      "write_bytes": n * 4, "avg_ms": float(ms.mean()),
+                      "GBs": 2 * n * 4 / (ms.mean() / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +111,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM bandwidth probe and the "
+                         "calibration of rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every (sample, chain) is an independent Markov chain, "
@@ -102,6 +124,9 @@ def main():
     import torch
     import paper_1006_4247_amd as hsg
 
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -149,7 +174,7 @@ def main():
     hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
     roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "k_resident (one sweep of every replica per launch)",
+                "kernel": "k_resident<float,16,512> (one sweep of every replica per launch)",
                 "avg_launch_ms": round(avg_launch_s * 1e3, 5),
                 "hbm_algorithmic_GBs": round(hbm_achieved, 1),
                 "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),

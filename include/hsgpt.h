@@ -111,7 +111,10 @@ typedef struct hsg_ensemble {
 
 /* Tuning knobs of the sweep kernels (0 = library default). */
 typedef struct hsg_tuning {
-    int32_t path;           /* 0 auto, 1 LDS-resident lattice, 2 streaming half-sweeps */
+    int32_t path;           /* 0 auto (3 if a replica fits in one workgroup's LDS, else 2);
+                               1 LDS-resident lattice on persistent double-buffered
+                               workgroups; 2 streaming half-sweeps; 3 LDS-resident lattice,
+                               one workgroup per replica */
     int32_t block_threads;  /* threads per workgroup */
     int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */
     int32_t reserved;

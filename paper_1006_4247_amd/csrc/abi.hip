@@ -91,11 +91,16 @@ hsg_status check_all(const hsg_ensemble* ens, int n_ens, unsigned need) {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-bool use_resident(const hsg_ensemble& e, const hsg_tuning* t) {
+// 1: LDS-resident, persistent double-buffered; 3: LDS-resident, one workgroup per
+// replica; 2: streaming half-sweeps; 0: 3 if a replica fits in LDS, else 2.
+int sweep_path(const hsg_ensemble& e, const hsg_tuning* t) {
     const int path = t ? t->path : 0;
-    if (path == 2) return false;
-    return hsg::resident_supported(e);
+    if (path != 0) return path;
+    if (hsg::resident_supported(e)) return 3;
+    return 2;
 }
+
+bool use_resident(const hsg_ensemble& e, const hsg_tuning* t) { return sweep_path(e, t) != 2; }
 
 }  // namespace
 
@@ -135,13 +140,15 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
     if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
         return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
                     n_sweeps, n_hb, n_or);
-    if (tuning && (tuning->path < 0 || tuning->path > 2 || tuning->block_threads < 0 ||
+    if (tuning && (tuning->path < 0 || tuning->path > 3 || tuning->block_threads < 0 ||
                    tuning->replicas_per_block < 0))
         return fail(HSG_ERR_INVALID, "bad tuning values");
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;
     for (int i = 0; i < n_ens; ++i) {
-        if (tuning && tuning->path == 1 && !hsg::resident_supported(ens[i]))
+        if (tuning && tuning->path == 1 && !hsg::persistent_supported(ens[i]))
+            return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the persistent LDS-resident path", i, ens[i].L);
+        if (tuning && tuning->path == 3 && !hsg::resident_supported(ens[i]))
             return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the LDS-resident path", i, ens[i].L);
         if (!use_resident(ens[i], tuning)) {
             s = check_one(ens[i], i, kScratch);
@@ -152,7 +159,10 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
     for (int i = 0; i < n_ens; ++i) {
         const int nt = tuning ? tuning->block_threads : 0;
         hipError_t err;
-        if (use_resident(ens[i], tuning)) {
+        const int path = sweep_path(ens[i], tuning);
+        if (path == 1) {
+            err = hsg::launch_resident(ens[i], n_sweeps, n_hb, n_or, 2, 0, nt, as_stream(stream));
+        } else if (path == 3) {
             err = hsg::launch_resident(ens[i], n_sweeps, n_hb, n_or, 0, 0, nt, as_stream(stream));
         } else {
             const int rb = tuning ? tuning->replicas_per_block : 0;
@@ -187,6 +197,8 @@ hsg_status hsg_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* strea
     if (pairing < 0 || pairing > 2) return fail(HSG_ERR_INVALID, "pairing must be 0, 1 or 2 (got %d)", pairing);
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i)
+        if (ens[i].n_temps > 256) return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: n_temps > 256", i);
     for (int i = 0; i < n_ens; ++i) {
         hipError_t err = hsg::launch_swap(ens[i], pairing, as_stream(stream));
         if (err != hipSuccess) return device(err, "swap");

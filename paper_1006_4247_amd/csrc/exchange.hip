@@ -146,11 +146,19 @@ __device__ __forceinline__ double swap_uniform(const hsg_ensemble& e, int i, uin
     return u01_52(w.w0, w.w1);
 }
 
-// Eq. (1): accept iff ln u < (beta_{i+1} - beta_i)(H_{i+1} - H_i).  One thread per chain.
-__global__ void k_swap(hsg_ensemble e, int pairing) {
-    const int n_chains = e.n_samples * e.n_chains;
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n_chains) return;
+// Eq. (1): accept iff ln u < (beta_{i+1} - beta_i)(H_{i+1} - H_i).  One wave per
+// chain: labels and energies are staged in LDS and every pair's uniform and its
+// logarithm are computed in parallel; one lane then takes the decisions in pair
+// order (each pair sees the labels the previous pair left), and the wave writes
+// labels, statistics and round-trip state back in parallel.
+constexpr int kSwapMaxR = 256;
+
+__global__ void __launch_bounds__(64) k_swap(hsg_ensemble e, int pairing) {
+    __shared__ int s_sot[kSwapMaxR], s_tos[kSwapMaxR];
+    __shared__ double s_en[kSwapMaxR], s_lu[kSwapMaxR], s_db[kSwapMaxR];
+    __shared__ unsigned char s_acc[kSwapMaxR];
+    const int ch = blockIdx.x;
+    const int lane = threadIdx.x;
     const int R = e.n_temps;
     int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
     int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
@@ -158,21 +166,53 @@ __global__ void k_swap(hsg_ensemble e, int pairing) {
     long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
     const uint32_t n = e.swap_ctr[ch];
     const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
-    for (int i = 0; i < R - 1; ++i) {
-        if (pairing == 1 && (i & 1)) continue;
-        if (pairing == 2 && !(i & 1)) continue;
-        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
-        const double delta = (e.betas[i + 1] - e.betas[i]) * (en[y] - en[x]);
-        const double u = swap_uniform(e, i, n, cg);
-        st[2 * i] += 1;
-        if (log(u) < delta) {
-            relabel(tos, sot, i, x, y);
-            st[2 * i + 1] += 1;
+    for (int r = lane; r < R; r += 64) {
+        s_sot[r] = label(sot[r], R, e.guard);
+        s_en[r] = en[r];
+    }
+    for (int i = lane; i < R - 1; i += 64) {
+        const bool sel = pairing == 0 || (pairing == 1 && !(i & 1)) || (pairing == 2 && (i & 1));
+        s_lu[i] = sel ? log(swap_uniform(e, i, n, cg)) : 0.0;
+        s_db[i] = e.betas[i + 1] - e.betas[i];
+        s_acc[i] = sel ? 2 : 0;  // 2 = attempted, 3 = accepted
+    }
+    __syncthreads();
+    if (lane == 0) {
+        for (int i = 0; i < R - 1; ++i) {
+            if (!s_acc[i]) continue;
+            const int x = s_sot[i], y = s_sot[i + 1];
+            if (s_lu[i] < s_db[i] * (s_en[y] - s_en[x])) {
+                s_sot[i] = y;
+                s_sot[i + 1] = x;
+                s_acc[i] = 3;
+            }
         }
     }
-    e.swap_ctr[ch] = n + 1u;
-    roundtrip_update(R, tos, e.rt_state + static_cast<size_t>(ch) * R,
-                     reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R);
+    __syncthreads();
+    for (int t = lane; t < R; t += 64) {
+        sot[t] = s_sot[t];
+        s_tos[s_sot[t]] = t;
+    }
+    for (int i = lane; i < R - 1; i += 64) {
+        if (s_acc[i]) {
+            st[2 * i] += 1;
+            if (s_acc[i] == 3) st[2 * i + 1] += 1;
+        }
+    }
+    __syncthreads();
+    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
+    for (int r = lane; r < R; r += 64) {
+        const int T = s_tos[r];
+        tos[r] = T;
+        if (T == 0) {
+            if (rs[r] == 2) rtt[r] += 1;
+            rs[r] = 1;
+        } else if (T == R - 1) {
+            if (rs[r] == 1) rs[r] = 2;
+        }
+    }
+    if (lane == 0) e.swap_ctr[ch] = n + 1u;
 }
 
 // Annealed exchange decision: accept iff ln u < -(W_up + W_dn); the annealed
@@ -309,7 +349,8 @@ hipError_t launch_energy(const hsg_ensemble& e, double* out, hipStream_t st) {
 
 hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st) {
     const int n_chains = e.n_samples * e.n_chains;
-    hipLaunchKernelGGL(k_swap, dim3(nblk(n_chains, 64)), dim3(64), 0, st, e, pairing);
+    if (e.n_temps > kSwapMaxR) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_swap, dim3(n_chains), dim3(64), 0, st, e, pairing);
     return hipGetLastError();
 }
 

@@ -32,10 +32,10 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+        const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -97,10 +97,6 @@ __device__ __forceinline__ Nbr neighbours(int h, int p, int Lrt) {
 }
 
 // ---------------------------------------------------------------- math wrappers
-__device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
-__device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
@@ -117,9 +113,37 @@ __device__ __forceinline__ void d_sincospi(double x, double* s, double* c) { sin
 // The orthogonal part sqrt(1 - c^2) (sin phi e1 + cos phi e2), phi = 2 pi r2,
 // uses the branch-free frame of Duff et al. (JCGT 2017), sign +1 iff n_z >= 0.
 //
-// (w, c, sin theta) are always evaluated in binary64, also for binary32 spins:
-// for large R and small r1 the argument of log1p approaches -1 and binary32
-// would lose the small r1 to the rounding of 1 - r1 (errors ~1e-8/(r1 R)).
+// The angles (c, sin theta) are evaluated so that they keep full relative
+// precision in every regime; in binary32 the single expression above would lose
+// the small r1 to the rounding of 1 - r1 when R is large (errors ~1e-8/(r1 R)).
+// With y = r1 + (1 - r1) exp(-2R) = exp(-R w):
+//   y >= 1/2: w = -log1p((1 - r1) expm1(-2R)) / R   (the form above)
+//   y <  1/2: w = -log(r1 + (1 - r1) exp(-2R)) / R  (sum of positive terms)
+// and, if c < 0, 1 + c = log1p(r1 expm1(2R)) / R directly, so that
+// sin theta = sqrt((1 - c)(1 + c)) has no cancellation near c = -1.
+__device__ __forceinline__ void heatbath_angles(float R, float r1, float& c, float& st) {
+    float w, v;
+    if (R >= 1e-30f) {
+        const float om = 1.0f - r1;
+        const float q = om * expm1f(-2.0f * R);  // y - 1, in (-1, 0]
+        const float ly = (q >= -0.5f) ? log1pf(q) : logf(fmaf(om, expf(-2.0f * R), r1));
+        w = -ly / R;
+        if (w > 1.0f && R < 40.0f) {
+            v = log1pf(r1 * expm1f(2.0f * R)) / R;
+            w = 2.0f - v;
+        } else {
+            v = 2.0f - w;
+        }
+    } else {
+        w = 2.0f * (1.0f - r1);
+        v = 2.0f * r1;
+    }
+    c = (w <= 1.0f) ? 1.0f - w : v - 1.0f;
+    st = sqrtf(w * v);
+}
+
+// Binary64: the single expression is accurate to ~1e-16/(r1 R), far inside
+// every tolerance, and matches the reference evaluation.
 __device__ __forceinline__ void heatbath_angles(double R, double r1, double& c, double& st) {
     double w;
     if (R >= 1e-300) {
@@ -143,10 +167,8 @@ __device__ __forceinline__ void heatbath(T Sx, T Sy, T Sz, T beta, T r1, T r2, T
         nz = Sz * inv;
         nrm = ss * inv;
     }
-    double cd, std_;
-    heatbath_angles(static_cast<double>(beta) * static_cast<double>(nrm), static_cast<double>(r1), cd, std_);
-    const T c = static_cast<T>(cd);
-    const T st = static_cast<T>(std_);
+    T c, st;
+    heatbath_angles(beta * nrm, r1, c, st);
     const T sgn = nz >= T(0) ? T(1) : T(-1);
     const T a = T(-1) / (sgn + nz);
     const T b = nx * ny * a;
@@ -187,6 +209,19 @@ struct NormTol<double> {
     static constexpr double value = 1e-10;
 };
 
+// ---------------------------------------------------------------- barriers
+// Workgroup barrier for LDS traffic only: waits until this wave's LDS accesses
+// have completed (lgkmcnt = 0), then joins the barrier.  Unlike __syncthreads()
+// it does not wait for outstanding global loads and stores, so a prefetch or a
+// write-back can stay in flight across it.  The empty asm statements with a
+// memory clobber stop the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: vmcnt = 63, expcnt = 7, lgkmcnt = 0
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -196,20 +231,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Deterministic block sum: fixed butterfly inside each wave, then wave partials
 // added in wave order by thread 0.  `red` holds >= NT/64 doubles of LDS.  The
-// result is valid in thread 0 only.  Contains __syncthreads().
-template <int NT>
+// result is valid in thread 0 only.  Contains two barriers (LDS-only ones if
+// LDS_ONLY, see lds_barrier).
+template <int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
-    __syncthreads();
+    if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int w = 0; w < (NT + 63) / 64; ++w) s += red[w];
     }
-    __syncthreads();
+    if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
     return s;
 }
 

@@ -13,7 +13,12 @@ size_t max_block_lds();
 // LDS-resident path: true if one replica of `e` fits in a workgroup's LDS and
 // an instantiation for e.L exists.
 bool resident_supported(const hsg_ensemble& e);
-// Regular sweeps (anneal = 0) or the annealing legs of one parity (anneal = 1).
+// ... and twice that fits (the two replica buffers of the persistent
+// double-buffered workgroups).
+bool persistent_supported(const hsg_ensemble& e);
+// Regular sweeps, one workgroup per replica (anneal = 0), the annealing legs of
+// one parity (anneal = 1), or regular sweeps on persistent double-buffered
+// workgroups (anneal = 2).
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
                            int parity, int block_threads, hipStream_t st);
 

@@ -4,7 +4,7 @@
 // every half-sweep of the launch (n sweeps of a regular step, or the K sweeps
 // of an annealing leg), so HBM sees one read and one write of the replica per
 // launch.  Each thread owns fixed site pairs (h, h + N/4) of both sublattices
-// and keeps their six couplings and six neighbour offsets in registers.  Sites
+// and keeps their six couplings in registers (neighbour offsets are recomputed).  Sites
 // of one sublattice never interact (paper Sec. III.A), so a half-sweep is one
 // barrier-separated LDS pass; the energy H = -sum_{x in p} s_x.S_x is fused
 // into the last half-sweep of each sweep (every bond has one end in p).
@@ -15,8 +15,7 @@ namespace hsg {
 
 template <typename T, int MQ>
 struct Owned {
-    int nb[2][MQ][2][6];  // [parity][pair][half][direction] neighbour index
-    T j[2][MQ][2][6];     // matching couplings
+    T j[2][MQ][2][6];  // [parity][pair][half][direction] couplings of the owned sites
 };
 
 // One half-sweep over the sites of parity P (compile-time), HB or OR.
@@ -35,17 +34,22 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
     const uint32_t c3 = heatbath_c3(hs);
 #pragma unroll
     for (int m = 0; m < MQ; ++m) {
-        const int q = static_cast<int>(threadIdx.x) + NT * m;
+        int q = static_cast<int>(threadIdx.x) + NT * m;
+        // Opaque copy: keeps the site arithmetic (neighbour offsets, LDS addresses)
+        // inside each half-sweep instead of letting it be hoisted and held live in
+        // registers across the whole kernel (empty asm, no instruction emitted).
+        asm volatile("" : "+v"(q));
         if ((NQ % NT) != 0 && q >= NQ) break;
         Words wq{0, 0, 0, 0};
         if (sizeof(T) == 4 && hb) wq = philox(static_cast<uint32_t>(q), tsw, g, c3, k0, k1);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int h = q + half * NQ;
+            const Nbr nb = neighbours<L>(h, P, L);
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
-                const int idx = own.nb[P][m][half][d];
+                const int idx = nb.n[d];
                 const T jj = own.j[P][m][half][d];
                 Sx = fma(jj, o0[idx], Sx);
                 Sy = fma(jj, o1[idx], Sy);
@@ -159,8 +163,6 @@ __global__ void __launch_bounds__(NT)
                 const int h = (q < NQ ? q : 0) + half * NQ;
                 const Nbr nb = neighbours<L>(h, p, L);
 #pragma unroll
-                for (int d = 0; d < 6; ++d) own.nb[p][m][half][d] = nb.n[d];
-#pragma unroll
                 for (int mu = 0; mu < 3; ++mu) {
                     own.j[p][m][half][2 * mu] = J[(mu * 2 + p) * NH + h];
                     own.j[p][m][half][2 * mu + 1] = J[(mu * 2 + (1 - p)) * NH + nb.n[2 * mu + 1]];
@@ -228,6 +230,132 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
+// Persistent variant for regular sweeps: each workgroup takes a contiguous range
+// of slots (consecutive replicas mostly share a sample, whose couplings then stay
+// in registers) and double-buffers the replicas in LDS: the next replica's loads
+// are issued during the current replica's overrelaxation half-sweeps and the
+// finished replica's stores drain behind the next one, so the load/store phases
+// overlap the arithmetic.  Its barriers are LDS-only (lds_barrier) so that those
+// global accesses stay in flight across them.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT)
+    k_resident_persist(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int n_tasks) {
+    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr int MQ = (NQ + NT - 1) / NT;
+    constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per replica
+    constexpr int PF = (NV + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint4* buf0 = reinterpret_cast<uint4*>(smem_raw);
+    uint4* buf1 = buf0 + NV;
+    __shared__ double red[(NT + 63) / 64];
+    __shared__ double s_H;
+
+    const int C = e.n_chains, R = e.n_temps;
+    const int t_begin = static_cast<int>(static_cast<long long>(blockIdx.x) * n_tasks / gridDim.x);
+    const int t_end = static_cast<int>(static_cast<long long>(blockIdx.x + 1) * n_tasks / gridDim.x);
+    if (t_begin >= t_end) return;
+    const uint4* gsrc = static_cast<const uint4*>(e.spins);
+    uint4* gdst = static_cast<uint4*>(e.spins);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int nhalf = 2 * (n_hb + n_or);
+
+    for (int v = threadIdx.x; v < NV; v += NT) buf0[v] = gsrc[static_cast<size_t>(t_begin) * NV + v];
+    int cur_sample = -1;
+    Owned<T, MQ> own;
+    uint4 pf[PF];
+    int sel = 0;
+    for (int slot = t_begin; slot < t_end; ++slot) {
+        T* sh = reinterpret_cast<T*>(sel ? buf1 : buf0);
+        uint4* nxt = sel ? buf0 : buf1;
+        const int smp = slot / (C * R);
+        if (smp != cur_sample) {
+            const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int m = 0; m < MQ; ++m)
+#pragma unroll
+                    for (int hf = 0; hf < 2; ++hf) {
+                        const int q = static_cast<int>(threadIdx.x) + NT * m;
+                        const int h = (q < NQ ? q : 0) + hf * NQ;
+                        const Nbr nb = neighbours<L>(h, p, L);
+#pragma unroll
+                        for (int mu = 0; mu < 3; ++mu) {
+                            own.j[p][m][hf][2 * mu] = J[(mu * 2 + p) * NH + h];
+                            own.j[p][m][hf][2 * mu + 1] = J[(mu * 2 + (1 - p)) * NH + nb.n[2 * mu + 1]];
+                        }
+                    }
+            cur_sample = smp;
+        }
+        const bool has_next = slot + 1 < t_end;
+        lds_barrier();  // this replica is in LDS; the other buffer's readers are done
+
+        const T beta = static_cast<T>(e.betas[label(e.temp_of_slot[slot], R, e.guard)]);
+        const uint32_t g = e.slot_base + static_cast<uint32_t>(slot);
+        const uint32_t t0 = e.sweep_ctr[slot];
+        double H = 0.0;
+        bool bad = false;
+        // Sweeps before the last one, then the last sweep split so that the next
+        // replica's loads are issued after its heat-bath half-sweeps (outside the
+        // heat-bath's register peak) and land during the overrelaxation ones.
+        double acc = 0.0;
+        const int n_pre = (n_or > 0) ? 2 * n_hb : nhalf - 1;  // half-sweeps before the loads
+        for (int k = 0; k < n_sweeps; ++k) {
+            const bool last = (k == n_sweeps - 1);
+            const uint32_t tsw = t0 + static_cast<uint32_t>(k);
+            const int stop = last ? n_pre : nhalf;
+            for (int pos = 0; pos < stop; ++pos) {
+                const bool hb = pos < 2 * n_hb;
+                if ((pos & 1) == 0)
+                    resident_half<T, L, NT, MQ, 0>(sh, own, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                else
+                    resident_half<T, L, NT, MQ, 1>(sh, own, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                lds_barrier();
+            }
+        }
+        if (has_next) {
+#pragma unroll
+            for (int kk = 0; kk < PF; ++kk) {
+                const int v = static_cast<int>(threadIdx.x) + kk * NT;
+                pf[kk] = (v < NV) ? gsrc[static_cast<size_t>(slot + 1) * NV + v] : make_uint4(0, 0, 0, 0);
+            }
+        }
+        {
+            const uint32_t tsw = t0 + static_cast<uint32_t>(n_sweeps - 1);
+            for (int pos = n_pre; pos < nhalf; ++pos) {
+                const bool hb = pos < 2 * n_hb;
+                const bool want = pos == nhalf - 1;
+                if ((pos & 1) == 0)
+                    resident_half<T, L, NT, MQ, 0>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                else
+                    resident_half<T, L, NT, MQ, 1>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                lds_barrier();
+            }
+        }
+        {
+            const double tot = block_sum<NT, true>(acc, red);
+            if (threadIdx.x == 0) s_H = -tot;
+            lds_barrier();
+            H = s_H;
+        }
+        if (bad || !isfinite(H)) atomicOr(e.guard, 1);
+        const uint4* shv = reinterpret_cast<const uint4*>(sh);
+        for (int v = threadIdx.x; v < NV; v += NT) gdst[static_cast<size_t>(slot) * NV + v] = shv[v];
+        if (has_next) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                if (v < NV) nxt[v] = pf[k];
+            }
+        }
+        if (threadIdx.x == 0) {
+            e.energy[slot] = H;
+            e.sweep_ctr[slot] = t0 + static_cast<uint32_t>(n_sweeps);
+        }
+        sel ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 static int default_threads(int L) {
     const int NQ = L * L * L / 4;
@@ -246,6 +374,39 @@ size_t max_block_lds() {
         if (cached == 0) cached = 65536;
     }
     return cached;
+}
+
+static int num_cus() {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cached = prop.multiProcessorCount;
+        if (cached <= 0) cached = 256;
+    }
+    return cached;
+}
+
+template <typename T, int L, int NT>
+static hipError_t go_persist(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    constexpr int N = L * L * L;
+    const size_t lds = 2 * 3 * N * sizeof(T);
+    const int n_tasks = e.n_samples * e.n_chains * e.n_temps;
+    auto kern = k_resident_persist<T, L, NT>;
+    if (lds > 65536) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (a != hipSuccess) return a;
+    }
+    int per_cu = 0;
+    hipError_t a = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, lds);
+    if (a != hipSuccess || per_cu < 1) per_cu = 1;
+    int grid = num_cus() * per_cu;
+    if (grid > n_tasks) grid = n_tasks;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, n_tasks);
+    return hipGetLastError();
 }
 
 template <typename T, int L, int NT>
@@ -278,7 +439,20 @@ static hipError_t go_nt(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
                         int parity, int nt, hipStream_t st) {
     constexpr int NQ = L * L * L / 4;
     constexpr int DEF = ((NQ + 63) / 64) * 64 > 1024 ? 1024 : ((NQ + 63) / 64) * 64;
-    if (nt == 0 || nt == DEF) return go<T, L, DEF>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
+    if (anneal == 2) {  // regular sweeps, persistent double-buffered workgroups
+        if (nt == 0 || nt == DEF) return go_persist<T, L, DEF>(e, n_sweeps, n_hb, n_or, st);
+        return hipErrorInvalidValue;
+    }
+    // default: one 512-thread workgroup per replica where a replica has >= 1024 site
+    // pairs (two such workgroups share a CU and overlap each other's LDS staging),
+    // else one thread per site pair
+    if (nt == 0) {
+        if constexpr (DEF >= 1024)
+            return go<T, L, 512>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
+        else
+            return go<T, L, DEF>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
+    }
+    if (nt == DEF) return go<T, L, DEF>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
     if constexpr (DEF >= 512) {
         if (nt == 512) return go<T, L, 512>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
         if (nt == 256) return go<T, L, 256>(e, n_sweeps, n_hb, n_or, anneal, parity, st);
@@ -307,6 +481,12 @@ bool resident_supported(const hsg_ensemble& e) {
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
     const size_t lds = 3 * N * (e.precision == HSG_FP64 ? 8 : 4);
     return lds <= max_block_lds();
+}
+
+bool persistent_supported(const hsg_ensemble& e) {
+    if (!resident_supported(e)) return false;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    return 2 * 3 * N * (e.precision == HSG_FP64 ? 8 : 4) <= max_block_lds();
 }
 
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
