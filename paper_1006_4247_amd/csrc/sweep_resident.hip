@@ -394,15 +394,20 @@ static hipError_t go_persist(const hsg_ensemble& e, int n_sweeps, int n_hb, int 
     const size_t lds = 2 * 3 * N * sizeof(T);
     const int n_tasks = e.n_samples * e.n_chains * e.n_temps;
     auto kern = k_resident_persist<T, L, NT>;
-    if (lds > 65536) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-        if (a != hipSuccess) return a;
+    // attribute and occupancy are queried once per instance (not per launch, so that
+    // launches can be captured into graphs without host-side queries in between)
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        if (lds > 65536) {
+            hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(lds));
+            if (a != hipSuccess) return a;
+        }
+        int pc = 0;
+        hipError_t a = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(kern), NT, lds);
+        per_cu = (a != hipSuccess || pc < 1) ? 1 : pc;
     }
-    int per_cu = 0;
-    hipError_t a = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, lds);
-    if (a != hipSuccess || per_cu < 1) per_cu = 1;
     int grid = num_cus() * per_cu;
     if (grid > n_tasks) grid = n_tasks;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, n_tasks);
@@ -423,11 +428,13 @@ static hipError_t go(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, in
         blocks = chains * ((R - parity) / 2) * 2;
     if (blocks <= 0) return hipSuccess;
     auto kern = k_resident<T, L, NT>;
-    if (lds > 65536) {
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
         hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds));
         if (a != hipSuccess) return a;
+        attr_set = true;
     }
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, anneal,
                        parity);

@@ -1,0 +1,182 @@
+"""Drivers for parallel-tempering runs on one GPU.
+
+`PTRun` steps one or several size classes (`Ensemble`s) through the hot path:
+sweep -> exchange (plain, Eq. (1), or annealed) -> measurement.  Each size class runs
+on its own HIP stream, so the kernels of an uneven batch (several L, sample counts and
+ladders) overlap on the chip; `capture()` records one or two steps of every class into
+a HIP graph (torch's graph API drives the capture; every kernel is ours) so that
+replays cost one launch.  Observables are copied into device-resident time series.
+"""
+import numpy as np
+import torch
+
+from .ensemble import Ensemble
+
+
+class PTRun:
+    """mode 'plain': exchange every step with `pairing` (0 = all pairs ascending);
+    mode 'anneal': annealed exchange alternating even / odd pairs (schedules must be
+    set on the ensembles)."""
+
+    def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=0, measure=True,
+                 series_len=0, tunings=None, anneal_sweep=None):
+        if isinstance(ensembles, Ensemble):
+            ensembles = [ensembles]
+        self.ens = list(ensembles)
+        self.n_hb, self.n_or = n_hb, n_or
+        self.mode = mode
+        self.pairing = pairing
+        self.measure = measure
+        self.tunings = tunings or [None] * len(self.ens)
+        self.anneal_sweep = anneal_sweep or (n_hb, n_or)
+        dev = self.ens[0].device
+        self.device = dev
+        self.streams = [torch.cuda.Stream(device=dev) for _ in self.ens]
+        self.parity = 0
+        self.steps_done = 0
+        self.graph = None
+        self.graph_steps = 0
+        self.series_len = int(series_len)
+        self.series_pos = 0
+        if self.series_len:
+            self.chi_series = [torch.zeros((self.series_len,) + tuple(e.chi.shape), dtype=torch.float64,
+                                           device=dev) for e in self.ens]
+            self.e_series = [torch.zeros((self.series_len,) + tuple(e.e_temp.shape), dtype=torch.float64,
+                                         device=dev) for e in self.ens]
+        for e, s in zip(self.ens, self.streams):
+            e.stream = s
+
+    # ------------------------------------------------------------ one step
+    def _step_one(self, i, parity, slot):
+        e = self.ens[i]
+        e.sweep(1, self.n_hb, self.n_or, tuning=self.tunings[i])
+        if self.mode == "plain":
+            e.swap(self.pairing)
+        else:
+            e.anneal_swap(parity, *self.anneal_sweep)
+        if self.measure:
+            e.measure()
+            if self.series_len and slot is not None:
+                self.chi_series[i][slot].copy_(e.chi)
+                self.e_series[i][slot].copy_(e.e_temp)
+
+    def _fork(self, fn):
+        cur = torch.cuda.current_stream(self.device)
+        for s in self.streams:
+            s.wait_stream(cur)
+        for i, s in enumerate(self.streams):
+            with torch.cuda.stream(s):
+                fn(i)
+        for s in self.streams:
+            cur.wait_stream(s)
+
+    def step(self, n=1):
+        """n eager steps (asynchronous)."""
+        if self.graph is not None:
+            raise RuntimeError("this run replays a captured graph; call replay()")
+        for _ in range(n):
+            slot = self._next_slot()
+            par = self.parity
+            self._fork(lambda i: self._step_one(i, par, slot))
+            self.parity ^= 1
+            self.steps_done += 1
+
+    def _next_slot(self):
+        if not self.series_len:
+            return None
+        if self.series_pos >= self.series_len:
+            raise RuntimeError("time series full; read it with series() and reset_series()")
+        p = self.series_pos
+        self.series_pos += 1
+        return p
+
+    # ------------------------------------------------------------ graphs
+    def capture(self, n_steps=None):
+        """Record n_steps steps (default: 1 for plain, 2 for annealed exchange, one per
+        parity) of every size class into one HIP graph.  Time series are not recorded
+        inside graphs."""
+        if self.series_len:
+            raise RuntimeError("graph capture does not record time series (series_len must be 0)")
+        n_steps = n_steps or (1 if self.mode == "plain" else 2)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream(device=self.device)
+        cap.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.graph(g, stream=cap):
+            par = self.parity
+            for _ in range(n_steps):
+                self._fork(lambda i, p=par: self._step_one(i, p, None))
+                par ^= 1
+        torch.cuda.synchronize(self.device)
+        self.graph = g
+        self.graph_steps = n_steps
+        return g
+
+    def replay(self, n=1):
+        """Replay the captured steps n times (on the current stream)."""
+        for _ in range(n):
+            self.graph.replay()
+            self.steps_done += self.graph_steps
+            if self.graph_steps % 2 == 1:
+                self.parity ^= 1
+
+    # ------------------------------------------------------------ results
+    def synchronize(self):
+        torch.cuda.synchronize(self.device)
+
+    def check(self):
+        self.synchronize()
+        for e in self.ens:
+            e.check()
+
+    def series(self, i=0):
+        """(chi [T][S][R], e [T][S][C][R]) recorded so far for size class i (host copies)."""
+        self.synchronize()
+        n = self.series_pos
+        return self.chi_series[i][:n].cpu().numpy(), self.e_series[i][:n].cpu().numpy()
+
+    def reset_series(self):
+        self.series_pos = 0
+
+    def site_updates_per_step(self):
+        return sum(e.n_slots * e.N * (self.n_hb + self.n_or) for e in self.ens)
+
+    def anneal_updates_per_step(self):
+        """Site updates spent in one annealed exchange pass (both legs of every selected
+        pair), averaged over the two parities."""
+        tot = 0.0
+        for e in self.ens:
+            K = e.anneal_K.cpu().numpy()
+            for par in (0, 1):
+                tot += 0.5 * 2 * K[par::2].sum() * e.S * e.C * e.N * sum(self.anneal_sweep)
+        return tot
+
+
+def uneven_batch(Ls, samples, temps, seed, chains=2, precision="fp32", bmin=1.0, bmax=8.0,
+                 device="cuda", K_max=0):
+    """Size classes L[i] with samples[i] samples x chains x temps[i] temperatures on one
+    geometric beta ladder bmin..bmax each, with disjoint random streams."""
+    from .ensemble import geometric_betas
+    ens = []
+    sb = cb = qb = 0
+    for L, S, R in zip(Ls, samples, temps):
+        e = Ensemble(L, S, chains, geometric_betas(bmin, bmax, R), seed, precision=precision,
+                     device=device, sample_base=sb, chain_base=cb, slot_base=qb, K_max=K_max)
+        sb += S
+        cb += S * chains
+        qb += S * chains * R
+        ens.append(e)
+    return ens
+
+
+def linear_schedule(betas, K):
+    """Interior points of the linear protocol l_k = a + k (b - a)/(K + 1), k = 1..K, per pair."""
+    betas = np.asarray(betas, dtype=np.float64)
+    K = np.broadcast_to(np.asarray(K, dtype=np.int64), (len(betas) - 1,))
+    K_max = int(K.max(initial=0))
+    lam = np.zeros((len(betas) - 1, max(K_max, 1)))
+    for i in range(len(betas) - 1):
+        a, b = betas[i], betas[i + 1]
+        for k in range(1, K[i] + 1):
+            lam[i, k - 1] = a + k * (b - a) / (K[i] + 1)
+    return lam
