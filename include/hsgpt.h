@@ -198,6 +198,11 @@ hsg_status hsg_mlp_forward(const float* params, int I, int H, int O, const float
                            float* acts, float* y, void* stream);
 hsg_status hsg_mlp_backward(const float* params, int I, int H, int O, const float* x, int B,
                             float* acts, const float* dy, float* dparams, void* stream);
+/* Weighted squared error of the learner's surrogate fit: with y, t [B][O] and
+ * optional sample weights w [B] (NULL = 1), writes dy = 2 w (y - t) / B and, if
+ * loss != NULL, *loss = sum_b w_b sum_o (y - t)^2 / B (FP64, fixed summation order). */
+hsg_status hsg_mlp_mse_grad(const float* y, const float* t, const float* w, int B, int O,
+                            float* dy, double* loss, void* stream);
 hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
                         float beta1, float beta2, float eps, int t, void* stream);
 

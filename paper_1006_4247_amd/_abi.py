@@ -56,6 +56,7 @@ SIGNATURES = {
     "hsg_check": (_i, [_E, _i, _vp]),
     "hsg_mlp_forward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp]),
     "hsg_mlp_backward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp]),
+    "hsg_mlp_mse_grad": (_i, [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),
     "hsg_mlp_adam": (_i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, _i, _vp]),
 }

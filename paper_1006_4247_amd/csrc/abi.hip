@@ -278,6 +278,14 @@ hsg_status hsg_mlp_backward(const float* params, int I, int H, int O, const floa
                   "mlp_backward");
 }
 
+hsg_status hsg_mlp_mse_grad(const float* y, const float* t, const float* w, int B, int O,
+                            float* dy, double* loss, void* stream) {
+    if (B < 0 || O < 1 || O > 64 || (B > 0 && (!y || !t || !dy)))
+        return fail(HSG_ERR_INVALID, "MLP mse_grad: bad arguments");
+    if (B == 0) return ok();
+    return device(hsg::launch_mlp_mse_grad(y, t, w, B, O, dy, loss, as_stream(stream)), "mlp_mse_grad");
+}
+
 hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
                         float beta1, float beta2, float eps, int t, void* stream) {
     if (!params || !grad || !m || !v || n < 0 || t < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||

@@ -41,6 +41,8 @@ hipError_t launch_mlp_forward(const float* p, int I, int H, int O, const float* 
                               float* acts, float* y, hipStream_t st);
 hipError_t launch_mlp_backward(const float* p, int I, int H, int O, const float* x, int B,
                                float* acts, const float* dy, float* dp, hipStream_t st);
+hipError_t launch_mlp_mse_grad(const float* y, const float* t, const float* w, int B, int O, float* dy,
+                               double* loss, hipStream_t st);
 hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr,
                            float b1, float b2, float eps, int t, hipStream_t st);
 

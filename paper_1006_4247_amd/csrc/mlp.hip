@@ -124,6 +124,31 @@ __global__ void k_mlp_adam(float* p, const float* g, float* m, float* v, int n, 
     p[id] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Weighted squared error L = sum_b w_b sum_o (y_bo - t_bo)^2 / B and dL/dy, one
+// workgroup (deterministic reduction of L in FP64).
+__global__ void __launch_bounds__(256) k_mlp_mse_grad(const float* __restrict__ y, const float* __restrict__ t,
+                                                      const float* __restrict__ w, int B, int O, float* dy,
+                                                      double* loss) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const int n = B * O;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int b = i / O;
+        const float wb = w ? w[b] : 1.0f;
+        const float r = y[i] - t[i];
+        dy[i] = 2.0f * wb * r / static_cast<float>(B);
+        acc += static_cast<double>(wb) * static_cast<double>(r) * static_cast<double>(r);
+    }
+    const double tot = block_sum<256>(acc, red);
+    if (threadIdx.x == 0 && loss) *loss = tot / static_cast<double>(B);
+}
+
+hipError_t launch_mlp_mse_grad(const float* y, const float* t, const float* w, int B, int O, float* dy,
+                               double* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_mse_grad, dim3(1), dim3(256), 0, st, y, t, w, B, O, dy, loss);
+    return hipGetLastError();
+}
+
 static int mlp_threads(int H, int O, int I) {
     int t = H > O ? H : O;
     if (I > t) t = I;

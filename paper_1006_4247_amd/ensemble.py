@@ -76,6 +76,8 @@ class Ensemble:
         self.seed = int(seed)
         self.precision = precision
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.K_max = int(K_max)
         self.stream = stream
         dt = _NT[precision]
@@ -153,6 +155,9 @@ class Ensemble:
         """Standalone bond-sum H of every slot (FP64); returns a new [S][C][R] tensor."""
         if out is None:
             out = torch.empty((self.S, self.C, self.R), dtype=torch.float64, device=self.device)
+        if (tuple(out.shape) != (self.S, self.C, self.R) or out.dtype != torch.float64
+                or not out.is_contiguous() or out.device != self.device):
+            raise ValueError("out must be a contiguous float64 [S][C][R] tensor on %s" % self.device)
         _abi.check(_abi.lib().hsg_energy(ctypes.byref(self.desc), 1, _ptr(out), self._stream()))
         return out
 
