@@ -84,6 +84,81 @@ def cpu_baseline(w, budget_s):
                       "measurement), %.1f s" % (S, w["S"], w["C"], w["R"], w["L"], n, dt)}
 
 
+def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
+    """Accepted exchanges and round trips per GPU-second at matched acceptance (~0.1) on
+    the workload's lattice and beta range: plain PT on a ladder dense enough for
+    acceptance ~0.1 versus annealed exchanges on the workload's own ladder with (a) one
+    protocol length for every pair, chosen for acceptance ~0.1, and (b) the learned
+    per-pair schedule.  Steps are replayed from a HIP graph; the learner's data
+    generation and training are timed separately."""
+    from paper_1006_4247_amd import runtime
+    from paper_1006_4247_amd import schedule as sch
+
+    L, S, C, bmin, bmax = w["L"], w["S"], w["C"], w["bmin"], w["bmax"]
+    R0 = w["R"]
+    R_dense = int(round(0.9 * np.sqrt(L ** 3) + 1))  # acceptance ~0.1 (erfc estimate)
+
+    def make(R, K_max=32):
+        betas = hsg.geometric_betas(bmin, bmax, R)
+        e = hsg.Ensemble(L, S, C, betas, seed + R, precision=w["prec"], K_max=K_max)
+        e.init_couplings()
+        e.init_spins()
+        return e
+
+    def timed(e, mode, steps, warm=300):
+        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode)
+        run.step(warm)
+        run.capture()
+        run.synchronize()
+        st0 = e.swap_stats.cpu().numpy().copy()
+        rt0 = e.rt_trips.cpu().numpy().copy()
+        t0 = time.perf_counter()
+        run.replay(max(1, steps // run.graph_steps))
+        run.synchronize()
+        dt = time.perf_counter() - t0
+        e.check()
+        st = e.swap_stats.cpu().numpy() - st0
+        rt = e.rt_trips.cpu().numpy() - rt0
+        acc = st[..., 1].sum(axis=(0, 1)) / np.maximum(st[..., 0].sum(axis=(0, 1)), 1)
+        n = max(1, steps // run.graph_steps) * run.graph_steps
+        return {"temperatures": e.R, "steps": n, "gpu_s": round(dt, 3), "ms_per_step": round(dt / n * 1e3, 4),
+                "acceptance_min": round(float(acc.min()), 4), "acceptance_mean": round(float(acc.mean()), 4),
+                "accepted_swaps_per_gpu_s": round(float(st[..., 1].sum()) / dt, 1),
+                "round_trips": int(rt.sum()), "round_trips_per_gpu_s": round(float(rt.sum()) / dt, 2)}
+
+    out = {"lattice": "L=%d, %d samples x %d chains, beta %.1f..%.1f" % (L, S, C, bmin, bmax)}
+    out["plain_dense_ladder"] = timed(make(R_dense), "plain", steps_plain)
+    out["plain_own_ladder"] = timed(make(R0), "plain", steps_anneal)
+    e = make(R0)
+    K_uni = 12
+    e.set_schedule(np.full(R0 - 1, K_uni, np.int32))
+    r = timed(e, "anneal", steps_anneal)
+    r["K"] = K_uni
+    out["annealed_uniform_K"] = r
+    e = make(R0)
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(1)
+    K_grid = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    e.sweep(100, w["n_hb"], w["n_or"])
+    x, y, wt = sch.generate_data(e, 120, K_grid, rng, n_hb=w["n_hb"], n_or=w["n_or"])
+    net, loss = sch.train(x, y, wt, steps=3000)
+    _, _, et = e.measure()
+    ebar = et.mean(dim=(0, 1)).cpu().numpy()
+    K, G, pred = sch.select_schedule(net, e.betas_host, ebar, L, K_grid)
+    learn_s = time.perf_counter() - t0
+    e.set_schedule(K, sch.protocol(e.betas_host, K, G, e.K_max))
+    r = timed(e, "anneal", steps_anneal)
+    r.update({"K": [int(k) for k in K], "learner_s": round(learn_s, 2), "train_mse": round(loss, 5)})
+    out["annealed_learned"] = r
+    base = out["plain_dense_ladder"]
+    for k in ("annealed_uniform_K", "annealed_learned"):
+        out[k]["round_trips_per_gpu_s_vs_plain"] = round(
+            out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12), 3)
+        out[k]["accepted_swaps_per_gpu_s_vs_plain"] = round(
+            out[k]["accepted_swaps_per_gpu_s"] / max(base["accepted_swaps_per_gpu_s"], 1e-12), 4)
+    return out
+
+
 def copy_probe(torch, mib, reps=10):
     """Plain device-to-device copy of `mib` MiB: prints the achieved bandwidth (read + write)."""
     n = mib * (1 << 20) // 4
@@ -111,6 +186,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exchange-comparison", action="store_true")
+    ap.add_argument("--compare-steps", type=int, nargs=2, default=[20000, 4000], metavar=("PLAIN", "ANNEAL"),
+                    help="steps of the plain dense-ladder run and of each annealed run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM bandwidth probe and the "
                          "calibration of rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -190,8 +268,10 @@ def main():
                    "exchange": "all neighbour pairs, ascending, every step", "measure": "every step"},
         "roofline": roofline,
         "swap_acceptance_per_pair": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
-        "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1),
+        "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1),  # this ladder (acceptance ~0)
     }
+    if not args.no_exchange_comparison:
+        line["exchange_comparison"] = exchange_comparison(torch, hsg, w, *args.compare_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)
