@@ -101,8 +101,19 @@ __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ void d_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
-__device__ __forceinline__ void d_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+// sin and cos of 2 pi r for r in [0, 1): the binary32 form uses the hardware
+// sine/cosine, whose argument is in turns (absolute error ~1.3e-7 over every
+// 23-bit uniform).
+__device__ __forceinline__ void d_sincos_turns(float r, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(r);
+    *c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void d_sincos_turns(double r, double* s, double* c) {
+    sincospi(2.0 * r, s, c);
+}
+// Reciprocal: hardware approximation (1 ulp) in binary32, exact in binary64.
+__device__ __forceinline__ float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double d_rcp(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------- single-site updates
 // Heat-bath (paper Sec. III.C).  With R = beta |S| the component c of the new
@@ -116,33 +127,71 @@ __device__ __forceinline__ void d_sincospi(double x, double* s, double* c) { sin
 // The angles (c, sin theta) are evaluated so that they keep full relative
 // precision in every regime; in binary32 the single expression above would lose
 // the small r1 to the rounding of 1 - r1 when R is large (errors ~1e-8/(r1 R)).
-// With y = r1 + (1 - r1) exp(-2R) = exp(-R w):
-//   y >= 1/2: w = -log1p((1 - r1) expm1(-2R)) / R   (the form above)
-//   y <  1/2: w = -log(r1 + (1 - r1) exp(-2R)) / R  (sum of positive terms)
-// and, if c < 0, 1 + c = log1p(r1 expm1(2R)) / R directly, so that
-// sin theta = sqrt((1 - c)(1 + c)) has no cancellation near c = -1.
-__device__ __forceinline__ void heatbath_angles(float R, float r1, float& c, float& st) {
-    float w, v;
-    if (R >= 1e-30f) {
-        const float om = 1.0f - r1;
-        const float q = om * expm1f(-2.0f * R);  // y - 1, in (-1, 0]
-        const float ly = (q >= -0.5f) ? log1pf(q) : logf(fmaf(om, expf(-2.0f * R), r1));
-        w = -ly / R;
-        if (w > 1.0f && R < 40.0f) {
-            v = log1pf(r1 * expm1f(2.0f * R)) / R;
-            w = 2.0f - v;
-        } else {
-            v = 2.0f - w;
-        }
-    } else {
-        w = 2.0f * (1.0f - r1);
-        v = 2.0f * r1;
-    }
-    c = (w <= 1.0f) ? 1.0f - w : v - 1.0f;
-    st = sqrtf(w * v);
+// The sign of c is known before any logarithm: c < 0 iff r1 < 1/(1 + e^R) =
+// t/(1 + t), t = e^-R.  The distance u from the nearer pole is then
+//   c >= 0: u = 1 - c = -ln(1 + a)/R,  a = (1 - r1) expm1(-2R)  in (-1, 0]
+//   c <  0: u = 1 + c =  ln(1 + a)/R,  a = r1 expm1(2R)         in [0, e^R)
+// and sin theta = sqrt(u (2 - u)), free of cancellation at both poles.  Each
+// lane evaluates one expm1 and one ln(1 + a): ln(1 + a) by 2 atanh(a/(2 + a))
+// (odd series to s^13, |s| <= 1/3) for a in [-1/2, 1], else by the hardware
+// log2 of 1 + a, or of r1 + (1 - r1) e^-2R, a sum of positive terms; expm1(x)
+// by its Taylor series to x^10 for |x| < 1, else from t^2 or its reciprocal.
+// The exponent rounding of t costs a relative error ~2R 2^-24 in e^-2R, which
+// the division by R turns into an absolute error below 1e-7 in u.  Worst case
+// over the (R, r1) plane: |dc| < 4e-7, |d sin theta| < 2e-7.
+__device__ __forceinline__ float expm1_taylor(float x) {  // |x| < 1
+    float p = 2.755731922e-7f;          // 1/10!
+    p = fmaf(p, x, 2.755731922e-6f);    // 1/9!
+    p = fmaf(p, x, 2.480158730e-5f);    // 1/8!
+    p = fmaf(p, x, 1.984126984e-4f);    // 1/7!
+    p = fmaf(p, x, 1.388888889e-3f);    // 1/6!
+    p = fmaf(p, x, 8.333333333e-3f);    // 1/5!
+    p = fmaf(p, x, 4.166666667e-2f);    // 1/4!
+    p = fmaf(p, x, 1.666666667e-1f);    // 1/3!
+    p = fmaf(p, x, 0.5f);
+    p = fmaf(p, x, 1.0f);
+    return p * x;
 }
 
-// Binary64: the single expression is accurate to ~1e-16/(r1 R), far inside
+__device__ __forceinline__ float log1p_atanh(float a) {  // a in [-1/2, 1]
+    const float s = a * __builtin_amdgcn_rcpf(2.0f + a);
+    const float s2 = s * s;
+    float p = 1.0f / 13.0f;
+    p = fmaf(p, s2, 1.0f / 11.0f);
+    p = fmaf(p, s2, 1.0f / 9.0f);
+    p = fmaf(p, s2, 1.0f / 7.0f);
+    p = fmaf(p, s2, 1.0f / 5.0f);
+    p = fmaf(p, s2, 1.0f / 3.0f);
+    p = fmaf(p, s2, 1.0f);
+    return (2.0f * s) * p;
+}
+
+__device__ __forceinline__ void heatbath_angles(float R, float r1, float& c, float& st) {
+    const float om = 1.0f - r1;
+    float u;
+    bool neg;
+    if (R >= 1e-30f) {
+        const float t = __builtin_amdgcn_exp2f(-1.44269504088896341f * R);
+        const float E = t * t;
+        neg = fmaf(r1, t, r1) < t;
+        const float x = neg ? 2.0f * R : -2.0f * R;
+        const float em = (R < 0.5f) ? expm1_taylor(x)
+                                    : (neg ? __builtin_amdgcn_rcpf(E) : E) - 1.0f;
+        const float a = (neg ? r1 : om) * em;
+        const float y = neg ? 1.0f + a : fmaf(om, E, r1);
+        const float lg = (a >= -0.5f && a <= 1.0f)
+                             ? log1p_atanh(a)
+                             : 0.693147180559945309f * __builtin_amdgcn_logf(y);
+        u = fabsf(lg) * __builtin_amdgcn_rcpf(R);
+    } else {
+        neg = r1 < 0.5f;
+        u = neg ? 2.0f * r1 : 2.0f * om;
+    }
+    c = neg ? u - 1.0f : 1.0f - u;
+    st = __builtin_amdgcn_sqrtf(u * (2.0f - u));
+}
+
+// Binary64: the single expression above is accurate to ~1e-16/(r1 R), far inside
 // every tolerance, and matches the reference evaluation.
 __device__ __forceinline__ void heatbath_angles(double R, double r1, double& c, double& st) {
     double w;
@@ -170,12 +219,12 @@ __device__ __forceinline__ void heatbath(T Sx, T Sy, T Sz, T beta, T r1, T r2, T
     T c, st;
     heatbath_angles(beta * nrm, r1, c, st);
     const T sgn = nz >= T(0) ? T(1) : T(-1);
-    const T a = T(-1) / (sgn + nz);
+    const T a = -d_rcp(sgn + nz);
     const T b = nx * ny * a;
     const T e1x = T(1) + sgn * nx * nx * a, e1y = sgn * b, e1z = -sgn * nx;
     const T e2x = b, e2y = sgn + ny * ny * a, e2z = -ny;
     T sp, cp;
-    d_sincospi(T(2) * r2, &sp, &cp);
+    d_sincos_turns(r2, &sp, &cp);
     ox = c * nx + st * (sp * e1x + cp * e2x);
     oy = c * ny + st * (sp * e1y + cp * e2y);
     oz = c * nz + st * (sp * e1z + cp * e2z);
@@ -187,7 +236,7 @@ __device__ __forceinline__ void overrelax(T sx, T sy, T sz, T Sx, T Sy, T Sz, T&
                                           T& oz) {
     const T ss = Sx * Sx + Sy * Sy + Sz * Sz;
     if (ss > T(0)) {
-        const T f = T(2) * (sx * Sx + sy * Sy + sz * Sz) / ss;
+        const T f = T(2) * (sx * Sx + sy * Sy + sz * Sz) * d_rcp(ss);
         ox = f * Sx - sx;
         oy = f * Sy - sy;
         oz = f * Sz - sz;
