@@ -21,6 +21,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every fused multiply-add is written out, so each
+    # kernel instance evaluates exactly the stated operations (bitwise-equal results
+    # across tile shapes and variants)
+    "-ffp-contract=off",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
 ]
 

@@ -207,7 +207,7 @@ __device__ __forceinline__ void heatbath_angles(double R, double r1, double& c, 
 template <typename T>
 __device__ __forceinline__ void heatbath(T Sx, T Sy, T Sz, T beta, T r1, T r2, T& ox, T& oy,
                                          T& oz) {
-    const T ss = Sx * Sx + Sy * Sy + Sz * Sz;
+    const T ss = fma(Sz, Sz, fma(Sy, Sy, Sx * Sx));
     T nx = T(0), ny = T(0), nz = T(1), nrm = T(0);
     if (ss > T(0)) {
         const T inv = d_rsqrt(ss);
@@ -221,25 +221,25 @@ __device__ __forceinline__ void heatbath(T Sx, T Sy, T Sz, T beta, T r1, T r2, T
     const T sgn = nz >= T(0) ? T(1) : T(-1);
     const T a = -d_rcp(sgn + nz);
     const T b = nx * ny * a;
-    const T e1x = T(1) + sgn * nx * nx * a, e1y = sgn * b, e1z = -sgn * nx;
-    const T e2x = b, e2y = sgn + ny * ny * a, e2z = -ny;
+    const T e1x = fma(sgn * nx, nx * a, T(1)), e1y = sgn * b, e1z = -sgn * nx;
+    const T e2x = b, e2y = fma(ny, ny * a, sgn), e2z = -ny;
     T sp, cp;
     d_sincos_turns(r2, &sp, &cp);
-    ox = c * nx + st * (sp * e1x + cp * e2x);
-    oy = c * ny + st * (sp * e1y + cp * e2y);
-    oz = c * nz + st * (sp * e1z + cp * e2z);
+    ox = fma(c, nx, st * fma(sp, e1x, cp * e2x));
+    oy = fma(c, ny, st * fma(sp, e1y, cp * e2y));
+    oz = fma(c, nz, st * fma(sp, e1z, cp * e2z));
 }
 
 // Overrelaxation (paper Sec. III.C): reflection about S; identity if S = 0.
 template <typename T>
 __device__ __forceinline__ void overrelax(T sx, T sy, T sz, T Sx, T Sy, T Sz, T& ox, T& oy,
                                           T& oz) {
-    const T ss = Sx * Sx + Sy * Sy + Sz * Sz;
+    const T ss = fma(Sz, Sz, fma(Sy, Sy, Sx * Sx));
     if (ss > T(0)) {
-        const T f = T(2) * (sx * Sx + sy * Sy + sz * Sz) * d_rcp(ss);
-        ox = f * Sx - sx;
-        oy = f * Sy - sy;
-        oz = f * Sz - sz;
+        const T f = T(2) * fma(sz, Sz, fma(sy, Sy, sx * Sx)) * d_rcp(ss);
+        ox = fma(f, Sx, -sx);
+        oy = fma(f, Sy, -sy);
+        oz = fma(f, Sz, -sz);
     } else {
         ox = sx;
         oy = sy;

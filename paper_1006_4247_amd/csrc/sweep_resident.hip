@@ -18,13 +18,56 @@ struct Owned {
     T j[2][MQ][2][6];  // [parity][pair][half][direction] couplings of the owned sites
 };
 
+// Owned-site geometry.  Thread t owns the sites h = t + NT m + NQ half of each
+// sublattice (h = ih + (L/2)(j + L k), x = 2 ih + o, o = (p + j + k) & 1).  When
+// NT is a whole number of sublattice k-planes (L/2 * L sites), NT divides NQ and
+// the k-steps NT/(L/2 L) (between m) and L/2 (between halves) keep the parity of
+// k, all sites of a thread share (ih, j, o): their neighbours are those of the
+// first site shifted by the compile-time NT m + NQ half, except the z-neighbours
+// across the periodic boundary, which only the first site (-z) and the last site
+// (+z) can have.  Nine per-thread indices then address every neighbour and the
+// site offsets fold into the LDS instructions.
+template <int L, int NT>
+struct SiteMap {
+    static constexpr int HL = L / 2, N = L * L * L, NQ = N / 4, PLANE = HL * L;
+    static constexpr int MQ = (NQ + NT - 1) / NT;
+    static constexpr int STEPK = NT / PLANE;
+    static constexpr bool invariant = (NT % PLANE == 0) && (NQ % NT == 0) &&
+                                      (STEPK % 2 == 0 || MQ == 1) && ((L / 2) % 2 == 0);
+};
+
+struct FirstNbr {
+    int x[2][2];  // [parity][+x, -x] of the first site
+    int yp, ym;   // +y, -y of the first site (either parity)
+    int zm_first, zp_last;
+};
+
+template <int L, int NT>
+__device__ __forceinline__ FirstNbr first_neighbours() {
+    using M = SiteMap<L, NT>;
+    const int t = static_cast<int>(threadIdx.x);
+    FirstNbr f;
+    const Nbr a = neighbours<L>(t, 0, L), b = neighbours<L>(t, 1, L);
+    f.x[0][0] = a.n[0];
+    f.x[0][1] = a.n[1];
+    f.x[1][0] = b.n[0];
+    f.x[1][1] = b.n[1];
+    f.yp = a.n[2];
+    f.ym = a.n[3];
+    f.zm_first = a.n[5];
+    f.zp_last = neighbours<L>(t + NT * (M::MQ - 1) + M::NQ, 0, L).n[4];
+    return f;
+}
+
 // One half-sweep over the sites of parity P (compile-time), HB or OR.
 template <typename T, int L, int NT, int MQ, int P>
 __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T, MQ>& own,
-                                              bool hb, int hs, T beta, uint32_t tsw, uint32_t g,
-                                              uint32_t k0, uint32_t k1, bool want,
-                                              double& acc, bool& bad) {
+                                              const FirstNbr& fn, bool hb, int hs, T beta,
+                                              uint32_t tsw, uint32_t g, uint32_t k0, uint32_t k1,
+                                              bool want, double& acc, bool& bad) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr bool INV = SiteMap<L, NT>::invariant;
+    constexpr int PLANE = SiteMap<L, NT>::PLANE;
     const T* __restrict__ o0 = sh + (0 * 2 + (1 - P)) * NH;
     const T* __restrict__ o1 = sh + (1 * 2 + (1 - P)) * NH;
     const T* __restrict__ o2 = sh + (2 * 2 + (1 - P)) * NH;
@@ -35,17 +78,30 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 #pragma unroll
     for (int m = 0; m < MQ; ++m) {
         int q = static_cast<int>(threadIdx.x) + NT * m;
-        // Opaque copy: keeps the site arithmetic (neighbour offsets, LDS addresses)
-        // inside each half-sweep instead of letting it be hoisted and held live in
-        // registers across the whole kernel (empty asm, no instruction emitted).
-        asm volatile("" : "+v"(q));
+        // Generic geometry: an opaque copy keeps the site arithmetic (neighbour
+        // offsets, LDS addresses) inside each half-sweep instead of letting it be
+        // hoisted and held live in registers across the whole kernel (empty asm,
+        // no instruction emitted).
+        if (!INV) asm volatile("" : "+v"(q));
         if ((NQ % NT) != 0 && q >= NQ) break;
         Words wq{0, 0, 0, 0};
         if (sizeof(T) == 4 && hb) wq = philox(static_cast<uint32_t>(q), tsw, g, c3, k0, k1);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int h = q + half * NQ;
-            const Nbr nb = neighbours<L>(h, P, L);
+            Nbr nb;
+            if constexpr (INV) {
+                const int c = NT * m + NQ * half;
+                const int t = static_cast<int>(threadIdx.x);
+                nb.n[0] = fn.x[P][0] + c;
+                nb.n[1] = fn.x[P][1] + c;
+                nb.n[2] = fn.yp + c;
+                nb.n[3] = fn.ym + c;
+                nb.n[4] = (m == MQ - 1 && half == 1) ? fn.zp_last : t + PLANE + c;
+                nb.n[5] = (m == 0 && half == 0) ? fn.zm_first : t - PLANE + c;
+            } else {
+                nb = neighbours<L>(h, P, L);
+            }
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
@@ -75,9 +131,9 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
             w2[h] = oz;
             if (want) {
                 const double dx = ox, dy = oy, dz = oz;
-                acc += dx * static_cast<double>(Sx) + dy * static_cast<double>(Sy) +
-                       dz * static_cast<double>(Sz);
-                const double n2 = dx * dx + dy * dy + dz * dz;
+                acc += fma(dz, static_cast<double>(Sz),
+                           fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+                const double n2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 if (!(fabs(n2 - 1.0) <= NormTol<T>::value)) bad = true;
             }
         }
@@ -153,6 +209,7 @@ __global__ void __launch_bounds__(NT)
         for (int v = threadIdx.x; v < NV; v += NT) dst[v] = src[v];
     }
     Owned<T, MQ> own;
+    const FirstNbr fn = first_neighbours<L, NT>();
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -196,9 +253,9 @@ __global__ void __launch_bounds__(NT)
             const int p = pos & 1;
             const bool want = need_e && (step == nhalf - 1);
             if (p == 0)
-                resident_half<T, L, NT, MQ, 0>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
             else
-                resident_half<T, L, NT, MQ, 1>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
             __syncthreads();
         }
         if (need_e) {
@@ -262,6 +319,7 @@ __global__ void __launch_bounds__(NT)
     for (int v = threadIdx.x; v < NV; v += NT) buf0[v] = gsrc[static_cast<size_t>(t_begin) * NV + v];
     int cur_sample = -1;
     Owned<T, MQ> own;
+    const FirstNbr fn = first_neighbours<L, NT>();
     uint4 pf[PF];
     int sel = 0;
     for (int slot = t_begin; slot < t_end; ++slot) {
@@ -307,9 +365,9 @@ __global__ void __launch_bounds__(NT)
             for (int pos = 0; pos < stop; ++pos) {
                 const bool hb = pos < 2 * n_hb;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
                 lds_barrier();
             }
         }
@@ -326,9 +384,9 @@ __global__ void __launch_bounds__(NT)
                 const bool hb = pos < 2 * n_hb;
                 const bool want = pos == nhalf - 1;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
                 lds_barrier();
             }
         }

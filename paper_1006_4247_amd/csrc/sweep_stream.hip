@@ -149,9 +149,9 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
                 w2[h] = oz;
                 if (a.want) {
                     const double dx = ox, dy = oy, dz = oz;
-                    acc += dx * static_cast<double>(Sx) + dy * static_cast<double>(Sy) +
-                           dz * static_cast<double>(Sz);
-                    const double n2 = dx * dx + dy * dy + dz * dz;
+                    acc += fma(dz, static_cast<double>(Sz),
+                               fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+                    const double n2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     if (!(fabs(n2 - 1.0) <= NormTol<T>::value)) bad = true;
                 }
             }

@@ -84,7 +84,7 @@ def test_sweep_variants_agree(prec, L):
     out = []
     for tune in [{"path": 3}, {"path": 1}, {"path": 2, "block_threads": 128, "replicas_per_block": 4},
                  {"path": 2, "block_threads": 256, "replicas_per_block": 2},
-                 {"path": 3, "block_threads": 256}]:
+                 {"path": 3, "block_threads": 256}, {"path": 3, "block_threads": 1024}]:
         e = hsg.Ensemble(L, 2, 2, hsg.geometric_betas(1.0, 8.0, 3), SEED, precision=prec)
         e.init_couplings()
         e.init_spins()
