@@ -96,6 +96,16 @@ __device__ __forceinline__ Nbr neighbours(int h, int p, int Lrt) {
     return r;
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b on XCD
+// b mod 8), and each XCD has its own L2.  Renumbering b so that XCD x receives
+// the contiguous work items [x n/8, (x + 1) n/8) keeps work items that share
+// data (replicas of one sample read the same couplings) on one L2.  A
+// bijection of [0, n); the identity when n is not a multiple of 8.
+__device__ __forceinline__ int xcd_order(int b, int n) {
+    if (n & 7) return b;
+    return (b & 7) * (n >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------- math wrappers
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }

@@ -59,6 +59,59 @@ __device__ __forceinline__ FirstNbr first_neighbours() {
     return f;
 }
 
+// Vector v of a replica as loaded into LDS: all six planes in order, or
+// (parity1_only) the three parity-1 planes, plane mu at (2 mu + 1) NVP.
+template <int NVP>
+__device__ __forceinline__ int loaded_vec(int v, bool parity1_only) {
+    if (!parity1_only) return v;
+    const int mu = v / NVP;
+    return (2 * mu + 1) * NVP + (v - mu * NVP);
+}
+
+// Neighbours of owned site (m, half) of parity p, h = t + NT m + NQ half.
+template <int L, int NT, int MQ>
+__device__ __forceinline__ Nbr site_nbrs(const FirstNbr& fn, int p, int m, int half, int h) {
+    using M = SiteMap<L, NT>;
+    Nbr nb;
+    if constexpr (M::invariant) {
+        const int c = NT * m + M::NQ * half;
+        const int t = static_cast<int>(threadIdx.x);
+        nb.n[0] = fn.x[p][0] + c;
+        nb.n[1] = fn.x[p][1] + c;
+        nb.n[2] = fn.yp + c;
+        nb.n[3] = fn.ym + c;
+        nb.n[4] = (m == MQ - 1 && half == 1) ? fn.zp_last : t + M::PLANE + c;
+        nb.n[5] = (m == 0 && half == 0) ? fn.zm_first : t - M::PLANE + c;
+    } else {
+        nb = neighbours<L>(h, p, L);
+    }
+    return nb;
+}
+
+// The six couplings of every owned site, from a coupling array [3][2][NH] (global
+// memory or its LDS copy): the bond to +mu is stored at the site, the bond to -mu
+// at the -mu neighbour.
+template <typename T, int L, int NT, int MQ>
+__device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restrict__ J,
+                                           const FirstNbr& fn) {
+    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int m = 0; m < MQ; ++m)
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int q = static_cast<int>(threadIdx.x) + NT * m;
+                const int h = (q < NQ ? q : 0) + half * NQ;
+                const Nbr nb = site_nbrs<L, NT, MQ>(fn, p, m, half, h);
+#pragma unroll
+                for (int mu = 0; mu < 3; ++mu) {
+                    own.j[p][m][half][2 * mu] = J[(mu * 2 + p) * NH + h];
+                    own.j[p][m][half][2 * mu + 1] = J[(mu * 2 + (1 - p)) * NH + nb.n[2 * mu + 1]];
+                }
+            }
+}
+
 // One half-sweep over the sites of parity P (compile-time), HB or OR.
 template <typename T, int L, int NT, int MQ, int P>
 __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T, MQ>& own,
@@ -67,7 +120,6 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
                                               bool want, double& acc, bool& bad) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
     constexpr bool INV = SiteMap<L, NT>::invariant;
-    constexpr int PLANE = SiteMap<L, NT>::PLANE;
     const T* __restrict__ o0 = sh + (0 * 2 + (1 - P)) * NH;
     const T* __restrict__ o1 = sh + (1 * 2 + (1 - P)) * NH;
     const T* __restrict__ o2 = sh + (2 * 2 + (1 - P)) * NH;
@@ -89,19 +141,7 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int h = q + half * NQ;
-            Nbr nb;
-            if constexpr (INV) {
-                const int c = NT * m + NQ * half;
-                const int t = static_cast<int>(threadIdx.x);
-                nb.n[0] = fn.x[P][0] + c;
-                nb.n[1] = fn.x[P][1] + c;
-                nb.n[2] = fn.yp + c;
-                nb.n[3] = fn.ym + c;
-                nb.n[4] = (m == MQ - 1 && half == 1) ? fn.zp_last : t + PLANE + c;
-                nb.n[5] = (m == 0 && half == 0) ? fn.zm_first : t - PLANE + c;
-            } else {
-                nb = neighbours<L>(h, P, L);
-            }
+            const Nbr nb = site_nbrs<L, NT, MQ>(fn, P, m, half, h);
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
@@ -140,13 +180,15 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
     }
 }
 
-// mode 0: regular sweeps of slot blockIdx.x at its own temperature.
+// Work item of a workgroup: xcd_order(blockIdx.x) (consecutive work items, which
+// share a sample and its couplings, run on one XCD).
+// mode 0: regular sweeps of slot (work item) at its own temperature.
 // mode 1: annealing legs of the pairs with i mod 2 == parity; block ->
 //         (chain, pair, leg); leg 0 = up (forward order), 1 = down (adjoint).
 template <typename T, int L, int NT>
 __global__ void __launch_bounds__(NT)
     k_resident(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int anneal, int parity) {
-    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr int N = L * L * L, NQ = N / 4;
     constexpr int MQ = (NQ + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
@@ -157,12 +199,13 @@ __global__ void __launch_bounds__(NT)
     int slot, leg = 0, ipair = 0, K = n_sweeps, ch = 0;
     double lam_a = 0.0, lam_b = 0.0;
     const double* lam_tab = nullptr;
+    const int bid = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
     if (!anneal) {
-        slot = blockIdx.x;
+        slot = bid;
     } else {
         const int npp = (R - parity) / 2;
-        leg = blockIdx.x & 1;
-        const int rest = blockIdx.x >> 1;
+        leg = bid & 1;
+        const int rest = bid >> 1;
         ch = rest / npp;
         ipair = parity + 2 * (rest % npp);
         slot = ch * R + label(e.slot_of_temp[ch * R + ipair + leg], R, e.guard);
@@ -201,30 +244,64 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    // stage the replica into LDS (16-byte vectors)
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(gs);
-        uint4* dst = reinterpret_cast<uint4*>(sh);
-        constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
-        for (int v = threadIdx.x; v < NV; v += NT) dst[v] = src[v];
-    }
+    // Couplings: global -> LDS (16-byte vectors) -> registers; then the replica ->
+    // LDS.  A sweep that opens with a heat-bath half-sweep of parity 0 (every
+    // regular sweep and forward leg with n_hb > 0) overwrites each parity-0 spin
+    // without reading it, as the heat-bath draw depends on the neighbours only:
+    // then only the three parity-1 planes are loaded.  Where the vectors fit in
+    // registers, the replica's loads are issued right after the couplings' loads
+    // and stay in flight while the couplings pass through LDS.
     Owned<T, MQ> own;
     const FirstNbr fn = first_neighbours<L, NT>();
+    {
+        constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // vectors per replica
+        constexpr int NVP = NV / 6;                                    // per plane
+        constexpr int PV = (NV + NT - 1) / NT;                         // per thread
+        constexpr bool PREFETCH = PV <= 6;
+        const bool hb_first = n_hb > 0 && (anneal ? leg == 0 : n_sweeps > 0);
+        const uint4* js = reinterpret_cast<const uint4*>(J);
+        const uint4* src = reinterpret_cast<const uint4*>(gs);
+        uint4* dst = reinterpret_cast<uint4*>(sh);
+        const int n_load = hb_first ? NV / 2 : NV;
+        if constexpr (PREFETCH) {
+            uint4 jv[PV], sv[PV];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+            for (int k = 0; k < PV; ++k) {
+                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                jv[k] = (v < NV) ? js[v] : make_uint4(0, 0, 0, 0);
+            }
 #pragma unroll
-        for (int m = 0; m < MQ; ++m)
+            for (int k = 0; k < PV; ++k) {
+                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                sv[k] = (v < n_load) ? src[loaded_vec<NVP>(v, hb_first)] : make_uint4(0, 0, 0, 0);
+            }
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const int q = static_cast<int>(threadIdx.x) + NT * m;
-                const int h = (q < NQ ? q : 0) + half * NQ;
-                const Nbr nb = neighbours<L>(h, p, L);
+            for (int k = 0; k < PV; ++k) {
+                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                if (v < NV) dst[v] = jv[k];
+            }
+            lds_barrier();
+            load_owned<T, L, NT, MQ>(own, sh, fn);
+            lds_barrier();  // every thread holds its couplings before the LDS is reused
 #pragma unroll
-                for (int mu = 0; mu < 3; ++mu) {
-                    own.j[p][m][half][2 * mu] = J[(mu * 2 + p) * NH + h];
-                    own.j[p][m][half][2 * mu + 1] = J[(mu * 2 + (1 - p)) * NH + nb.n[2 * mu + 1]];
+            for (int k = 0; k < PV; ++k) {
+                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                if (v < n_load) {
+                    const int o = loaded_vec<NVP>(v, hb_first);
+                    dst[o] = sv[k];
                 }
             }
+        } else {
+            for (int v = threadIdx.x; v < NV; v += NT) dst[v] = js[v];
+            __syncthreads();
+            load_owned<T, L, NT, MQ>(own, sh, fn);
+            __syncthreads();
+            for (int v = threadIdx.x; v < n_load; v += NT) {
+                const int o = loaded_vec<NVP>(v, hb_first);
+                dst[o] = src[o];
+            }
+        }
+    }
     __syncthreads();
 
     const int nhalf = 2 * (n_hb + n_or);
@@ -297,7 +374,7 @@ __global__ void __launch_bounds__(NT)
 template <typename T, int L, int NT>
 __global__ void __launch_bounds__(NT)
     k_resident_persist(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int n_tasks) {
-    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr int N = L * L * L, NQ = N / 4;
     constexpr int MQ = (NQ + NT - 1) / NT;
     constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per replica
     constexpr int PF = (NV + NT - 1) / NT;
@@ -308,8 +385,9 @@ __global__ void __launch_bounds__(NT)
     __shared__ double s_H;
 
     const int C = e.n_chains, R = e.n_temps;
-    const int t_begin = static_cast<int>(static_cast<long long>(blockIdx.x) * n_tasks / gridDim.x);
-    const int t_end = static_cast<int>(static_cast<long long>(blockIdx.x + 1) * n_tasks / gridDim.x);
+    const long long bid = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int t_begin = static_cast<int>(bid * n_tasks / gridDim.x);
+    const int t_end = static_cast<int>((bid + 1) * n_tasks / gridDim.x);
     if (t_begin >= t_end) return;
     const uint4* gsrc = static_cast<const uint4*>(e.spins);
     uint4* gdst = static_cast<uint4*>(e.spins);
@@ -328,21 +406,7 @@ __global__ void __launch_bounds__(NT)
         const int smp = slot / (C * R);
         if (smp != cur_sample) {
             const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int m = 0; m < MQ; ++m)
-#pragma unroll
-                    for (int hf = 0; hf < 2; ++hf) {
-                        const int q = static_cast<int>(threadIdx.x) + NT * m;
-                        const int h = (q < NQ ? q : 0) + hf * NQ;
-                        const Nbr nb = neighbours<L>(h, p, L);
-#pragma unroll
-                        for (int mu = 0; mu < 3; ++mu) {
-                            own.j[p][m][hf][2 * mu] = J[(mu * 2 + p) * NH + h];
-                            own.j[p][m][hf][2 * mu + 1] = J[(mu * 2 + (1 - p)) * NH + nb.n[2 * mu + 1]];
-                        }
-                    }
+            load_owned<T, L, NT, MQ>(own, J, fn);
             cur_sample = smp;
         }
         const bool has_next = slot + 1 < t_end;
