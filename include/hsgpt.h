@@ -177,6 +177,21 @@ hsg_status hsg_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* strea
 hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n_hb, int n_or,
                            void* stream);
 
+/* Decimated replica exchange (paper Sec. III.A, Eq. (eq:aswap)) of the selected
+ * pairs of every chain (pairing 0: all pairs in ascending order; 1: even i;
+ * 2: odd i).  Pair i decimates sublattice D_i = (d_0 + i) mod 2 (parity of
+ * i + j + k), d_0 one random bit per chain and call.  With S_z the local field
+ * of the kept sublattice at z in D and h(u) = ln(sinh(u)/u),
+ *   ln A = sum_{z in D} h(b2 |S_z(x)|) - h(b1 |S_z(x)|) + h(b1 |S_z(y)|) - h(b2 |S_z(y)|)
+ * for x at b1 = beta_i and y at b2 = beta_{i+1}, in FP64 (fields in the spin
+ * precision).  Accept iff ln u < ln A (u from the same per-pair stream as
+ * hsg_swap): the labels are exchanged and the D spins of x and y are drawn anew
+ * by heat-bath at beta_{i+1} and beta_i, and their energies recomputed;
+ * otherwise nothing changes.  Advances swap_ctr, updates swap_stats and round
+ * trips.  If work is not NULL it receives, per pair, ln A and D_i
+ * ([S][C][R-1][2]; 0 and -1 for pairs not attempted).  n_temps <= 65536. */
+hsg_status hsg_decimate_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* stream);
+
 /* Overlap (paper Sec. II): Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between the
  * chain-0 and chain-1 configurations at each temperature, chi = Q:Q / N, and
  * e_temp = H/N by temperature (the paper's E is -e).  Q and chi need C >= 2. */

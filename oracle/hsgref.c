@@ -21,6 +21,7 @@
  *   replica exchange acceptance  -- paper Sec. I, Eq. (1)
  *   overlap, susceptibility, E   -- paper Sec. II, Eq. (eq:over) and following
  *   round trips                  -- paper Sec. IV.B
+ *   decimated exchange           -- paper Sec. III.A, Eqs. (xxxY), (HI), (eq:aswap)
  *   annealed (nonequilibrium) swap -- cited prior art of Sec. I (Opps & Schofield
  *     2001; Ballard & Jarzynski 2009); the protocol below is the standard
  *     nonequilibrium-candidate construction, which reduces to Eq. (1) at K = 0.
@@ -101,6 +102,8 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
 #define TAG_INIT 2u
 #define TAG_HEATBATH 3u
 #define TAG_SWAP 4u
+#define TAG_DECIMATE 5u      /* heat-bath re-insertion after a decimated exchange */
+#define TAG_DECIMATE_ROLE 6u /* which sublattice the first pair decimates */
 
 /* ------------------------------------------------------------------------- */
 /* Lattice: periodic simple cubic, x = i + L(j + L k); W = even, B = odd.    */
@@ -607,6 +610,148 @@ void hsgref_anneal_batch(int L, int S, int C, int R, const double* J, double* sp
     }
     free(cand);
     free(wbuf);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Decimated exchange (paper Sec. III.A).  The sites of one sublattice D do   */
+/* not interact, so integrating their spins out of exp(-beta H) leaves, per   */
+/* site z in D, I(beta S_z) = int ds exp(beta s.S_z) = 4 pi sinh(R)/R with    */
+/* R = beta |S_z| (Eq. (HI); the measure ds on the unit sphere has total      */
+/* 4 pi), S_z the local field of the kept sublattice.  Exchanging the kept    */
+/* fields of x (at beta_1) and y (at beta_2) is accepted with Eq. (eq:aswap): */
+/*   ln A = sum_{z in D} [h(b2 a_z) - h(b1 a_z) + h(b1 c_z) - h(b2 c_z)],      */
+/* a_z = |S_z(x)|, c_z = |S_z(y)|, h(u) = ln(sinh(u)/u) = ln I / (4 pi); the   */
+/* constants 4 pi and the 1/R factors cancel between the four terms.          */
+/* If accepted, the D spins of both configurations are drawn anew by heat-    */
+/* bath at their new temperatures (x at beta_2, y at beta_1); if rejected,    */
+/* nothing changes.  The first pair decimates a random sublattice and the     */
+/* role alternates from one pair to the next: D_i = (d_0 + i) mod 2.          */
+/* ------------------------------------------------------------------------- */
+
+/* h(u) = ln(sinh(u)/u) for u >= 0, written as u + ln((1 - e^{-2u})/(2u)):     */
+/* finite for every u, h(0) = 0.                                               */
+double hsgref_log_sinhc(double u)
+{
+    if (u <= 0.0) return 0.0;
+    return u + log(-expm1(-2.0 * u) / (2.0 * u));
+}
+
+/* ln A of Eq. (eq:aswap) for x at b1 and y at b2, decimating parity d. */
+double hsgref_decimated_log_ratio(int L, const double* J, const double* sx, const double* sy,
+                                  int d, double b1, double b2)
+{
+    int N = L * L * L, z;
+    double lnA = 0.0;
+    for (z = 0; z < N; ++z) {
+        double Sa[3], Sc[3], a, c;
+        if (hsgref_parity(L, z) != d) continue;
+        hsgref_local_field(L, J, sx, z, Sa);
+        hsgref_local_field(L, J, sy, z, Sc);
+        a = sqrt(Sa[0] * Sa[0] + Sa[1] * Sa[1] + Sa[2] * Sa[2]);
+        c = sqrt(Sc[0] * Sc[0] + Sc[1] * Sc[1] + Sc[2] * Sc[2]);
+        lnA += hsgref_log_sinhc(b2 * a) - hsgref_log_sinhc(b1 * a)
+             + hsgref_log_sinhc(b1 * c) - hsgref_log_sinhc(b2 * c);
+    }
+    return lnA;
+}
+
+/* Uniforms of the re-insertion of site x after pair i of call n: the layout  */
+/* of hsgref_hb_uniforms with counter word 1 = n and word 3 = tag, pair.      */
+void hsgref_decimate_uniforms(int L, int rng32, uint64_t seed, uint32_t slot_global, uint32_t n,
+                              uint32_t pair, int x, double* r1, double* r2)
+{
+    int N = L * L * L;
+    int h = hsgref_compressed_index(L, x);
+    uint32_t w[4];
+    uint32_t c3 = (TAG_DECIMATE << 24) | (pair & 0xFFFFu);
+    if (!rng32) {
+        draw(seed, (uint32_t)h, n, slot_global, c3, w);
+        *r1 = hsgref_u01_52(w[0], w[1]);
+        *r2 = hsgref_u01_52(w[2], w[3]);
+    } else {
+        int quarter = N / 4;
+        int half = h / quarter;
+        draw(seed, (uint32_t)(h % quarter), n, slot_global, c3, w);
+        *r1 = hsgref_u01_24(w[2 * half]);
+        *r2 = hsgref_u01_24(w[2 * half + 1]);
+    }
+}
+
+/* Heat-bath draw of every site of parity d at beta (fields from the other    */
+/* sublattice, which stays fixed).                                            */
+static void reinsert(int L, const double* J, double* s, int d, double beta, uint64_t seed,
+                     uint32_t slot_global, uint32_t n, uint32_t pair, int rng32)
+{
+    int N = L * L * L, z;
+    for (z = 0; z < N; ++z) {
+        double S[3], r1, r2;
+        if (hsgref_parity(L, z) != d) continue;
+        hsgref_local_field(L, J, s, z, S);
+        hsgref_decimate_uniforms(L, rng32, seed, slot_global, n, pair, z, &r1, &r2);
+        hsgref_heatbath_spin(S, beta, r1, r2, s + (size_t)z * 3);
+    }
+}
+
+int hsgref_decimate_role(uint64_t seed, uint32_t chain_global, uint32_t n)
+{
+    uint32_t w[4];
+    draw(seed, 0u, n, chain_global, TAG_DECIMATE_ROLE << 24, w);
+    return (int)(w[0] & 1u);
+}
+
+void hsgref_decimate_batch(int L, int S, int C, int R, const double* J, double* spins,
+                           const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
+                           uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
+                           int64_t* rt_trips, uint32_t slot_base, uint32_t chain_base,
+                           uint64_t seed, int pairing, int rng32, double* log_ratio_out,
+                           int32_t* role_out)
+{
+    int N = L * L * L;
+    int ch, n_chain = S * C;
+    size_t rep = (size_t)N * 3;
+    for (ch = 0; ch < n_chain; ++ch) {
+        int smp = ch / C, i;
+        const double* Js = J + (size_t)smp * rep;
+        int32_t* tos = temp_of_slot + (size_t)ch * R;
+        int32_t* sot = slot_of_temp + (size_t)ch * R;
+        int64_t* st = stats + (size_t)ch * (R - 1) * 2;
+        uint32_t cg = chain_base + (uint32_t)ch;
+        uint32_t n = swap_ctr[ch];
+        int d0 = hsgref_decimate_role(seed, cg, n);
+        for (i = 0; i < R - 1; ++i) {
+            uint32_t w[4];
+            double u, lnA;
+            int x, y, d;
+            size_t gx, gy;
+            if (log_ratio_out) log_ratio_out[(size_t)ch * (R - 1) + i] = 0.0;
+            if (role_out) role_out[(size_t)ch * (R - 1) + i] = -1;
+            if (!pair_selected(i, pairing)) continue;
+            d = (d0 + i) & 1;
+            x = sot[i];
+            y = sot[i + 1];
+            gx = (size_t)ch * R + (size_t)x;
+            gy = (size_t)ch * R + (size_t)y;
+            lnA = hsgref_decimated_log_ratio(L, Js, spins + gx * rep, spins + gy * rep, d,
+                                             betas[i], betas[i + 1]);
+            if (log_ratio_out) log_ratio_out[(size_t)ch * (R - 1) + i] = lnA;
+            if (role_out) role_out[(size_t)ch * (R - 1) + i] = d;
+            draw(seed, (uint32_t)i, n, cg, TAG_SWAP << 24, w);
+            u = hsgref_u01_52(w[0], w[1]);
+            st[2 * i] += 1;
+            if (log(u) < lnA) {
+                reinsert(L, Js, spins + gx * rep, d, betas[i + 1], seed, slot_base + (uint32_t)gx,
+                         n, (uint32_t)i, rng32);
+                reinsert(L, Js, spins + gy * rep, d, betas[i], seed, slot_base + (uint32_t)gy,
+                         n, (uint32_t)i, rng32);
+                energy[gx] = hsgref_energy(L, Js, spins + gx * rep);
+                energy[gy] = hsgref_energy(L, Js, spins + gy * rep);
+                relabel(tos, sot, i);
+                st[2 * i + 1] += 1;
+            }
+        }
+        swap_ctr[ch] = n + 1;
+        hsgref_roundtrip_update(R, tos, rt_state + (size_t)ch * R, rt_trips + (size_t)ch * R);
+    }
 }
 
 /* ------------------------------------------------------------------------- */

@@ -72,6 +72,18 @@ void hsgref_anneal_batch(int L, int S, int C, int R, const double* J, double* sp
                          uint32_t slot_base, uint32_t chain_base, uint64_t seed, int parity,
                          const int32_t* K, const double* lambda, int K_max, int n_hb, int n_or,
                          int rng32, double* work_out);
+double hsgref_log_sinhc(double u);
+double hsgref_decimated_log_ratio(int L, const double* J, const double* sx, const double* sy,
+                                  int d, double b1, double b2);
+void hsgref_decimate_uniforms(int L, int rng32, uint64_t seed, uint32_t slot_global, uint32_t n,
+                              uint32_t pair, int x, double* r1, double* r2);
+int hsgref_decimate_role(uint64_t seed, uint32_t chain_global, uint32_t n);
+void hsgref_decimate_batch(int L, int S, int C, int R, const double* J, double* spins,
+                           const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
+                           uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
+                           int64_t* rt_trips, uint32_t slot_base, uint32_t chain_base,
+                           uint64_t seed, int pairing, int rng32, double* log_ratio_out,
+                           int32_t* role_out);
 void hsgref_measure_batch(int L, int S, int C, int R, const double* spins, const double* energy,
                           const int32_t* slot_of_temp, double* Q, double* chi, double* e);
 void hsgref_roundtrip_update(int R, const int32_t* temp_of_slot, int32_t* rt_state,

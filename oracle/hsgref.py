@@ -67,6 +67,14 @@ def lib():
                                            _i32p, _u32p, _u32p, _dp, _i64p, _i32p, _i64p, _c_u32,
                                            _c_u32, _c_u64, _c_int, _i32p, _dp, _c_int, _c_int,
                                            _c_int, _c_int, _dp]),
+            "hsgref_log_sinhc": (_c_dbl, [_c_dbl]),
+            "hsgref_decimated_log_ratio": (_c_dbl, [_c_int, _dp, _dp, _dp, _c_int, _c_dbl, _c_dbl]),
+            "hsgref_decimate_uniforms": (None, [_c_int, _c_int, _c_u64, _c_u32, _c_u32, _c_u32,
+                                                _c_int, _dp, _dp]),
+            "hsgref_decimate_role": (_c_int, [_c_u64, _c_u32, _c_u32]),
+            "hsgref_decimate_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _dp, _i32p,
+                                             _i32p, _u32p, _dp, _i64p, _i32p, _i64p, _c_u32,
+                                             _c_u32, _c_u64, _c_int, _c_int, _dp, _i32p]),
             "hsgref_measure_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _i32p, _dp,
                                             _dp, _dp]),
             "hsgref_roundtrip_update": (None, [_c_int, _i32p, _i32p, _i64p]),
@@ -209,6 +217,32 @@ def sweep(L, J, s, n_hb, n_or, beta, seed, slot_global, t, adjoint=False, rng32=
                        slot_global, t, int(rng32))
 
 
+def log_sinhc(u):
+    """h(u) = ln(sinh(u)/u), h(0) = 0."""
+    return lib().hsgref_log_sinhc(float(u))
+
+
+def decimated_log_ratio(L, J, sx, sy, d, b1, b2):
+    """ln A of the decimated exchange (paper Eq. (eq:aswap)): x at b1, y at b2, parity d
+    integrated out."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    sx = np.ascontiguousarray(sx, dtype=np.float64)
+    sy = np.ascontiguousarray(sy, dtype=np.float64)
+    return lib().hsgref_decimated_log_ratio(L, dp(J), dp(sx), dp(sy), int(d), float(b1), float(b2))
+
+
+def decimate_uniforms(L, rng32, seed, slot_global, n, pair, x):
+    r1 = ctypes.c_double()
+    r2 = ctypes.c_double()
+    lib().hsgref_decimate_uniforms(L, int(rng32), seed, slot_global, n, pair, x,
+                                   ctypes.byref(r1), ctypes.byref(r2))
+    return r1.value, r2.value
+
+
+def decimate_role(seed, chain_global, n):
+    return lib().hsgref_decimate_role(seed, chain_global, n)
+
+
 def geometric_betas(bmin, bmax, R):
     """beta_r = bmin (bmax/bmin)^(r/(R-1)), ascending (the paper's ladder family, Sec. IV)."""
     r = np.arange(R, dtype=np.float64)
@@ -306,6 +340,20 @@ class RefEnsemble:
                                   self.slot_base, self.chain_base, self.seed, int(parity),
                                   i32p(Kv), lp, K_max, n_hb, n_or, int(self.rng32), dp(work))
         return work
+
+    def decimate_swap(self, pairing=0):
+        """Decimated exchange (paper Sec. III.A) of the selected pairs (pairing as in swap).
+        Returns ln A [S][C][R-1] (0 where not attempted) and the decimated parity
+        [S][C][R-1] (-1 where not attempted)."""
+        lnA = np.zeros((self.S, self.C, self.R - 1))
+        role = np.zeros((self.S, self.C, self.R - 1), dtype=np.int32)
+        lib().hsgref_decimate_batch(self.L, self.S, self.C, self.R, dp(self.J), dp(self.spins),
+                                    dp(self.betas), i32p(self.temp_of_slot),
+                                    i32p(self.slot_of_temp), u32p(self.swap_ctr), dp(self.energy),
+                                    i64p(self.stats), i32p(self.rt_state), i64p(self.rt_trips),
+                                    self.slot_base, self.chain_base, self.seed, int(pairing),
+                                    int(self.rng32), dp(lnA), i32p(role))
+        return lnA, role
 
     def measure(self):
         Q = np.zeros((self.S, self.R, 3, 3))

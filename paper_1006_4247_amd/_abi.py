@@ -52,6 +52,7 @@ SIGNATURES = {
     "hsg_energy": (_i, [_E, _i, _vp, _vp]),
     "hsg_swap": (_i, [_E, _i, _i, _vp]),
     "hsg_anneal_swap": (_i, [_E, _i, _i, _i, _i, _vp]),
+    "hsg_decimate_swap": (_i, [_E, _i, _i, _vp]),
     "hsg_measure": (_i, [_E, _i, _vp]),
     "hsg_check": (_i, [_E, _i, _vp]),
     "hsg_mlp_forward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp]),

@@ -226,6 +226,23 @@ hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n
     return ok();
 }
 
+hsg_status hsg_decimate_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* stream) {
+    if (pairing < 0 || pairing > 2) return fail(HSG_ERR_INVALID, "pairing must be 0, 1 or 2 (got %d)", pairing);
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        if (ens[i].n_temps > 65536)
+            return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: n_temps > 65536", i);
+        if (ens[i].work && !aligned(ens[i].work, 8))
+            return fail(HSG_ERR_INVALID, "ensemble %d: work must be 8-byte aligned", i);
+    }
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_decimate(ens[i], pairing, as_stream(stream));
+        if (err != hipSuccess) return device(err, "decimated exchange");
+    }
+    return ok();
+}
+
 hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream) {
     hsg_status s = check_all(ens, n_ens, kState | kMeasure);
     if (s != HSG_OK) return s;

@@ -1,0 +1,244 @@
+// Decimated replica exchange (paper Sec. III.A).
+//
+// The spins of one sublattice D do not interact, so integrating them out of
+// exp(-beta H) leaves one factor I(beta S_z) = 4 pi sinh(R_z)/R_z per z in D
+// (Eq. (HI)), R_z = beta |S_z| with S_z the local field of the kept sublattice.
+// Exchanging the kept fields of x (at beta_1) and y (at beta_2) is accepted with
+// Eq. (eq:aswap),
+//     ln A = sum_{z in D} h(b2 a_z) - h(b1 a_z) + h(b1 c_z) - h(b2 c_z),
+// h(u) = ln(sinh(u)/u), a_z = |S_z(x)|, c_z = |S_z(y)| (the 4 pi and 1/R factors
+// cancel).  An accepted pair exchanges temperature labels and draws the D spins
+// of both configurations anew by heat-bath at their new temperatures; a
+// rejected pair changes nothing.  The first pair decimates a random sublattice
+// d_0 and the role alternates along the ladder, D_i = (d_0 + i) mod 2.
+//
+// Ascending order over all pairs (pairing 0) is sequential within a chain: one
+// workgroup per chain walks the pairs.  The even or odd pairs (pairing 1, 2) are
+// disjoint: one workgroup per pair.  Fields and ln A terms are per site, ln A and
+// the energies are deterministic FP64 block sums; one lane decides.
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace hsg {
+
+constexpr uint32_t kTagDecimate = 5u;      // heat-bath re-insertion draws
+constexpr uint32_t kTagDecimateRole = 6u;  // sublattice of the first pair
+constexpr int kDecThreads = 256;
+
+// h(u) = ln(sinh(u)/u) = u + ln((1 - e^{-2u})/(2u)), finite for all u >= 0.
+__device__ __forceinline__ double log_sinhc(double u) {
+    if (!(u > 0.0)) return 0.0;
+    return u + log(-expm1(-2.0 * u) / (2.0 * u));
+}
+
+// Local field of site h (sublattice p) from the other sublattice, in the order
+// +x, -x, +y, -y, +z, -z; the bond to -mu is stored at the neighbour.
+template <typename T>
+__device__ __forceinline__ void field(const T* __restrict__ s, const T* __restrict__ J, int NH,
+                                      int h, int p, const Nbr& nb, T& Sx, T& Sy, T& Sz) {
+    const T* o0 = s + (0 * 2 + (1 - p)) * NH;
+    const T* o1 = s + (1 * 2 + (1 - p)) * NH;
+    const T* o2 = s + (2 * 2 + (1 - p)) * NH;
+    Sx = T(0);
+    Sy = T(0);
+    Sz = T(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int mu = d >> 1;
+        const T jj = (d & 1) ? J[(mu * 2 + (1 - p)) * NH + nb.n[d]] : J[(mu * 2 + p) * NH + h];
+        const int idx = nb.n[d];
+        Sx = fma(jj, o0[idx], Sx);
+        Sy = fma(jj, o1[idx], Sy);
+        Sz = fma(jj, o2[idx], Sz);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double norm3(T x, T y, T z) {
+    const double a = x, b = y, c = z;
+    return sqrt(fma(c, c, fma(b, b, a * a)));
+}
+
+// Heat-bath of site h of configuration s (sublattice p) at beta with the given
+// uniforms; returns s_new . S for the energy.
+template <typename T>
+__device__ __forceinline__ double reinsert_site(T* __restrict__ s, const T* __restrict__ J, int NH,
+                                               int h, int p, const Nbr& nb, T beta, T r1, T r2) {
+    T Sx, Sy, Sz, ox, oy, oz;
+    field<T>(s, J, NH, h, p, nb, Sx, Sy, Sz);
+    heatbath<T>(Sx, Sy, Sz, beta, r1, r2, ox, oy, oz);
+    T* w0 = s + (0 * 2 + p) * NH;
+    T* w1 = s + (1 * 2 + p) * NH;
+    T* w2 = s + (2 * 2 + p) * NH;
+    w0[h] = ox;
+    w1[h] = oy;
+    w2[h] = oz;
+    const double dx = ox, dy = oy, dz = oz;
+    return fma(dz, static_cast<double>(Sz), fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pairing) {
+    __shared__ double red[kDecThreads / 64];
+    __shared__ int s_acc;
+    const int L = e.L, N = L * L * L, NH = N / 2, NQ = N / 4;
+    const int R = e.n_temps, C = e.n_chains;
+    int ch, i_begin, i_end, i_step;
+    if (pairing == 0) {
+        ch = blockIdx.x;
+        i_begin = 0;
+        i_end = R - 1;
+        i_step = 1;
+    } else {
+        const int first = pairing == 1 ? 0 : 1;
+        const int n_sel = (R - 1 - first + 1) / 2;
+        ch = blockIdx.x / n_sel;
+        i_begin = first + 2 * (blockIdx.x % n_sel);
+        i_end = i_begin + 1;
+        i_step = 1;
+    }
+    const int smp = ch / C;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int d0 = static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u);
+
+    for (int i = i_begin; i < i_end; i += i_step) {
+        const int d = (d0 + i) & 1;
+        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+        const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
+        T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
+        T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
+        const double b1 = e.betas[i], b2 = e.betas[i + 1];
+
+        double acc = 0.0;
+        for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+            const Nbr nb = neighbours<0>(h, d, L);
+            T ax, ay, az, cx, cy, cz;
+            field<T>(sx, J, NH, h, d, nb, ax, ay, az);
+            field<T>(sy, J, NH, h, d, nb, cx, cy, cz);
+            const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
+            acc += (log_sinhc(b2 * a) - log_sinhc(b1 * a)) + (log_sinhc(b1 * c) - log_sinhc(b2 * c));
+        }
+        const double lnA = block_sum<kDecThreads>(acc, red);
+        if (threadIdx.x == 0) {
+            if (e.work) {
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = static_cast<double>(d);
+            }
+            if (!isfinite(lnA)) atomicOr(e.guard, 1);
+            const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, k0, k1);
+            const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
+            st[2 * i] += 1;
+            if (ok) {
+                sot[i] = y;
+                sot[i + 1] = x;
+                tos[x] = i + 1;
+                tos[y] = i;
+                st[2 * i + 1] += 1;
+            }
+            s_acc = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (s_acc) {
+            // x goes to beta_2, y to beta_1; the kept sublattice is unchanged
+            const uint32_t c3 = (kTagDecimate << 24) | (static_cast<uint32_t>(i) & 0xFFFFu);
+            const T tb2 = static_cast<T>(b2), tb1 = static_cast<T>(b1);
+            double ex = 0.0, ey = 0.0;
+            if (sizeof(T) == 4) {
+                for (int q = threadIdx.x; q < NQ; q += kDecThreads) {
+                    const Words wx = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
+                    const Words wy = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int h = q + half * NQ;
+                        const Nbr nb = neighbours<0>(h, d, L);
+                        ex += reinsert_site<T>(sx, J, NH, h, d, nb, tb2,
+                                               static_cast<T>(u01_23(half ? wx.w2 : wx.w0)),
+                                               static_cast<T>(u01_23(half ? wx.w3 : wx.w1)));
+                        ey += reinsert_site<T>(sy, J, NH, h, d, nb, tb1,
+                                               static_cast<T>(u01_23(half ? wy.w2 : wy.w0)),
+                                               static_cast<T>(u01_23(half ? wy.w3 : wy.w1)));
+                    }
+                }
+            } else {
+                for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+                    const Nbr nb = neighbours<0>(h, d, L);
+                    const Words wx = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
+                    const Words wy = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
+                    ex += reinsert_site<T>(sx, J, NH, h, d, nb, tb2, static_cast<T>(u01_52(wx.w0, wx.w1)),
+                                           static_cast<T>(u01_52(wx.w2, wx.w3)));
+                    ey += reinsert_site<T>(sy, J, NH, h, d, nb, tb1, static_cast<T>(u01_52(wy.w0, wy.w1)),
+                                           static_cast<T>(u01_52(wy.w2, wy.w3)));
+                }
+            }
+            const double Hx = -block_sum<kDecThreads>(ex, red);
+            const double Hy = -block_sum<kDecThreads>(ey, red);
+            if (threadIdx.x == 0) {
+                e.energy[gx] = Hx;
+                e.energy[gy] = Hy;
+                if (!isfinite(Hx) || !isfinite(Hy)) atomicOr(e.guard, 1);
+            }
+        }
+        __syncthreads();  // spins, labels and energies of this pair are visible to the next
+    }
+}
+
+// Per chain, after every pair: advance the exchange counter, update round trips
+// and clear the diagnostics of the pairs not attempted.
+__global__ void k_decimate_finish(hsg_ensemble e, int pairing) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_chains) return;
+    const int R = e.n_temps;
+    if (e.work) {
+        for (int i = 0; i < R - 1; ++i) {
+            const bool sel = pairing == 0 || (pairing == 1 ? (i % 2) == 0 : (i % 2) == 1);
+            if (!sel) {
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = 0.0;
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = -1.0;
+            }
+        }
+    }
+    e.swap_ctr[ch] += 1u;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
+    for (int r = 0; r < R; ++r) {
+        const int T = tos[r];
+        if (T == 0) {
+            if (rs[r] == 2) rtt[r] += 1;
+            rs[r] = 1;
+        } else if (T == R - 1) {
+            if (rs[r] == 1) rs[r] = 2;
+        }
+    }
+}
+
+hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
+    const int chains = e.n_samples * e.n_chains;
+    const int R = e.n_temps;
+    if (chains <= 0 || R < 2) return hipSuccess;
+    int blocks = chains;
+    if (pairing != 0) {
+        const int first = pairing == 1 ? 0 : 1;
+        const int n_sel = (R - 1 - first + 1) / 2;
+        blocks = chains * n_sel;
+    }
+    if (blocks > 0) {
+        if (e.precision == HSG_FP64)
+            hipLaunchKernelGGL(k_decimate<double>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
+        else
+            hipLaunchKernelGGL(k_decimate<float>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing);
+    return hipGetLastError();
+}
+
+}  // namespace hsg

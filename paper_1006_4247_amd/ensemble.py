@@ -184,6 +184,14 @@ class Ensemble:
         _abi.check(_abi.lib().hsg_anneal_swap(ctypes.byref(self.desc), 1, int(parity), n_hb, n_or,
                                               self._stream()))
 
+    def decimate_swap(self, pairing=0):
+        """Decimated exchange (paper Sec. III.A) of the selected pairs; afterwards
+        work[..., i, 0] holds ln A and work[..., i, 1] the decimated sublattice of pair i
+        (0 and -1 where not attempted)."""
+        _abi.check(_abi.lib().hsg_decimate_swap(ctypes.byref(self.desc), 1, int(pairing),
+                                                self._stream()))
+        return self.work
+
     def measure(self):
         _abi.check(_abi.lib().hsg_measure(ctypes.byref(self.desc), 1, self._stream()))
         return self.Q, self.chi, self.e_temp

@@ -1,0 +1,227 @@
+"""Decimated exchange (paper Sec. III.A) on the GPU against the oracle.
+
+FP64: ln A of every pair to 1e-10 (relative), the decimated sublattice, decisions,
+labels, counters and statistics bit for bit, spins to 1e-12, over several calls in
+all three pair orders.
+
+FP32 (spins and fields in binary32, ln A in binary64): ln A of every pair within the
+rigorous bound of the field rounding, |d ln A| <= 2 sqrt(3) gamma_6 max(beta) sum_b |J_b|
+(gamma_6 = 6u/(1-6u), u = 2^-24: six fused multiply-adds per field component; |h'| < 1
+for h(u) = ln(sinh(u)/u); every bond has one end on the decimated sublattice).  A
+decision is compared where |ln A - ln u| exceeds that bound; with disjoint pairs each
+pair is then checked on its own: labels, statistics, the kept sublattice bit for bit
+and the re-inserted spins within the lattice-sweep bar.
+
+At the full L = 16, 64 x 2 x 24 shape the sampled pairs are recomputed by the oracle
+from the GPU's own state before the call.  On the open-chain forest the exact law is
+stationary under the GPU's decimated exchanges (closed forms).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1006_4247_amd as hsg
+from oracle import hsgref
+from tests import closed_forms as cf
+from tests import inputs
+from tests.gpu_pair import LATTICE_BAR, compare_ints, make_pair
+
+pytestmark = pytest.mark.gpu
+SEED = 0xDEC1
+GAMMA6 = 6 * 2.0 ** -24 / (1 - 6 * 2.0 ** -24)
+
+
+def _betas(R, lo=0.5, hi=3.0):
+    return hsgref.geometric_betas(lo, hi, R)
+
+
+def _log_u(ref, ch, i, n):
+    w = hsgref.philox([i, n, ref.chain_base + ch, 4 << 24], [ref.seed & 0xFFFFFFFF, ref.seed >> 32])
+    return np.log(hsgref.u01_52(int(w[0]), int(w[1])))
+
+
+def _lnA_bound(ref):
+    """[S] bound on |ln A_gpu - ln A_ref| for FP32 fields (see the module docstring)."""
+    sumJ = np.abs(ref.J).sum(axis=(1, 2))
+    return 2.0 * np.sqrt(3.0) * GAMMA6 * ref.betas.max() * sumJ + 1e-11 * ref.N
+
+
+@pytest.mark.parametrize("L", [4, 6, 16])
+@pytest.mark.parametrize("pairing", [0, 1, 2])
+def test_decimate_parity_fp64(L, pairing):
+    S, C, R = 2, 2, 6
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 10 * L + pairing, prec="fp64")
+    for call in range(3):
+        w = gpu.decimate_swap(pairing)
+        lnA, role = ref.decimate_swap(pairing)
+        torch.cuda.synchronize()
+        wg = w.cpu().numpy()
+        what = "decimate fp64 L=%d pairing %d call %d" % (L, pairing, call)
+        assert np.array_equal(wg[..., 1].astype(np.int32), role), what
+        assert np.max(np.abs(wg[..., 0] - lnA)) <= 1e-10 * max(1.0, np.abs(lnA).max()), what
+        st = compare_ints(gpu, ref, what)
+        assert np.max(np.abs(st["spins"] - ref.spins)) <= 1e-12, what
+        assert np.max(np.abs(st["energy"] - ref.energy)) <= 1e-9, what
+    acc = ref.stats[..., 1].sum()
+    assert 0 < acc < ref.stats[..., 0].sum()
+    gpu.check()
+
+
+@pytest.mark.parametrize("L", [4, 8, 16])
+@pytest.mark.parametrize("pairing", [1, 2])
+def test_decimate_parity_fp32(L, pairing):
+    S, C, R = 2, 3, 7
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 100 + L + pairing, prec="fp32")
+    before = ref.spins.copy()
+    sot = ref.slot_of_temp.copy()
+    n0 = ref.swap_ctr.copy()
+    w = gpu.decimate_swap(pairing)
+    lnA, role = ref.decimate_swap(pairing)
+    torch.cuda.synchronize()
+    wg = w.cpu().numpy()
+    assert np.array_equal(wg[..., 1].astype(np.int32), role)
+    bound = _lnA_bound(ref)
+    dl = np.abs(wg[..., 0] - lnA)
+    assert np.all(dl <= bound[:, None, None]), (dl.max(), bound)
+    st = gpu.host_state()
+    assert np.array_equal(st["swap_ctr"], ref.swap_ctr)
+    par = np.array([hsgref.parity(L, x) for x in range(L ** 3)])
+    checked = 0
+    for s in range(S):
+        for c in range(C):
+            ch = s * C + c
+            for i in range(R - 1):
+                if role[s, c, i] < 0:
+                    continue
+                if abs(lnA[s, c, i] - _log_u(ref, ch, i, int(n0[s, c]))) <= bound[s]:
+                    continue  # ambiguous in binary32: either decision is correct
+                checked += 1
+                x, y = sot[s, c, i], sot[s, c, i + 1]
+                assert np.array_equal(st["stats"][s, c, i], ref.stats[s, c, i])
+                for slot in (x, y):
+                    assert st["temp_of_slot"][s, c, slot] == ref.temp_of_slot[s, c, slot]
+                    keep = par != role[s, c, i]
+                    g, r_ = st["spins"][s, c, slot], ref.spins[s, c, slot]
+                    assert np.array_equal(g[keep], before[s, c, slot][keep])
+                    d = np.abs(g - r_).max()
+                    if d > LATTICE_BAR["fp32"]:
+                        # only sites whose field is ill-conditioned may exceed the bar
+                        for z in np.flatnonzero(np.abs(g - r_).max(axis=-1) > LATTICE_BAR["fp32"]):
+                            Sz = hsgref.local_field(L, ref.J[s], before[s, c, slot], z)
+                            nz = np.linalg.norm(Sz)
+                            assert nz < 0.1 or abs(Sz[2]) < 1e-4 * nz, (s, c, slot, z, d)
+    assert checked >= S * C * len(range(pairing - 1, R - 1, 2)) // 2
+    assert ref.stats[..., 1].sum() > 0
+    gpu.check()
+
+
+def test_decimate_no_selected_pair_only_advances_counters():
+    gpu, ref = make_pair(4, 2, 2, _betas(2), SEED + 7, prec="fp64")
+    gpu.decimate_swap(2)
+    ref.decimate_swap(2)
+    torch.cuda.synchronize()
+    st = compare_ints(gpu, ref, "R=2 odd pairs")
+    assert np.array_equal(st["spins"], ref.spins)
+    assert np.all(st["swap_ctr"] == 1)
+
+
+def test_decimate_full_shape_sampled_pairs():
+    """L = 16, 64 samples x 2 chains x 24 temperatures (FP32): sampled pairs recomputed by
+    the oracle from the GPU's state before the call."""
+    L, S, C, R = 16, 64, 2, 24
+    betas = hsgref.geometric_betas(1.0, 8.0, R)
+    gpu = hsg.Ensemble(L, S, C, betas, 0x100642470002, precision="fp32")
+    gpu.init_couplings()
+    gpu.init_spins()
+    gpu.sweep(20, 1, 3)
+    torch.cuda.synchronize()
+    st0 = gpu.host_state()
+    J = gpu.couplings_natural()
+    w = gpu.decimate_swap(1)
+    torch.cuda.synchronize()
+    wg = w.cpu().numpy()
+    st = gpu.host_state()
+    rng = np.random.default_rng(3)
+    par = np.array([hsgref.parity(L, x) for x in range(L ** 3)])
+    bound = 2.0 * np.sqrt(3.0) * GAMMA6 * betas.max() * np.abs(J).sum(axis=(1, 2)) + 1e-11 * L ** 3
+    n_acc = 0
+    for k in range(8):
+        s, c = int(rng.integers(S)), int(rng.integers(C))
+        i = 2 * int(rng.integers((R - 1 + 1) // 2))
+        x, y = st0["slot_of_temp"][s, c, i], st0["slot_of_temp"][s, c, i + 1]
+        d = int(wg[s, c, i, 1])
+        assert d in (0, 1)
+        sx = st0["spins"][s, c, x].astype(np.float64)
+        sy = st0["spins"][s, c, y].astype(np.float64)
+        ref_lnA = hsgref.decimated_log_ratio(L, J[s], sx, sy, d, betas[i], betas[i + 1])
+        assert abs(wg[s, c, i, 0] - ref_lnA) <= bound[s], (k, wg[s, c, i, 0], ref_lnA)
+        accepted = st["stats"][s, c, i, 1] - st0["stats"][s, c, i, 1]
+        for slot in (x, y):
+            old = st0["spins"][s, c, slot]
+            new = st["spins"][s, c, slot]
+            if accepted:
+                assert np.array_equal(new[par != d], old[par != d])
+            else:
+                assert np.array_equal(new, old)
+        n_acc += int(accepted)
+        # the decision follows ln u < ln A wherever binary32 cannot change it
+        lu = np.log(hsgref.u01_52(*[int(v) for v in hsgref.philox(
+            [i, int(st0["swap_ctr"][s, c]), s * C + c, 4 << 24],
+            [0x100642470002 & 0xFFFFFFFF, 0x100642470002 >> 32])[:2]]))
+        if abs(ref_lnA - lu) > bound[s]:
+            assert bool(accepted) == bool(lu < ref_lnA)
+    assert np.all(st["swap_ctr"] == st0["swap_ctr"] + 1)
+    gpu.check()
+
+
+def _exact_forest(L, J, beta, rng):
+    N = L ** 3
+    s = np.zeros((N, 3))
+    for row in range(L * L):
+        x0 = row * L
+        v = rng.normal(size=3)
+        s[x0] = v / np.linalg.norm(v)
+        for i in range(1, L):
+            x = x0 + i
+            a = beta * J[x - 1, 0]
+            n = s[x - 1] * np.sign(a)
+            R = abs(a)
+            r = rng.uniform()
+            cth = 1.0 + np.log(r + (1.0 - r) * np.exp(-2.0 * R)) / R
+            cth = min(1.0, max(-1.0, cth))
+            t = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+            e1 = np.cross(n, t)
+            e1 /= np.linalg.norm(e1)
+            e2 = np.cross(n, e1)
+            ph = 2.0 * np.pi * rng.uniform()
+            s[x] = cth * n + np.sqrt(max(0.0, 1.0 - cth * cth)) * (np.cos(ph) * e1 + np.sin(ph) * e2)
+    return s
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forest_law_stationary_under_gpu_decimation(prec):
+    L, C = 4, 256
+    betas = np.array([0.5, 1.0, 2.0, 4.0])
+    R = len(betas)
+    rng = np.random.default_rng(91)
+    J = inputs.forest_couplings(L, 1, 92)[0]
+    spins = np.zeros((1, C, R, L ** 3, 3))
+    for c in range(C):
+        for r in range(R):
+            spins[0, c, r] = _exact_forest(L, J, betas[r], rng)
+    gpu, _ = make_pair(L, 1, C, betas, 0xF0E, prec=prec, J=J[None], spins=spins)
+    for t in range(100):
+        gpu.decimate_swap(t % 3)
+    torch.cuda.synchronize()
+    st = gpu.host_state()
+    acc = st["stats"][..., 1].sum() / st["stats"][..., 0].sum()
+    assert acc > 0.2
+    Jb = np.array([b[2] for b in cf.forest_bonds(L, J)])
+    for r in range(R):
+        H = np.array([st["energy"][0, c, st["slot_of_temp"][0, c, r]] for c in range(C)])
+        mean, var = cf.forest_mean_H(betas[r], Jb), cf.forest_var_H(betas[r], Jb)
+        z = (H.mean() - mean) / np.sqrt(var / C)
+        assert abs(z) < 4.0, (r, H.mean(), mean, z)
+        zv = (H.var(ddof=1) - var) / (var * np.sqrt(2.0 / (C - 1)))
+        assert abs(zv) < 4.5, (r, H.var(ddof=1), var, zv)
+    gpu.check()
