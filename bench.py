@@ -89,8 +89,10 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     the workload's lattice and beta range: plain PT on a ladder dense enough for
     acceptance ~0.1 versus annealed exchanges on the workload's own ladder with (a) one
     protocol length for every pair, chosen for acceptance ~0.1, and (b) the learned
-    per-pair schedule.  Steps are replayed from a HIP graph; the learner's data
-    generation and training are timed separately."""
+    per-pair schedule; and the decimated exchange (paper Sec. III.A) on the dense ladder
+    (acceptance against plain PT at equal spacing) and on the workload's own ladder.
+    Steps are replayed from a HIP graph; the learner's data generation and training are
+    timed separately."""
     from paper_1006_4247_amd import runtime
     from paper_1006_4247_amd import schedule as sch
 
@@ -124,7 +126,8 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
         return {"temperatures": e.R, "steps": n, "gpu_s": round(dt, 3), "ms_per_step": round(dt / n * 1e3, 4),
                 "acceptance_min": round(float(acc.min()), 4), "acceptance_mean": round(float(acc.mean()), 4),
                 "accepted_swaps_per_gpu_s": round(float(st[..., 1].sum()) / dt, 1),
-                "round_trips": int(rt.sum()), "round_trips_per_gpu_s": round(float(rt.sum()) / dt, 2)}
+                "round_trips": int(rt.sum()), "round_trips_per_gpu_s": round(float(rt.sum()) / dt, 2),
+                "_acc": acc}
 
     out = {"lattice": "L=%d, %d samples x %d chains, beta %.1f..%.1f" % (L, S, C, bmin, bmax)}
     out["plain_dense_ladder"] = timed(make(R_dense), "plain", steps_plain)
@@ -150,8 +153,18 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     r = timed(e, "anneal", steps_anneal)
     r.update({"K": [int(k) for k in K], "learner_s": round(learn_s, 2), "train_mse": round(loss, 5)})
     out["annealed_learned"] = r
+    # decimated exchange (paper Sec. III.A), even / odd pairs alternating
+    out["decimated_dense_ladder"] = timed(make(R_dense), "decimate", steps_plain)
+    out["decimated_own_ladder"] = timed(make(R0), "decimate", steps_anneal)
     base = out["plain_dense_ladder"]
-    for k in ("annealed_uniform_K", "annealed_learned"):
+    ratio = out["decimated_dense_ladder"]["_acc"] / np.maximum(base["_acc"], 1e-12)
+    out["decimated_dense_ladder"]["acceptance_vs_plain_same_ladder"] = {
+        "min": round(float(ratio.min()), 3), "mean": round(float(ratio.mean()), 3),
+        "max": round(float(ratio.max()), 3)}
+    for v in out.values():
+        if isinstance(v, dict):
+            v.pop("_acc", None)
+    for k in ("annealed_uniform_K", "annealed_learned", "decimated_dense_ladder", "decimated_own_ladder"):
         out[k]["round_trips_per_gpu_s_vs_plain"] = round(
             out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12), 3)
         out[k]["accepted_swaps_per_gpu_s_vs_plain"] = round(

@@ -188,6 +188,165 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
     }
 }
 
+// ---------------------------------------------------------------- LDS-resident variant
+// Per pair, the kept sublattice of both configurations is staged into LDS with
+// 16-byte loads ([config][mu][NH]); neighbour offsets use the compile-time L and
+// every coupling is read once for both configurations.  Per site,
+//   h(b2 s) - h(b1 s) = (b2 - b1) s + ln[expm1(-2 b2 s) / expm1(-2 b1 s)] - ln(b2/b1),
+// and the ln(b2/b1) terms cancel between x and y, so the site contributes
+//   (b2 - b1)(a - c) + ln[rho(a) / rho(c)],  rho(s) = expm1(-2 b2 s) / expm1(-2 b1 s),
+// with one logarithm; rho -> b2/b1 as s -> 0 (its value at s = 0).
+__device__ __forceinline__ double dec_rho(double s, double b1, double b2) {
+    if (!(s > 0.0)) return b2 / b1;
+    return expm1(-2.0 * b2 * s) / expm1(-2.0 * b1 * s);
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimate_res(hsg_ensemble e, int pairing) {
+    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr int NVP = NH * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per plane
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* kept = reinterpret_cast<T*>(smem_raw);  // [2][3][NH]
+    __shared__ double red[kDecThreads / 64];
+    __shared__ int s_acc;
+    const int R = e.n_temps, C = e.n_chains;
+    int ch, i_begin, i_end;
+    if (pairing == 0) {
+        ch = blockIdx.x;
+        i_begin = 0;
+        i_end = R - 1;
+    } else {
+        const int first = pairing == 1 ? 0 : 1;
+        const int n_sel = (R - first) / 2;
+        ch = blockIdx.x / n_sel;
+        i_begin = first + 2 * (blockIdx.x % n_sel);
+        i_end = i_begin + 1;
+    }
+    const int smp = ch / C;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int d0 = static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u);
+
+    for (int i = i_begin; i < i_end; ++i) {
+        const int d = (d0 + i) & 1;
+        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+        const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
+        T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
+        T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
+        const double b1 = e.betas[i], b2 = e.betas[i + 1];
+        {
+            const uint4* srcx = reinterpret_cast<const uint4*>(sx);
+            const uint4* srcy = reinterpret_cast<const uint4*>(sy);
+            uint4* dst = reinterpret_cast<uint4*>(kept);
+            for (int v = threadIdx.x; v < 3 * NVP; v += kDecThreads) {
+                const int mu = v / NVP, r = v - mu * NVP;
+                const int src = (2 * mu + 1 - d) * NVP + r;
+                dst[v] = srcx[src];
+                dst[3 * NVP + v] = srcy[src];
+            }
+        }
+        __syncthreads();
+        double lin = 0.0, lg = 0.0;
+        for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+            const Nbr nb = neighbours<L>(h, d, L);
+            T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
+#pragma unroll
+            for (int dd = 0; dd < 6; ++dd) {
+                const int mu = dd >> 1;
+                const T jj = (dd & 1) ? J[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : J[(mu * 2 + d) * NH + h];
+                const int idx = nb.n[dd];
+                ax = fma(jj, kept[0 * NH + idx], ax);
+                ay = fma(jj, kept[1 * NH + idx], ay);
+                az = fma(jj, kept[2 * NH + idx], az);
+                cx = fma(jj, kept[3 * NH + idx], cx);
+                cy = fma(jj, kept[4 * NH + idx], cy);
+                cz = fma(jj, kept[5 * NH + idx], cz);
+            }
+            const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
+            lin += a - c;
+            lg += log(dec_rho(a, b1, b2) / dec_rho(c, b1, b2));
+        }
+        const double lnA = block_sum<kDecThreads>(fma(b2 - b1, lin, lg), red);
+        if (threadIdx.x == 0) {
+            if (e.work) {
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = static_cast<double>(d);
+            }
+            if (!isfinite(lnA)) atomicOr(e.guard, 1);
+            const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, k0, k1);
+            const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
+            st[2 * i] += 1;
+            if (ok) {
+                sot[i] = y;
+                sot[i + 1] = x;
+                tos[x] = i + 1;
+                tos[y] = i;
+                st[2 * i + 1] += 1;
+            }
+            s_acc = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (s_acc) {
+            const uint32_t c3 = (kTagDecimate << 24) | (static_cast<uint32_t>(i) & 0xFFFFu);
+            const T tb[2] = {static_cast<T>(b2), static_cast<T>(b1)};  // x -> beta_2, y -> beta_1
+            T* out[2] = {sx, sy};
+            const uint32_t gs[2] = {e.slot_base + static_cast<uint32_t>(gx), e.slot_base + static_cast<uint32_t>(gy)};
+            double en[2] = {0.0, 0.0};
+            constexpr int NSITE = (sizeof(T) == 4) ? NQ : NH;  // one Philox block per site pair (binary32) or site
+            for (int q = threadIdx.x; q < NSITE; q += kDecThreads) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const Words w = philox(static_cast<uint32_t>(q), n, gs[r], c3, k0, k1);
+#pragma unroll
+                    for (int half = 0; half < (sizeof(T) == 4 ? 2 : 1); ++half) {
+                        const int h = q + half * NQ;
+                        const Nbr nb = neighbours<L>(h, d, L);
+                        T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+                        for (int dd = 0; dd < 6; ++dd) {
+                            const int mu = dd >> 1;
+                            const T jj = (dd & 1) ? J[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : J[(mu * 2 + d) * NH + h];
+                            const int idx = nb.n[dd];
+                            Sx = fma(jj, kept[(3 * r + 0) * NH + idx], Sx);
+                            Sy = fma(jj, kept[(3 * r + 1) * NH + idx], Sy);
+                            Sz = fma(jj, kept[(3 * r + 2) * NH + idx], Sz);
+                        }
+                        T r1, r2;
+                        if (sizeof(T) == 4) {
+                            r1 = static_cast<T>(u01_23(half ? w.w2 : w.w0));
+                            r2 = static_cast<T>(u01_23(half ? w.w3 : w.w1));
+                        } else {
+                            r1 = static_cast<T>(u01_52(w.w0, w.w1));
+                            r2 = static_cast<T>(u01_52(w.w2, w.w3));
+                        }
+                        T ox, oy, oz;
+                        heatbath<T>(Sx, Sy, Sz, tb[r], r1, r2, ox, oy, oz);
+                        out[r][(0 * 2 + d) * NH + h] = ox;
+                        out[r][(1 * 2 + d) * NH + h] = oy;
+                        out[r][(2 * 2 + d) * NH + h] = oz;
+                        const double dx = ox, dy = oy, dz = oz;
+                        en[r] += fma(dz, static_cast<double>(Sz),
+                                     fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+                    }
+                }
+            }
+            const double Hx = -block_sum<kDecThreads>(en[0], red);
+            const double Hy = -block_sum<kDecThreads>(en[1], red);
+            if (threadIdx.x == 0) {
+                e.energy[gx] = Hx;
+                e.energy[gy] = Hy;
+                if (!isfinite(Hx) || !isfinite(Hy)) atomicOr(e.guard, 1);
+            }
+        }
+        __syncthreads();  // the next pair restages the LDS and may read these spins
+    }
+}
+
 // Per chain, after every pair: advance the exchange counter, update round trips
 // and clear the diagnostics of the pairs not attempted.
 __global__ void k_decimate_finish(hsg_ensemble e, int pairing) {
@@ -219,6 +378,39 @@ __global__ void k_decimate_finish(hsg_ensemble e, int pairing) {
     }
 }
 
+template <typename T, int L>
+static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+    constexpr size_t lds = 2 * 3 * (L * L * L / 2) * sizeof(T);
+    auto kern = k_decimate_res<T, L>;
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kDecThreads), lds, st, e, pairing);
+    return hipGetLastError();
+}
+
+// LDS-resident variant for L <= 16 (its two kept sublattices fit one workgroup's
+// LDS), the generic kernel otherwise.
+template <typename T>
+static hipError_t go_decimate(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+    switch (e.L) {
+        case 4: return go_decimate_res<T, 4>(e, pairing, blocks, st);
+        case 6: return go_decimate_res<T, 6>(e, pairing, blocks, st);
+        case 8: return go_decimate_res<T, 8>(e, pairing, blocks, st);
+        case 10: return go_decimate_res<T, 10>(e, pairing, blocks, st);
+        case 12: return go_decimate_res<T, 12>(e, pairing, blocks, st);
+        case 14: return go_decimate_res<T, 14>(e, pairing, blocks, st);
+        case 16: return go_decimate_res<T, 16>(e, pairing, blocks, st);
+        default:
+            hipLaunchKernelGGL(k_decimate<T>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
+            return hipGetLastError();
+    }
+}
+
 hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
     const int chains = e.n_samples * e.n_chains;
     const int R = e.n_temps;
@@ -230,11 +422,8 @@ hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
         blocks = chains * n_sel;
     }
     if (blocks > 0) {
-        if (e.precision == HSG_FP64)
-            hipLaunchKernelGGL(k_decimate<double>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
-        else
-            hipLaunchKernelGGL(k_decimate<float>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
-        hipError_t err = hipGetLastError();
+        hipError_t err = e.precision == HSG_FP64 ? go_decimate<double>(e, pairing, blocks, st)
+                                                 : go_decimate<float>(e, pairing, blocks, st);
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing);

@@ -16,10 +16,15 @@ from .ensemble import Ensemble
 class PTRun:
     """mode 'plain': exchange every step with `pairing` (0 = all pairs ascending);
     mode 'anneal': annealed exchange alternating even / odd pairs (schedules must be
-    set on the ensembles)."""
+    set on the ensembles); mode 'decimate': decimated exchange (paper Sec. III.A),
+    alternating even / odd pairs, or all pairs ascending every step if pairing == 0."""
 
-    def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=0, measure=True,
+    def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
                  series_len=0, tunings=None, anneal_sweep=None):
+        if mode not in ("plain", "anneal", "decimate"):
+            raise ValueError("mode must be 'plain', 'anneal' or 'decimate'")
+        if pairing is None:
+            pairing = 0 if mode == "plain" else -1
         if isinstance(ensembles, Ensemble):
             ensembles = [ensembles]
         self.ens = list(ensembles)
@@ -52,6 +57,8 @@ class PTRun:
         e.sweep(1, self.n_hb, self.n_or, tuning=self.tunings[i])
         if self.mode == "plain":
             e.swap(self.pairing)
+        elif self.mode == "decimate":
+            e.decimate_swap(self.pairing if self.pairing >= 0 else parity + 1)
         else:
             e.anneal_swap(parity, *self.anneal_sweep)
         if self.measure:
@@ -92,12 +99,13 @@ class PTRun:
 
     # ------------------------------------------------------------ graphs
     def capture(self, n_steps=None):
-        """Record n_steps steps (default: 1 for plain, 2 for annealed exchange, one per
-        parity) of every size class into one HIP graph.  Time series are not recorded
+        """Record n_steps steps (default: 1, or 2 where the exchange alternates between
+        even and odd pairs, one per parity) of every size class into one HIP graph.  Time series are not recorded
         inside graphs."""
         if self.series_len:
             raise RuntimeError("graph capture does not record time series (series_len must be 0)")
-        n_steps = n_steps or (1 if self.mode == "plain" else 2)
+        alternating = self.mode == "anneal" or (self.mode == "decimate" and self.pairing < 0)
+        n_steps = n_steps or (2 if alternating else 1)
         torch.cuda.synchronize(self.device)
         g = torch.cuda.CUDAGraph()
         cap = torch.cuda.Stream(device=self.device)

@@ -46,9 +46,10 @@ def _lnA_bound(ref):
     return 2.0 * np.sqrt(3.0) * GAMMA6 * ref.betas.max() * sumJ + 1e-11 * ref.N
 
 
-@pytest.mark.parametrize("L", [4, 6, 16])
+@pytest.mark.parametrize("L", [4, 6, 16, 20])
 @pytest.mark.parametrize("pairing", [0, 1, 2])
 def test_decimate_parity_fp64(L, pairing):
+    """L <= 16: LDS-resident kernel; L = 20: the generic kernel."""
     S, C, R = 2, 2, 6
     gpu, ref = make_pair(L, S, C, _betas(R), SEED + 10 * L + pairing, prec="fp64")
     for call in range(3):
@@ -67,7 +68,7 @@ def test_decimate_parity_fp64(L, pairing):
     gpu.check()
 
 
-@pytest.mark.parametrize("L", [4, 8, 16])
+@pytest.mark.parametrize("L", [4, 8, 16, 24])
 @pytest.mark.parametrize("pairing", [1, 2])
 def test_decimate_parity_fp32(L, pairing):
     S, C, R = 2, 3, 7
