@@ -51,12 +51,55 @@ def algorithmic_ops_per_update(n_hb, n_or, prec):
 
 
 def hbm_bytes_per_launch(w, n_sweeps=1):
-    """Algorithmic HBM bytes of one LDS-resident sweep launch: every replica read and
-    written once, the couplings of every sample read once."""
+    """Algorithmic HBM bytes of one LDS-resident sweep launch: every replica written
+    once and read once, where a sweep that opens with a heat-bath half-sweep needs only
+    the sublattice that half-sweep does not update (the other one is redrawn unread);
+    the couplings of every sample read once."""
     t = 4 if w["prec"] == "fp32" else 8
     N = w["L"] ** 3
     slots = w["S"] * w["C"] * w["R"]
-    return slots * 2 * 3 * N * t + w["S"] * 3 * N * t
+    read = 3 * (N // 2) * t if w["n_hb"] > 0 else 3 * N * t
+    return slots * (read + 3 * N * t) + w["S"] * 3 * N * t
+
+
+def resident_kernel_name(w):
+    """The LDS-resident sweep instance the library picks by default for this workload."""
+    nq = w["L"] ** 3 // 4
+    nt = min(1024, (nq + 63) // 64 * 64)
+    nt = 512 if nt >= 1024 else nt
+    return "k_resident<%s,%d,%d>" % ("float" if w["prec"] == "fp32" else "double", w["L"], nt)
+
+
+# Sources of the sweep kernel whose HBM traffic the counter summary records; the
+# summary is used only while they are unchanged.
+KERNEL_SOURCES = ["paper_1006_4247_amd/csrc/sweep_resident.hip", "paper_1006_4247_amd/csrc/hsg_device.h",
+                  "paper_1006_4247_amd/csrc/hsg_launch.h", "paper_1006_4247_amd/build.py"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in
+    profiles/ (each counter scaled by its reading on a plain copy of known size), or None
+    if the summary was taken on other kernel sources or for another workload."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_resident_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    digest = kernel_sources_sha256()
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if kv.get("workload") == workload and kv.get("sources_sha256") == digest:
+                    return int(kv["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(w, budget_s):
@@ -264,8 +307,9 @@ def main():
     alu_achieved = ops / avg_launch_s / 1e12
     hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
     roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "k_resident<float,16,512> (one sweep of every replica per launch)",
+                "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(args.workload),
+                "kernel": "%s (one sweep of every replica per launch)" % resident_kernel_name(w),
                 "avg_launch_ms": round(avg_launch_s * 1e3, 5),
                 "hbm_algorithmic_GBs": round(hbm_achieved, 1),
                 "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
