@@ -19,3 +19,14 @@ def block_var_err(x, n_blocks=20):
     jk = np.array([np.delete(blocks, i, axis=0).ravel().var() for i in range(n_blocks)])
     err = np.sqrt((n_blocks - 1) / n_blocks * np.sum((jk - jk.mean()) ** 2))
     return full, err
+
+
+def jackknife_mean_err(x, n_blocks=20):
+    """Mean of a time series and its block-jackknife error: the n_blocks leave-one-block-out
+    means m_k give err^2 = (n-1)/n sum_k (m_k - mean(m))^2."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x) // n_blocks * n_blocks
+    b = x[:n].reshape(n_blocks, -1).mean(axis=1)
+    loo = (b.sum() - b) / (n_blocks - 1)
+    err = np.sqrt((n_blocks - 1) / n_blocks * np.sum((loo - loo.mean()) ** 2))
+    return float(b.mean()), float(err)

@@ -6,7 +6,7 @@
 * Long runs at the shape of the small FP64 workload (L = 4, 2 chains, 8 temperatures,
   beta geometric 1..6, 1 HB + 3 OR + exchange every step): per-temperature energy
   density and overlap susceptibility of the GPU agree with the oracle's (different
-  random streams, same couplings) within 4 sigma of the blocked errors.
+  random streams, same couplings) within 3 sigma of the block-jackknife errors.
 """
 import numpy as np
 import pytest
@@ -88,10 +88,11 @@ def test_long_run_matches_oracle():
     for b in range(R):
         for name, xg, xr in [("e", e_g[burn:, :, :, b].mean(axis=(1, 2)), e_r[burn:, :, :, b].mean(axis=(1, 2))),
                              ("chi", chi_g[burn:, :, b].mean(axis=1), chi_r[burn:, :, b].mean(axis=1))]:
-            mg, sg = su.block_mean_err(xg)
-            mr, sr = su.block_mean_err(xr)
+            mg, sg = su.jackknife_mean_err(xg)
+            mr, sr = su.jackknife_mean_err(xr)
             zz = (mg - mr) / np.sqrt(sg ** 2 + sr ** 2)
-            assert abs(zz) < 4.0, (name, b, mg, sg, mr, sr)
+            print("%s beta_%d gpu %.6f +- %.6f oracle %.6f +- %.6f z %+.2f" % (name, b, mg, sg, mr, sr, zz))
+            assert abs(zz) < 3.0, (name, b, mg, sg, mr, sr)
             z.append(zz)
     z = np.array(z)
     # the combined chi-square of the 2R comparisons stays plausible
