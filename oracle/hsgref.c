@@ -22,6 +22,7 @@
  *   overlap, susceptibility, E   -- paper Sec. II, Eq. (eq:over) and following
  *   round trips                  -- paper Sec. IV.B
  *   decimated exchange           -- paper Sec. III.A, Eqs. (xxxY), (HI), (eq:aswap)
+ *   cooling / heating exchange   -- paper Sec. III.B
  *   annealed (nonequilibrium) swap -- cited prior art of Sec. I (Opps & Schofield
  *     2001; Ballard & Jarzynski 2009); the protocol below is the standard
  *     nonequilibrium-candidate construction, which reduces to Eq. (1) at K = 0.
@@ -752,6 +753,176 @@ void hsgref_decimate_batch(int L, int S, int C, int R, const double* J, double* 
         swap_ctr[ch] = n + 1;
         hsgref_roundtrip_update(R, tos, rt_state + (size_t)ch * R, rt_trips + (size_t)ch * R);
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cooling / heating exchange (paper Sec. III.B).  One spin s with field S    */
+/* (|S| > 0, n = S/|S|, cos(theta) = s.n, k = eps |S|): cooling turns s       */
+/* towards S by alpha = eps |p| = k sin(theta), p = S - (S.s) s, in the plane */
+/* of s and S:  s' = s cos(alpha) + (p/|p|) sin(alpha), theta' = theta-alpha.  */
+/* For k < 1, theta -> theta' is increasing on [0, pi], so the map is a       */
+/* bijection of the sphere; its Jacobian (area ratio) is                      */
+/*   |1 - eps S.s| (cos(alpha) - cot(theta) sin(alpha))                       */
+/*   = (1 - k cos(theta)) (cos(alpha) - cos(theta) k sinc(alpha)),            */
+/* sinc(a) = sin(a)/a, finite at the poles.  Heating is the inverse: theta    */
+/* from theta' by Newton's method on theta - k sin(theta) = theta'.           */
+/* A lattice cooling C cools every parity-0 spin (fields from parity 1), then */
+/* every parity-1 spin (fields from the cooled parity 0); the Jacobian of C is */
+/* the product of the site factors.  Heating C^-1 undoes the parity-1 step,   */
+/* then the parity-0 step.                                                    */
+/* Exchange of x at b1 = beta_i and y at b2 = beta_{i+1}: the proposal       */
+/* (x, y) -> (C^-1 y at b1, C x at b2) is an involution, accepted with        */
+/*   ln A = b1 H(x) + b2 H(y) - b1 H(C^-1 y) - b2 H(C x)                     */
+/*          + ln det J_C(x) - ln det J_C(C^-1 y),                            */
+/* decided as ln u < ln A; eps = 0 is Eq. (1).  If k >= 1 at a site of either */
+/* map the pair is rejected (the map is then not a bijection).               */
+/* ------------------------------------------------------------------------- */
+
+static double sinc(double a)
+{
+    if (fabs(a) < 1e-4) return 1.0 - a * a / 6.0;
+    return sin(a) / a;
+}
+
+/* log of the Jacobian of the cooling map at a spin with cos(theta) = c,
+ * sin(theta) = st, k = eps |S|. */
+static double cool_log_jacobian(double c, double st, double k)
+{
+    double alpha = k * st;
+    return log(1.0 - k * c) + log(cos(alpha) - c * k * sinc(alpha));
+}
+
+/* Cool one spin; returns the log Jacobian, or NAN if eps |S| >= 1. */
+double hsgref_cool_spin(const double s[3], const double S[3], double eps, double out[3])
+{
+    double nS = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    double k = eps * nS, Ss, c, p[3], np, st, alpha, ca, sa;
+    int a;
+    if (k >= 1.0) return NAN;
+    if (nS == 0.0) {
+        for (a = 0; a < 3; ++a) out[a] = s[a];
+        return 0.0;
+    }
+    Ss = S[0] * s[0] + S[1] * s[1] + S[2] * s[2];
+    c = Ss / nS;
+    for (a = 0; a < 3; ++a) p[a] = S[a] - Ss * s[a];
+    np = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    st = np / nS;
+    alpha = eps * np;
+    ca = cos(alpha);
+    sa = sin(alpha);
+    for (a = 0; a < 3; ++a) out[a] = (np > 0.0) ? s[a] * ca + p[a] / np * sa : s[a];
+    return cool_log_jacobian(c, st, k);
+}
+
+/* Heat one spin (the inverse of cooling); returns the log Jacobian of the
+ * cooling map at the result, or NAN if eps |S| >= 1. */
+double hsgref_heat_spin(const double sp[3], const double S[3], double eps, double out[3])
+{
+    double nS = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    double k = eps * nS, Ss, q[3], nq, thp, th, alpha, ca, sa;
+    int a, it;
+    if (k >= 1.0) return NAN;
+    if (nS == 0.0) {
+        for (a = 0; a < 3; ++a) out[a] = sp[a];
+        return 0.0;
+    }
+    Ss = S[0] * sp[0] + S[1] * sp[1] + S[2] * sp[2];
+    for (a = 0; a < 3; ++a) q[a] = S[a] - Ss * sp[a];
+    nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    thp = atan2(nq, Ss); /* theta' in [0, pi] */
+    th = thp + k * sin(thp);
+    for (it = 0; it < 50; ++it) {
+        double g = th - k * sin(th) - thp;
+        double d = g / (1.0 - k * cos(th));
+        th -= d;
+        if (fabs(d) <= 1e-16 * (1.0 + th)) break;
+    }
+    alpha = th - thp;
+    ca = cos(alpha);
+    sa = sin(alpha);
+    for (a = 0; a < 3; ++a) out[a] = (nq > 0.0) ? sp[a] * ca - q[a] / nq * sa : sp[a];
+    return cool_log_jacobian(cos(th), sin(th), k);
+}
+
+/* Lattice cooling (heat = 0) or heating (heat = 1) in place; returns the log
+ * Jacobian of the cooling map (at s before cooling, or at the heated result). */
+double hsgref_coolheat(int L, const double* J, double* s, double eps, int heat)
+{
+    int N = L * L * L, step, z;
+    double logdet = 0.0;
+    for (step = 0; step < 2; ++step) {
+        int par = heat ? 1 - step : step;
+        for (z = 0; z < N; ++z) {
+            double S[3], o[3], ld;
+            if (hsgref_parity(L, z) != par) continue;
+            hsgref_local_field(L, J, s, z, S);
+            ld = heat ? hsgref_heat_spin(s + (size_t)z * 3, S, eps, o)
+                      : hsgref_cool_spin(s + (size_t)z * 3, S, eps, o);
+            s[(size_t)z * 3 + 0] = o[0];
+            s[(size_t)z * 3 + 1] = o[1];
+            s[(size_t)z * 3 + 2] = o[2];
+            logdet += ld;
+        }
+    }
+    return logdet;
+}
+
+void hsgref_coolheat_batch(int L, int S, int C, int R, const double* J, double* spins,
+                           const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
+                           uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
+                           int64_t* rt_trips, uint32_t chain_base, uint64_t seed, int pairing,
+                           double eps, double* log_ratio_out, double* logdet_out)
+{
+    int N = L * L * L;
+    int ch, n_chain = S * C;
+    size_t rep = (size_t)N * 3;
+    double* cx = (double*)malloc(rep * sizeof(double));
+    double* cy = (double*)malloc(rep * sizeof(double));
+    for (ch = 0; ch < n_chain; ++ch) {
+        int smp = ch / C, i;
+        const double* Js = J + (size_t)smp * rep;
+        int32_t* tos = temp_of_slot + (size_t)ch * R;
+        int32_t* sot = slot_of_temp + (size_t)ch * R;
+        int64_t* st = stats + (size_t)ch * (R - 1) * 2;
+        uint32_t cg = chain_base + (uint32_t)ch;
+        uint32_t n = swap_ctr[ch];
+        for (i = 0; i < R - 1; ++i) {
+            uint32_t w[4];
+            double u, lnA, ldx, ldy, hx, hy, b1 = betas[i], b2 = betas[i + 1];
+            size_t gx, gy;
+            size_t o = (size_t)ch * (R - 1) + i;
+            if (log_ratio_out) log_ratio_out[o] = 0.0;
+            if (logdet_out) { logdet_out[2 * o] = 0.0; logdet_out[2 * o + 1] = 0.0; }
+            if (!pair_selected(i, pairing)) continue;
+            gx = (size_t)ch * R + (size_t)sot[i];
+            gy = (size_t)ch * R + (size_t)sot[i + 1];
+            memcpy(cx, spins + gx * rep, rep * sizeof(double));
+            memcpy(cy, spins + gy * rep, rep * sizeof(double));
+            ldx = hsgref_coolheat(L, Js, cx, eps, 0);
+            ldy = hsgref_coolheat(L, Js, cy, eps, 1);
+            hx = hsgref_energy(L, Js, cx);
+            hy = hsgref_energy(L, Js, cy);
+            lnA = b1 * energy[gx] + b2 * energy[gy] - b1 * hy - b2 * hx + ldx - ldy;
+            if (log_ratio_out) log_ratio_out[o] = lnA;
+            if (logdet_out) { logdet_out[2 * o] = ldx; logdet_out[2 * o + 1] = ldy; }
+            draw(seed, (uint32_t)i, n, cg, TAG_SWAP << 24, w);
+            u = hsgref_u01_52(w[0], w[1]);
+            st[2 * i] += 1;
+            if (log(u) < lnA) { /* false for NaN: a map that is not a bijection rejects */
+                memcpy(spins + gx * rep, cx, rep * sizeof(double));
+                memcpy(spins + gy * rep, cy, rep * sizeof(double));
+                energy[gx] = hx;
+                energy[gy] = hy;
+                relabel(tos, sot, i);
+                st[2 * i + 1] += 1;
+            }
+        }
+        swap_ctr[ch] = n + 1;
+        hsgref_roundtrip_update(R, tos, rt_state + (size_t)ch * R, rt_trips + (size_t)ch * R);
+    }
+    free(cx);
+    free(cy);
 }
 
 /* ------------------------------------------------------------------------- */

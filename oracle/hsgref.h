@@ -84,6 +84,14 @@ void hsgref_decimate_batch(int L, int S, int C, int R, const double* J, double* 
                            int64_t* rt_trips, uint32_t slot_base, uint32_t chain_base,
                            uint64_t seed, int pairing, int rng32, double* log_ratio_out,
                            int32_t* role_out);
+double hsgref_cool_spin(const double s[3], const double S[3], double eps, double out[3]);
+double hsgref_heat_spin(const double sp[3], const double S[3], double eps, double out[3]);
+double hsgref_coolheat(int L, const double* J, double* s, double eps, int heat);
+void hsgref_coolheat_batch(int L, int S, int C, int R, const double* J, double* spins,
+                           const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
+                           uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
+                           int64_t* rt_trips, uint32_t chain_base, uint64_t seed, int pairing,
+                           double eps, double* log_ratio_out, double* logdet_out);
 void hsgref_measure_batch(int L, int S, int C, int R, const double* spins, const double* energy,
                           const int32_t* slot_of_temp, double* Q, double* chi, double* e);
 void hsgref_roundtrip_update(int R, const int32_t* temp_of_slot, int32_t* rt_state,

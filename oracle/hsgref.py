@@ -75,6 +75,12 @@ def lib():
             "hsgref_decimate_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _dp, _i32p,
                                              _i32p, _u32p, _dp, _i64p, _i32p, _i64p, _c_u32,
                                              _c_u32, _c_u64, _c_int, _c_int, _dp, _i32p]),
+            "hsgref_cool_spin": (_c_dbl, [_dp, _dp, _c_dbl, _dp]),
+            "hsgref_heat_spin": (_c_dbl, [_dp, _dp, _c_dbl, _dp]),
+            "hsgref_coolheat": (_c_dbl, [_c_int, _dp, _dp, _c_dbl, _c_int]),
+            "hsgref_coolheat_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _dp, _i32p,
+                                             _i32p, _u32p, _dp, _i64p, _i32p, _i64p, _c_u32,
+                                             _c_u64, _c_int, _c_dbl, _dp, _dp]),
             "hsgref_measure_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _i32p, _dp,
                                             _dp, _dp]),
             "hsgref_roundtrip_update": (None, [_c_int, _i32p, _i32p, _i64p]),
@@ -243,6 +249,31 @@ def decimate_role(seed, chain_global, n):
     return lib().hsgref_decimate_role(seed, chain_global, n)
 
 
+def cool_spin(s, S, eps):
+    """Cooling map of one spin (paper Sec. III.B): (new spin, log Jacobian)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.zeros(3)
+    ld = lib().hsgref_cool_spin(dp(s), dp(S), float(eps), dp(out))
+    return out, ld
+
+
+def heat_spin(s, S, eps):
+    """Inverse of cool_spin: (pre-image, log Jacobian of cooling at the pre-image)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.zeros(3)
+    ld = lib().hsgref_heat_spin(dp(s), dp(S), float(eps), dp(out))
+    return out, ld
+
+
+def coolheat(L, J, s, eps, heat):
+    """Lattice cooling (heat=False) or heating in place; returns the log Jacobian of cooling."""
+    assert s.dtype == np.float64 and s.flags["C_CONTIGUOUS"]
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    return lib().hsgref_coolheat(L, dp(J), dp(s), float(eps), int(heat))
+
+
 def geometric_betas(bmin, bmax, R):
     """beta_r = bmin (bmax/bmin)^(r/(R-1)), ascending (the paper's ladder family, Sec. IV)."""
     r = np.arange(R, dtype=np.float64)
@@ -354,6 +385,20 @@ class RefEnsemble:
                                     self.slot_base, self.chain_base, self.seed, int(pairing),
                                     int(self.rng32), dp(lnA), i32p(role))
         return lnA, role
+
+    def coolheat_swap(self, eps, pairing=0):
+        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs.  Returns
+        ln A [S][C][R-1] and the log Jacobians of cooling at x and at C^-1 y
+        [S][C][R-1][2] (zeros where not attempted)."""
+        lnA = np.zeros((self.S, self.C, self.R - 1))
+        ld = np.zeros((self.S, self.C, self.R - 1, 2))
+        lib().hsgref_coolheat_batch(self.L, self.S, self.C, self.R, dp(self.J), dp(self.spins),
+                                    dp(self.betas), i32p(self.temp_of_slot),
+                                    i32p(self.slot_of_temp), u32p(self.swap_ctr), dp(self.energy),
+                                    i64p(self.stats), i32p(self.rt_state), i64p(self.rt_trips),
+                                    self.chain_base, self.seed, int(pairing), float(eps), dp(lnA),
+                                    dp(ld))
+        return lnA, ld
 
     def measure(self):
         Q = np.zeros((self.S, self.R, 3, 3))
