@@ -17,8 +17,9 @@
  *  - A launch failure returns HSG_ERR_DEVICE with the HIP error string.
  *  - Numerical trouble seen by a kernel (a non-finite spin or energy, a spin
  *    whose norm left 1 by more than the precision's tolerance, a protocol
- *    length outside [0, anneal_K_max], a temperature label outside [0, R)) is
- *    latched in *guard (bits 1, 2, 4) and reported by hsg_check as
+ *    length outside [0, anneal_K_max], a temperature label outside [0, R), a
+ *    cooling map that is not a bijection) is latched in *guard (bits 1, 2, 4, 8)
+ *    and reported by hsg_check as
  *    HSG_ERR_NUMERIC.  Out-of-range values are clamped before use, so a
  *    corrupted label or protocol length never addresses outside its ensemble.
  *  - Calls on one ensemble must not overlap in time (use one stream per
@@ -191,6 +192,27 @@ hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n
  * trips.  If work is not NULL it receives, per pair, ln A and D_i
  * ([S][C][R-1][2]; 0 and -1 for pairs not attempted).  n_temps <= 65536. */
 hsg_status hsg_decimate_swap(const hsg_ensemble* ens, int n_ens, int pairing, void* stream);
+
+/* Cooling / heating replica exchange (paper Sec. III.B) of the selected pairs of
+ * every chain (pairing 0: all pairs in ascending order, each seeing the states
+ * the previous pair left; 1: even i; 2: odd i).  Site map with field S of the
+ * other sublattice, k = eps |S|, cos(theta) = s.S/|S|: cooling turns s towards S
+ * by alpha = k sin(theta) in the plane of s and S; heating is its inverse
+ * (Newton's method on theta - k sin(theta) = theta').  The lattice cooling C maps
+ * sublattice 0 and then 1; C^-1 undoes 1 and then 0.  For x at b1 = beta_i and
+ * y at b2 = beta_{i+1} the involution (x, y) -> (C^-1 y at b1, C x at b2) is
+ * accepted iff ln u < ln A,
+ *   ln A = b1 H(x) + b2 H(y) - b1 H(C^-1 y) - b2 H(C x)
+ *          + ln det J_C(x) - ln det J_C(C^-1 y)
+ * (FP64; maps in the spin precision; u from the same per-pair stream as
+ * hsg_swap); eps = 0 is Eq. (1).  Accepted pairs take the transformed states at
+ * the exchanged temperatures, rejected pairs change nothing.  A site with
+ * eps |S| >= 1 (the map is then not a bijection) rejects its pair and sets guard
+ * bit 8.  Needs scratch (hsg_scratch_bytes) and work, which receives
+ * ln det J_C(x) and ln det J_C(C^-1 y) per pair ([S][C][R-1][2], zeros for the
+ * pairs not attempted).  Advances swap_ctr, updates swap_stats and round trips. */
+hsg_status hsg_coolheat_swap(const hsg_ensemble* ens, int n_ens, int pairing, double eps,
+                             void* stream);
 
 /* Overlap (paper Sec. II): Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between the
  * chain-0 and chain-1 configurations at each temperature, chi = Q:Q / N, and

@@ -243,6 +243,21 @@ hsg_status hsg_decimate_swap(const hsg_ensemble* ens, int n_ens, int pairing, vo
     return ok();
 }
 
+hsg_status hsg_coolheat_swap(const hsg_ensemble* ens, int n_ens, int pairing, double eps, void* stream) {
+    if (pairing < 0 || pairing > 2) return fail(HSG_ERR_INVALID, "pairing must be 0, 1 or 2 (got %d)", pairing);
+    if (!(eps >= 0.0) || !(eps < 1e6)) return fail(HSG_ERR_INVALID, "eps must be finite and >= 0 (got %g)", eps);
+    hsg_status s = check_all(ens, n_ens, kState | kScratch);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i)
+        if (!ens[i].work || !aligned(ens[i].work, 8))
+            return fail(HSG_ERR_INVALID, "ensemble %d: work ([S][C][R-1][2] doubles) is required", i);
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_coolheat(ens[i], pairing, eps, as_stream(stream));
+        if (err != hipSuccess) return device(err, "cooling/heating exchange");
+    }
+    return ok();
+}
+
 hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream) {
     hsg_status s = check_all(ens, n_ens, kState | kMeasure);
     if (s != HSG_OK) return s;
@@ -263,10 +278,11 @@ hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream) {
         err = hipMemcpy(&g, ens[i].guard, sizeof(g), hipMemcpyDeviceToHost);
         if (err != hipSuccess) return device(err, "check: read guard");
         if (g != 0)
-            return fail(HSG_ERR_NUMERIC, "ensemble %d: guard = %d (%s%s%s)", i, g,
+            return fail(HSG_ERR_NUMERIC, "ensemble %d: guard = %d (%s%s%s%s)", i, g,
                         (g & 1) ? "non-finite or non-unit spin or energy; " : "",
                         (g & 2) ? "protocol length outside [0, anneal_K_max]; " : "",
-                        (g & 4) ? "temperature label outside [0, R)" : "");
+                        (g & 4) ? "temperature label outside [0, R); " : "",
+                        (g & 8) ? "cooling map not a bijection (eps |S| >= 1)" : "");
     }
     return ok();
 }

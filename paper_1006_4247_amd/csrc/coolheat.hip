@@ -1,0 +1,369 @@
+// Cooling / heating replica exchange (paper Sec. III.B).
+//
+// Site map (spin s, field S of the other sublattice, k = eps |S|, cos(theta) = s.S/|S|):
+// cooling turns s towards S by alpha = eps |p| = k sin(theta), p = S - (S.s) s,
+//     s' = s cos(alpha) + (p/|p|) sin(alpha),   theta' = theta - alpha,
+// a bijection of the sphere for k < 1 with Jacobian
+//     (1 - k cos(theta)) (cos(alpha) - cos(theta) k sinc(alpha)).
+// Heating inverts it: theta from theta' by Newton's method on
+// theta - k sin(theta) = theta', then s = s' cos(alpha) - (q/|q|) sin(alpha),
+// q = S - (S.s') s'.  Lattice cooling C maps parity 0 (fields from parity 1) and then
+// parity 1; heating C^-1 undoes parity 1 and then parity 0.
+//
+// Exchange of x at b1 = beta_i and y at b2 = beta_{i+1}: the involution
+// (x, y) -> (C^-1 y at b1, C x at b2) is accepted iff ln u < ln A,
+//     ln A = b1 H(x) + b2 H(y) - b1 H(C^-1 y) - b2 H(C x) + ln det J_C(x) - ln det J_C(C^-1 y).
+// Legs: one workgroup cools x, one heats y, into the candidate buffer, with the log
+// Jacobian (FP64 sum of site terms) and the fused FP64 energy; a per-chain kernel
+// decides; accepted candidates are copied back.  A site with k >= 1 makes the pair's
+// Jacobian NaN (the map is not a bijection): the pair is rejected and guard bit 8 set.
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace hsg {
+
+constexpr int kChThreads = 256;
+
+__device__ __forceinline__ double ch_sinc(double a) {
+    return fabs(a) < 1e-4 ? 1.0 - a * a / 6.0 : sin(a) / a;
+}
+
+// log Jacobian of cooling at a spin with cos(theta) = c, sin(theta) = st
+__device__ __forceinline__ double cool_log_jac(double c, double st, double k) {
+    const double alpha = k * st;
+    return log(1.0 - k * c) + log(cos(alpha) - c * k * ch_sinc(alpha));
+}
+
+template <typename T>
+__device__ __forceinline__ T d_atan2(T y, T x);
+template <>
+__device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x); }
+template <>
+__device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
+
+// One site: cool (HEAT = false) or heat s in place given the field; returns the log
+// Jacobian of cooling (at s before cooling / at the heated result), NaN if k >= 1.
+template <typename T, bool HEAT>
+__device__ __forceinline__ double coolheat_site(T& sx, T& sy, T& sz, T Sx, T Sy, T Sz, T eps) {
+    const T nS = sqrt(fma(Sz, Sz, fma(Sy, Sy, Sx * Sx)));
+    const T k = eps * nS;
+    if (!(k < T(1))) return __builtin_nan("");
+    if (nS == T(0)) return 0.0;
+    const T Ss = fma(Sz, sz, fma(Sy, sy, Sx * sx));
+    const T px = fma(-Ss, sx, Sx), py = fma(-Ss, sy, Sy), pz = fma(-Ss, sz, Sz);
+    const T np = sqrt(fma(pz, pz, fma(py, py, px * px)));
+    if (!HEAT) {
+        const T alpha = eps * np;
+        const T ca = cos(alpha), sa = sin(alpha);
+        if (np > T(0)) {
+            const T f = sa / np;
+            sx = fma(px, f, sx * ca);
+            sy = fma(py, f, sy * ca);
+            sz = fma(pz, f, sz * ca);
+        }
+        return cool_log_jac(static_cast<double>(Ss) / static_cast<double>(nS),
+                            static_cast<double>(np) / static_cast<double>(nS), static_cast<double>(k));
+    } else {
+        const T thp = d_atan2<T>(np, Ss);  // theta' in [0, pi]
+        T th = fma(k, sin(thp), thp);
+        for (int it = 0; it < 50; ++it) {
+            const T g = fma(-k, sin(th), th) - thp;
+            const T d = g / fma(-k, cos(th), T(1));
+            th -= d;
+            if (!(fabs(d) > T(sizeof(T) == 4 ? 1e-7 : 1e-16) * (T(1) + th))) break;
+        }
+        const T alpha = th - thp;
+        const T ca = cos(alpha), sa = sin(alpha);
+        if (np > T(0)) {
+            const T f = -sa / np;
+            sx = fma(px, f, sx * ca);
+            sy = fma(py, f, sy * ca);
+            sz = fma(pz, f, sz * ca);
+        }
+        const double thd = static_cast<double>(th);
+        return cool_log_jac(cos(thd), sin(thd), static_cast<double>(k));
+    }
+}
+
+// Work item b of a launch over the pairs i = i0 + istep m (m < npc) of every chain,
+// two legs each: leg 0 cools the configuration at beta_i, leg 1 heats the one at
+// beta_{i+1}.
+struct ChItem {
+    int ch, i, leg, slot;
+};
+
+__device__ __forceinline__ ChItem ch_item(const hsg_ensemble& e, int b, int i0, int istep, int npc) {
+    ChItem it;
+    const int R = e.n_temps;
+    it.ch = b / (2 * npc);
+    const int rest = b - it.ch * 2 * npc;
+    it.leg = rest & 1;
+    it.i = i0 + istep * (rest >> 1);
+    it.slot = it.ch * R + label(e.slot_of_temp[it.ch * R + it.i + it.leg], R, e.guard);
+    return it;
+}
+
+// LDS-resident legs (L <= 16): the replica in LDS, couplings from global memory.
+template <typename T, int L>
+__global__ void __launch_bounds__(kChThreads) k_coolheat_leg_res(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+    constexpr int N = L * L * L, NH = N / 2;
+    constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sh = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[kChThreads / 64];
+    const ChItem it = ch_item(e, blockIdx.x, i0, istep, npc);
+    const int smp = it.ch / e.n_chains;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) + static_cast<size_t>(it.slot) * 3 * N);
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<T*>(scr + sl.cand) + static_cast<size_t>(it.slot) * 3 * N);
+    uint4* s4 = reinterpret_cast<uint4*>(sh);
+    for (int v = threadIdx.x; v < NV; v += kChThreads) s4[v] = src[v];
+    __syncthreads();
+    double ld = 0.0, en = 0.0;
+    for (int step = 0; step < 2; ++step) {
+        const int p = it.leg ? 1 - step : step;
+        const T* o0 = sh + (0 * 2 + (1 - p)) * NH;
+        const T* o1 = sh + (1 * 2 + (1 - p)) * NH;
+        const T* o2 = sh + (2 * 2 + (1 - p)) * NH;
+        T* w0 = sh + (0 * 2 + p) * NH;
+        T* w1 = sh + (1 * 2 + p) * NH;
+        T* w2 = sh + (2 * 2 + p) * NH;
+        for (int h = threadIdx.x; h < NH; h += kChThreads) {
+            const Nbr nb = neighbours<L>(h, p, L);
+            T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int mu = d >> 1;
+                const T jj = (d & 1) ? J[(mu * 2 + (1 - p)) * NH + nb.n[d]] : J[(mu * 2 + p) * NH + h];
+                const int idx = nb.n[d];
+                Sx = fma(jj, o0[idx], Sx);
+                Sy = fma(jj, o1[idx], Sy);
+                Sz = fma(jj, o2[idx], Sz);
+            }
+            T sx = w0[h], sy = w1[h], sz = w2[h];
+            ld += it.leg ? coolheat_site<T, true>(sx, sy, sz, Sx, Sy, Sz, eps)
+                         : coolheat_site<T, false>(sx, sy, sz, Sx, Sy, Sz, eps);
+            w0[h] = sx;
+            w1[h] = sy;
+            w2[h] = sz;
+            if (step == 1) {
+                const double dx = sx, dy = sy, dz = sz;
+                en += fma(dz, static_cast<double>(Sz), fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+            }
+        }
+        __syncthreads();
+    }
+    for (int v = threadIdx.x; v < NV; v += kChThreads) dst[v] = s4[v];
+    const double LD = block_sum<kChThreads>(ld, red);
+    const double H = -block_sum<kChThreads>(en, red);
+    if (threadIdx.x == 0) {
+        e.work[(static_cast<size_t>(it.ch) * (e.n_temps - 1) + it.i) * 2 + it.leg] = LD;
+        reinterpret_cast<double*>(scr + sl.cand_energy)[it.slot] = H;
+        if (isnan(LD)) atomicOr(e.guard, 8);
+    }
+}
+
+// Generic legs (any even L): the candidate in global memory.
+template <typename T>
+__global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+    __shared__ double red[kChThreads / 64];
+    const int L = e.L, N = L * L * L, NH = N / 2;
+    const ChItem it = ch_item(e, blockIdx.x, i0, istep, npc);
+    const int smp = it.ch / e.n_chains;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    T* c = reinterpret_cast<T*>(scr + sl.cand) + static_cast<size_t>(it.slot) * 3 * N;
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) + static_cast<size_t>(it.slot) * 3 * N);
+        uint4* dst = reinterpret_cast<uint4*>(c);
+        const int nv = 3 * N * static_cast<int>(sizeof(T)) / 16;
+        for (int v = threadIdx.x; v < nv; v += kChThreads) dst[v] = src[v];
+    }
+    __syncthreads();
+    double ld = 0.0, en = 0.0;
+    for (int step = 0; step < 2; ++step) {
+        const int p = it.leg ? 1 - step : step;
+        const T* o0 = c + (0 * 2 + (1 - p)) * NH;
+        const T* o1 = c + (1 * 2 + (1 - p)) * NH;
+        const T* o2 = c + (2 * 2 + (1 - p)) * NH;
+        T* w0 = c + (0 * 2 + p) * NH;
+        T* w1 = c + (1 * 2 + p) * NH;
+        T* w2 = c + (2 * 2 + p) * NH;
+        for (int h = threadIdx.x; h < NH; h += kChThreads) {
+            const Nbr nb = neighbours<0>(h, p, L);
+            T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int mu = d >> 1;
+                const T jj = (d & 1) ? J[(mu * 2 + (1 - p)) * NH + nb.n[d]] : J[(mu * 2 + p) * NH + h];
+                const int idx = nb.n[d];
+                Sx = fma(jj, o0[idx], Sx);
+                Sy = fma(jj, o1[idx], Sy);
+                Sz = fma(jj, o2[idx], Sz);
+            }
+            T sx = w0[h], sy = w1[h], sz = w2[h];
+            ld += it.leg ? coolheat_site<T, true>(sx, sy, sz, Sx, Sy, Sz, eps)
+                         : coolheat_site<T, false>(sx, sy, sz, Sx, Sy, Sz, eps);
+            w0[h] = sx;
+            w1[h] = sy;
+            w2[h] = sz;
+            if (step == 1) {
+                const double dx = sx, dy = sy, dz = sz;
+                en += fma(dz, static_cast<double>(Sz), fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+            }
+        }
+        __syncthreads();  // the next half-step reads this one's spins
+    }
+    const double LD = block_sum<kChThreads>(ld, red);
+    const double H = -block_sum<kChThreads>(en, red);
+    if (threadIdx.x == 0) {
+        e.work[(static_cast<size_t>(it.ch) * (e.n_temps - 1) + it.i) * 2 + it.leg] = LD;
+        reinterpret_cast<double*>(scr + sl.cand_energy)[it.slot] = H;
+        if (isnan(LD)) atomicOr(e.guard, 8);
+    }
+}
+
+// Decisions of the pairs i0 + istep m (m < npc) of one chain per thread; `last`
+// advances the exchange counter and the round trips (once per call).
+__global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, int last) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_chains) return;
+    const int R = e.n_temps;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const double* cen = reinterpret_cast<const double*>(scr + sl.cand_energy);
+    int* flags = reinterpret_cast<int*>(scr + sl.flags);
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    double* en = e.energy + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    for (int r = 0; r < R; ++r) flags[ch * R + r] = 0;
+    for (int m = 0; m < npc; ++m) {
+        const int i = i0 + istep * m;
+        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+        const double b1 = e.betas[i], b2 = e.betas[i + 1];
+        const double lnA = b1 * en[x] + b2 * en[y] - b1 * cen[ch * R + y] - b2 * cen[ch * R + x] + W[2 * i] - W[2 * i + 1];
+        const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
+        st[2 * i] += 1;
+        if (log(u01_52(w.w0, w.w1)) < lnA) {
+            en[x] = cen[ch * R + x];
+            en[y] = cen[ch * R + y];
+            flags[ch * R + x] = 1;
+            flags[ch * R + y] = 1;
+            sot[i] = y;
+            sot[i + 1] = x;
+            tos[x] = i + 1;
+            tos[y] = i;
+            st[2 * i + 1] += 1;
+        }
+    }
+    if (!last) return;
+    if (istep == 2)  // even / odd pairs: clear the entries of the pairs not attempted
+        for (int i = 1 - (i0 & 1); i < R - 1; i += 2) {
+            W[2 * i] = 0.0;
+            W[2 * i + 1] = 0.0;
+        }
+    e.swap_ctr[ch] = n + 1u;
+    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
+    for (int r = 0; r < R; ++r) {
+        const int Tr = tos[r];
+        if (Tr == 0) {
+            if (rs[r] == 2) rtt[r] += 1;
+            rs[r] = 1;
+        } else if (Tr == R - 1) {
+            if (rs[r] == 1) rs[r] = 2;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_coolheat_copyback(hsg_ensemble e) {
+    const int slot = blockIdx.x;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    if (!reinterpret_cast<const int*>(scr + sl.flags)[slot]) return;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
+    uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
+    const size_t nv = 3 * N * sizeof(T) / 16;
+    for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+}
+
+template <typename T, int L>
+static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
+    constexpr size_t lds = 3 * L * L * L * sizeof(T);
+    auto kern = k_coolheat_leg_res<T, L>;
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kChThreads), lds, st, e, eps, i0, istep, npc);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, int npc, hipStream_t st) {
+    const int blocks = e.n_samples * e.n_chains * npc * 2;
+    const T te = static_cast<T>(eps);
+    switch (e.L) {
+        case 4: return go_leg_res<T, 4>(e, te, i0, istep, npc, blocks, st);
+        case 6: return go_leg_res<T, 6>(e, te, i0, istep, npc, blocks, st);
+        case 8: return go_leg_res<T, 8>(e, te, i0, istep, npc, blocks, st);
+        case 10: return go_leg_res<T, 10>(e, te, i0, istep, npc, blocks, st);
+        case 12: return go_leg_res<T, 12>(e, te, i0, istep, npc, blocks, st);
+        case 14: return go_leg_res<T, 14>(e, te, i0, istep, npc, blocks, st);
+        case 16: return go_leg_res<T, 16>(e, te, i0, istep, npc, blocks, st);
+        default:
+            hipLaunchKernelGGL(k_coolheat_leg<T>, dim3(blocks), dim3(kChThreads), 0, st, e, te, i0, istep, npc);
+            return hipGetLastError();
+    }
+}
+
+static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int istep, int npc, int last,
+                                 hipStream_t st) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int n_slots = n_chains * e.n_temps;
+    hipError_t err = hipSuccess;
+    if (npc > 0) {
+        err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, st)
+                                      : go_legs<float>(e, eps, i0, istep, npc, st);
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep, npc, last);
+    err = hipGetLastError();
+    if (err != hipSuccess || npc == 0) return err;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_coolheat_copyback<double>, dim3(n_slots), dim3(256), 0, st, e);
+    else
+        hipLaunchKernelGGL(k_coolheat_copyback<float>, dim3(n_slots), dim3(256), 0, st, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipStream_t st) {
+    const int R = e.n_temps;
+    if (e.n_samples * e.n_chains <= 0 || R < 2) return hipSuccess;
+    if (pairing == 0) {
+        // ascending order: each pair sees the states the previous pair left
+        for (int i = 0; i < R - 1; ++i) {
+            hipError_t err = coolheat_round(e, eps, i, 1, 1, i == R - 2, st);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    const int first = pairing == 1 ? 0 : 1;
+    const int npc = (R - first) / 2;
+    return coolheat_round(e, eps, first, 2, npc, 1, st);
+}
+
+}  // namespace hsg

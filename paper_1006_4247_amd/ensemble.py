@@ -192,6 +192,14 @@ class Ensemble:
                                                 self._stream()))
         return self.work
 
+    def coolheat_swap(self, eps, pairing=0):
+        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs; afterwards
+        work[..., i, 0] and work[..., i, 1] hold ln det J_C(x) and ln det J_C(C^-1 y) of
+        pair i (zeros where not attempted)."""
+        _abi.check(_abi.lib().hsg_coolheat_swap(ctypes.byref(self.desc), 1, int(pairing),
+                                                float(eps), self._stream()))
+        return self.work
+
     def measure(self):
         _abi.check(_abi.lib().hsg_measure(ctypes.byref(self.desc), 1, self._stream()))
         return self.Q, self.chi, self.e_temp
