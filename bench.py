@@ -43,6 +43,11 @@ WORKLOADS = {
 }
 DEFAULT = "plain-pt-L16-S64-C2-R24"
 
+# cooling / heating parameter: the paper's per lattice size (Sec. IV), and the grid the
+# short tuning runs scan
+COOLHEAT_EPS_PAPER = {16: 0.017, 24: 0.01}
+COOLHEAT_EPS_GRID = (0.001, 0.002, 0.003, 0.004, 0.005, 0.006, 0.008)
+
 
 def algorithmic_ops_per_update(n_hb, n_or, prec):
     per_hb = OPS_LOCAL_FIELD + OPS_HEATBATH + OPS_PHILOX_PER_BLOCK / (2 if prec == "fp32" else 1)
@@ -132,8 +137,9 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     the workload's lattice and beta range: plain PT on a ladder dense enough for
     acceptance ~0.1 versus annealed exchanges on the workload's own ladder with (a) one
     protocol length for every pair, chosen for acceptance ~0.1, and (b) the learned
-    per-pair schedule; and the decimated exchange (paper Sec. III.A) on the dense ladder
-    (acceptance against plain PT at equal spacing) and on the workload's own ladder.
+    per-pair schedule; the decimated exchange (paper Sec. III.A) on the dense ladder
+    (acceptance against plain PT at equal spacing) and on the workload's own ladder; and
+    the cooling / heating exchange (paper Sec. III.B) on the dense ladder.
     Steps are replayed from a HIP graph; the learner's data generation and training are
     timed separately."""
     from paper_1006_4247_amd import runtime
@@ -150,8 +156,8 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
         e.init_spins()
         return e
 
-    def timed(e, mode, steps, warm=300):
-        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode)
+    def timed(e, mode, steps, warm=300, eps=0.0):
+        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode, eps=eps)
         run.step(warm)
         run.capture()
         run.synchronize()
@@ -199,15 +205,27 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     # decimated exchange (paper Sec. III.A), even / odd pairs alternating
     out["decimated_dense_ladder"] = timed(make(R_dense), "decimate", steps_plain)
     out["decimated_own_ladder"] = timed(make(R0), "decimate", steps_anneal)
+    # cooling / heating exchange (paper Sec. III.B), eps tuned by short acceptance runs
+    # as in the paper; its quoted eps for this L is reported beside
+    e = make(R_dense)
+    t0 = time.perf_counter()
+    eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID, steps=200, n_hb=w["n_hb"], n_or=w["n_or"])
+    tune_s = time.perf_counter() - t0
+    r = timed(e, "coolheat", steps_plain, eps=eps)
+    r.update({"eps": eps, "eps_paper": COOLHEAT_EPS_PAPER.get(L), "tuner_s": round(tune_s, 2),
+              "tuner_acceptance": {("%g" % k): round(v, 4) for k, v in table.items()}})
+    out["coolheat_dense_ladder"] = r
     base = out["plain_dense_ladder"]
-    ratio = out["decimated_dense_ladder"]["_acc"] / np.maximum(base["_acc"], 1e-12)
-    out["decimated_dense_ladder"]["acceptance_vs_plain_same_ladder"] = {
-        "min": round(float(ratio.min()), 3), "mean": round(float(ratio.mean()), 3),
-        "max": round(float(ratio.max()), 3)}
+    for k in ("decimated_dense_ladder", "coolheat_dense_ladder"):
+        ratio = out[k]["_acc"] / np.maximum(base["_acc"], 1e-12)
+        out[k]["acceptance_vs_plain_same_ladder"] = {
+            "min": round(float(ratio.min()), 3), "mean": round(float(ratio.mean()), 3),
+            "max": round(float(ratio.max()), 3)}
     for v in out.values():
         if isinstance(v, dict):
             v.pop("_acc", None)
-    for k in ("annealed_uniform_K", "annealed_learned", "decimated_dense_ladder", "decimated_own_ladder"):
+    for k in ("annealed_uniform_K", "annealed_learned", "decimated_dense_ladder", "decimated_own_ladder",
+              "coolheat_dense_ladder"):
         out[k]["round_trips_per_gpu_s_vs_plain"] = round(
             out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12), 3)
         out[k]["accepted_swaps_per_gpu_s_vs_plain"] = round(

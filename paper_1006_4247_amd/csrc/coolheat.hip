@@ -41,10 +41,67 @@ __device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x)
 template <>
 __device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
 
+// Binary32 helpers: sine and cosine of x radians from the hardware sine/cosine in
+// turns (|error| < 1.3e-7 for |x| <= 2 pi), and the site log Jacobian as one
+// logarithm of the product of its two factors (absolute error ~1e-7 per site; the
+// sum over sites is FP64).
+__device__ __forceinline__ void sincos_hw(float x, float& s, float& c) {
+    const float t = x * 0.159154943091895336f;
+    s = __builtin_amdgcn_sinf(t);
+    c = __builtin_amdgcn_cosf(t);
+}
+
+__device__ __forceinline__ float cool_log_jac_f(float c, float k, float alpha, float sa, float ca) {
+    const float sinc = alpha < 1e-3f ? fmaf(-alpha * alpha, 1.0f / 6.0f, 1.0f) : sa / alpha;
+    return 0.693147180559945309f * __builtin_amdgcn_logf(fmaf(-k, c, 1.0f) * fmaf(-c * k, sinc, ca));
+}
+
+// Binary32 site map (same steps as the generic one below, hardware sine/cosine).
+template <bool HEAT>
+__device__ __forceinline__ double coolheat_site_f(float& sx, float& sy, float& sz, float Sx, float Sy, float Sz,
+                                                  float eps) {
+    const float nS = sqrtf(fmaf(Sz, Sz, fmaf(Sy, Sy, Sx * Sx)));
+    const float k = eps * nS;
+    if (!(k < 1.0f)) return __builtin_nan("");
+    if (nS == 0.0f) return 0.0;
+    const float Ss = fmaf(Sz, sz, fmaf(Sy, sy, Sx * sx));
+    const float px = fmaf(-Ss, sx, Sx), py = fmaf(-Ss, sy, Sy), pz = fmaf(-Ss, sz, Sz);
+    const float np = sqrtf(fmaf(pz, pz, fmaf(py, py, px * px)));
+    float alpha, c;
+    if (!HEAT) {
+        alpha = eps * np;
+        c = Ss / nS;
+    } else {
+        const float thp = atan2f(np, Ss);  // theta' in [0, pi]
+        float sn, cs;
+        sincos_hw(thp, sn, cs);
+        float th = fmaf(k, sn, thp);
+        for (int it = 0; it < 8; ++it) {
+            sincos_hw(th, sn, cs);
+            const float d = (fmaf(-k, sn, th) - thp) / fmaf(-k, cs, 1.0f);
+            th -= d;
+            if (!(fabsf(d) > 1e-7f * (1.0f + th))) break;
+        }
+        sincos_hw(th, sn, cs);
+        alpha = th - thp;
+        c = cs;
+    }
+    float sa, ca;
+    sincos_hw(alpha, sa, ca);
+    if (np > 0.0f) {
+        const float f = (HEAT ? -sa : sa) / np;
+        sx = fmaf(px, f, sx * ca);
+        sy = fmaf(py, f, sy * ca);
+        sz = fmaf(pz, f, sz * ca);
+    }
+    return static_cast<double>(cool_log_jac_f(c, k, alpha, sa, ca));
+}
+
 // One site: cool (HEAT = false) or heat s in place given the field; returns the log
 // Jacobian of cooling (at s before cooling / at the heated result), NaN if k >= 1.
 template <typename T, bool HEAT>
 __device__ __forceinline__ double coolheat_site(T& sx, T& sy, T& sz, T Sx, T Sy, T Sz, T eps) {
+    if constexpr (sizeof(T) == 4) return coolheat_site_f<HEAT>(sx, sy, sz, Sx, Sy, Sz, eps);
     const T nS = sqrt(fma(Sz, Sz, fma(Sy, Sy, Sx * Sx)));
     const T k = eps * nS;
     if (!(k < T(1))) return __builtin_nan("");

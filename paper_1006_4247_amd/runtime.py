@@ -17,12 +17,15 @@ class PTRun:
     """mode 'plain': exchange every step with `pairing` (0 = all pairs ascending);
     mode 'anneal': annealed exchange alternating even / odd pairs (schedules must be
     set on the ensembles); mode 'decimate': decimated exchange (paper Sec. III.A),
-    alternating even / odd pairs, or all pairs ascending every step if pairing == 0."""
+    alternating even / odd pairs, or all pairs ascending every step if pairing == 0;
+    mode 'coolheat': cooling / heating exchange (paper Sec. III.B) with parameter
+    `eps`, pairs as for 'decimate'."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
-                 series_len=0, tunings=None, anneal_sweep=None):
-        if mode not in ("plain", "anneal", "decimate"):
-            raise ValueError("mode must be 'plain', 'anneal' or 'decimate'")
+                 series_len=0, tunings=None, anneal_sweep=None, eps=0.0):
+        if mode not in ("plain", "anneal", "decimate", "coolheat"):
+            raise ValueError("mode must be 'plain', 'anneal', 'decimate' or 'coolheat'")
+        self.eps = float(eps)
         if pairing is None:
             pairing = 0 if mode == "plain" else -1
         if isinstance(ensembles, Ensemble):
@@ -59,6 +62,8 @@ class PTRun:
             e.swap(self.pairing)
         elif self.mode == "decimate":
             e.decimate_swap(self.pairing if self.pairing >= 0 else parity + 1)
+        elif self.mode == "coolheat":
+            e.coolheat_swap(self.eps, self.pairing if self.pairing >= 0 else parity + 1)
         else:
             e.anneal_swap(parity, *self.anneal_sweep)
         if self.measure:
@@ -104,7 +109,7 @@ class PTRun:
         inside graphs."""
         if self.series_len:
             raise RuntimeError("graph capture does not record time series (series_len must be 0)")
-        alternating = self.mode == "anneal" or (self.mode == "decimate" and self.pairing < 0)
+        alternating = self.mode == "anneal" or (self.mode in ("decimate", "coolheat") and self.pairing < 0)
         n_steps = n_steps or (2 if alternating else 1)
         torch.cuda.synchronize(self.device)
         g = torch.cuda.CUDAGraph()
@@ -188,3 +193,21 @@ def linear_schedule(betas, K):
         for k in range(1, K[i] + 1):
             lam[i, k - 1] = a + k * (b - a) / (K[i] + 1)
     return lam
+
+
+def tune_coolheat_eps(ens, grid, steps=200, n_hb=1, n_or=3):
+    """The paper's tuning of the cooling / heating parameter (Sec. III.B): short runs at
+    each eps of `grid` (in order, on the ensemble itself, so they also serve as
+    equilibration), keeping the eps with the highest mean acceptance over the ladder.
+    Returns (eps, {eps: mean acceptance})."""
+    table = {}
+    for eps in grid:
+        run = PTRun([ens], n_hb, n_or, mode="coolheat", eps=eps, measure=False)
+        st0 = ens.swap_stats.cpu().numpy().copy()
+        run.step(steps)
+        run.synchronize()
+        st = ens.swap_stats.cpu().numpy() - st0
+        acc = st[..., 1].sum(axis=(0, 1)) / np.maximum(st[..., 0].sum(axis=(0, 1)), 1)
+        table[float(eps)] = float(acc.mean())
+    best = max(table, key=table.get)
+    return best, table

@@ -4,11 +4,12 @@ FP64: the log Jacobians of both maps to 1e-9 (relative), decisions, labels, coun
 and statistics bit for bit, spins to 1e-12, energies to 1e-9, over several calls in all
 three pair orders; L <= 16 runs the LDS-resident legs, L = 20 the generic ones.
 
-FP32 (maps in binary32, Jacobians, energies and ln A in binary64): each site is moved
-once per map, like one lattice sweep, so the transformed spins meet the lattice-sweep
-bar (1e-5 per component).  From it: per site |d ln det| <= 4 k/(1-k)^2 |ds|-scale
-terms, bounded here by 4 N k_max/(1-k_max)^2 * 1e-5, and |d ln A| <= that bound for both
-maps + max(beta) * (energy bound of the candidates).  Decisions are compared where
+FP32 (maps and site log Jacobians in binary32, their sums, energies and ln A in
+binary64): each site is moved once per map, like one lattice sweep, so the transformed
+spins meet the lattice-sweep bar (1e-5 per component).  From it: per site
+|d ln det| <= 4 k/(1-k)^2 |ds|-scale terms plus ~2.4e-7 for the binary32 logarithm,
+bounded here by N (4 k_max/(1-k_max)^2 * 1e-5 + 2.4e-7), and |d ln A| <= that bound for
+both maps + max(beta) * (energy bound of the candidates).  Decisions are compared where
 |ln A - ln u| exceeds it, pair by pair with disjoint pairings.
 """
 import numpy as np
@@ -77,7 +78,7 @@ def test_coolheat_parity_fp32(L, pairing):
     wg = w.cpu().numpy()
     N = L ** 3
     bar = LATTICE_BAR["fp32"]
-    tol_ld = 4.0 * N * kmax / (1.0 - kmax) ** 2 * bar
+    tol_ld = N * (4.0 * kmax / (1.0 - kmax) ** 2 * bar + 2.4e-7)
     assert np.all(np.abs(wg - ld) <= tol_ld), (np.abs(wg - ld).max(), tol_ld)
     ebound = energy_bound(L, ref.J, np.full(ref.spins.shape[:-1], np.sqrt(3.0) * bar), "fp32")
     tol_lnA = 2.0 * tol_ld + ref.betas.max() * 2.0 * ebound.max()
@@ -165,7 +166,7 @@ def test_coolheat_full_shape_sampled_pairs():
         ldx = hsgref.coolheat(L, J[s], cx, EPS, False)
         ldy = hsgref.coolheat(L, J[s], cy, EPS, True)
         kmax = 0.6
-        tol_ld = 4.0 * N * kmax / (1.0 - kmax) ** 2 * bar
+        tol_ld = N * (4.0 * kmax / (1.0 - kmax) ** 2 * bar + 2.4e-7)
         assert abs(wg[s, c, i, 0] - ldx) <= tol_ld and abs(wg[s, c, i, 1] - ldy) <= tol_ld, (k, wg[s, c, i], ldx, ldy)
         accepted = st["stats"][s, c, i, 1] - st0["stats"][s, c, i, 1]
         if accepted:
