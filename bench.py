@@ -76,17 +76,18 @@ def resident_kernel_name(w):
 
 
 # Sources of the sweep kernel whose HBM traffic the counter summary records; the
-# summary is used only while they are unchanged.
-KERNEL_SOURCES = ["paper_1006_4247_amd/csrc/sweep_resident.hip", "paper_1006_4247_amd/csrc/hsg_device.h",
-                  "paper_1006_4247_amd/csrc/hsg_launch.h", "paper_1006_4247_amd/build.py"]
+# summary is used only while they and the compiler flags are unchanged.
+KERNEL_SOURCES = ["paper_1006_4247_amd/csrc/sweep_resident.hip", "paper_1006_4247_amd/csrc/hsg_device.h"]
 
 
 def kernel_sources_sha256():
     import hashlib
+    from paper_1006_4247_amd import build as hip_build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(repr(hip_build.FLAGS).encode())
     return h.hexdigest()
 
 
