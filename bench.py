@@ -234,6 +234,86 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     return out
 
 
+# The paper's ladders (Sec. IV): T_i = T_max (T_min/T_max)^((i-1)/(N_T-1)), one heat-bath
+# and (5/4) L overrelaxation sweeps per cycle.
+PAPER_T_MIN, PAPER_T_MAX = 0.12, 0.19
+PAPER_LADDERS = {16: dict(n_temps=15, n_or=20), 24: dict(n_temps=27, n_or=30), 32: dict(n_temps=43, n_or=40)}
+
+
+def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
+    """Standard, decimated and cooling / heating tempering on the paper's ladder for L
+    (Sec. IV), all pairs in ascending order every cycle, on the same S coupling sets
+    (fresh Gaussian sets; the paper's ten are unpublished) with 2 chains: per coupling
+    set the acceptance, the round-trip time t_R = cycles x configurations / trips
+    (Sec. IV.B) and tau_int of the overlap susceptibility at T_min (window c = 4), and
+    the per-set speed-ups over standard tempering averaged over the sets (Table II)."""
+    from paper_1006_4247_amd import analysis, runtime
+
+    cfg = PAPER_LADDERS[L]
+    R, n_or = cfg["n_temps"], cfg["n_or"]
+    i = np.arange(1, R + 1)
+    temps = PAPER_T_MAX * (PAPER_T_MIN / PAPER_T_MAX) ** ((i - 1) / (R - 1))
+    betas = 1.0 / temps
+    C = 2
+    res = {}
+    for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat")):
+        e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
+        e.init_couplings()
+        e.init_spins()
+        t0 = time.perf_counter()
+        eps, table = 0.0, None
+        runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False).step(equil // 2)
+        if mode == "coolheat":
+            eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID, steps=300, n_hb=1, n_or=n_or, pairing=0)
+        runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, measure=False).step(equil - equil // 2)
+        torch.cuda.synchronize()
+        eq_s = time.perf_counter() - t0
+        st0 = e.swap_stats.cpu().numpy().copy()
+        rt0 = e.rt_trips.cpu().numpy().copy()
+        run = runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, series_len=cycles)
+        t0 = time.perf_counter()
+        run.step(cycles)
+        run.synchronize()
+        dt = time.perf_counter() - t0
+        e.check()
+        chi, _ = run.series(0)  # [T][S][R]
+        st = e.swap_stats.cpu().numpy() - st0  # [S][C][R-1][2]
+        rt = e.rt_trips.cpu().numpy() - rt0
+        acc_set = st[..., 1].sum(axis=(1, 2)) / np.maximum(st[..., 0].sum(axis=(1, 2)), 1)  # [S]
+        acc_pair = st[..., 1].sum(axis=(0, 1)) / np.maximum(st[..., 0].sum(axis=(0, 1)), 1)  # [R-1]
+        trips = rt.sum(axis=(1, 2)).astype(np.float64)
+        t_R = cycles * C * R / np.maximum(trips, 1.0)
+        tau = np.array([analysis.tau_int(chi[:, s, R - 1], c=4.0)[0] for s in range(S)])
+        res[method] = dict(acc_set=acc_set, acc_pair=acc_pair, t_R=t_R, tau=tau, trips=trips, gpu_s=dt,
+                           eq_s=eq_s, eps=eps, table=table)
+
+    def q(a):
+        a = np.asarray(a, dtype=np.float64)
+        return {"mean": round(float(a.mean()), 4), "min": round(float(a.min()), 4),
+                "max": round(float(a.max()), 4)}
+
+    out = {"study": "paper-ladder", "L": L, "coupling_sets": S, "chains": C, "temperatures": R,
+           "T": [PAPER_T_MIN, PAPER_T_MAX], "sweep": "1 HB + %d OR" % n_or, "exchange": "all pairs ascending",
+           "cycles": cycles, "equilibration_cycles": equil, "data": "synthetic Gaussian coupling sets from Philox"}
+    std = res["standard"]
+    for m, r in res.items():
+        d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
+             "t_R_per_set": q(r["t_R"]), "round_trips": int(r["trips"].sum()),
+             "tau_int_chi_Tmin_c4": q(r["tau"]), "gpu_s": round(r["gpu_s"], 2),
+             "ms_per_cycle": round(r["gpu_s"] / cycles * 1e3, 4)}
+        if m == "coolheat":
+            d["eps"] = r["eps"]
+            d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
+            d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
+        if m != "standard":
+            d["speedup_vs_standard"] = {
+                "acceptance": round(float(np.mean(r["acc_set"] / np.maximum(std["acc_set"], 1e-12))), 3),
+                "round_trip": round(float(np.mean(std["t_R"] / r["t_R"])), 3),
+                "tau_int_chi": round(float(np.mean(std["tau"] / r["tau"])), 3)}
+        out[m] = d
+    return out
+
+
 def copy_probe(torch, mib, reps=10):
     """Plain device-to-device copy of `mib` MiB: prints the achieved bandwidth (read + write)."""
     n = mib * (1 << 20) // 4
@@ -264,6 +344,12 @@ def main():
     ap.add_argument("--no-exchange-comparison", action="store_true")
     ap.add_argument("--compare-steps", type=int, nargs=2, default=[20000, 4000], metavar=("PLAIN", "ANNEAL"),
                     help="steps of the plain dense-ladder run and of each annealed run")
+    ap.add_argument("--paper-ladder", type=int, default=0, metavar="L",
+                    help="only run the study of standard / decimated / cooling-heating tempering on "
+                         "the paper's ladder for L (16, 24 or 32) and print its JSON line")
+    ap.add_argument("--study-sets", type=int, default=64, help="coupling sets of the paper-ladder study")
+    ap.add_argument("--study-cycles", type=int, nargs=2, default=[10000, 20000], metavar=("EQUIL", "MEASURE"),
+                    help="equilibration and measurement cycles of the paper-ladder study")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM bandwidth probe and the "
                          "calibration of rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -279,6 +365,13 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)
+        return
+    if args.paper_ladder:
+        if args.paper_ladder not in PAPER_LADDERS:
+            print("--paper-ladder takes L = 16, 24 or 32", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(paper_ladder_study(torch, hsg, args.paper_ladder, args.study_sets,
+                                            args.study_cycles[1], args.study_cycles[0])), flush=True)
         return
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

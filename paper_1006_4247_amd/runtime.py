@@ -195,14 +195,14 @@ def linear_schedule(betas, K):
     return lam
 
 
-def tune_coolheat_eps(ens, grid, steps=200, n_hb=1, n_or=3):
+def tune_coolheat_eps(ens, grid, steps=200, n_hb=1, n_or=3, pairing=-1):
     """The paper's tuning of the cooling / heating parameter (Sec. III.B): short runs at
     each eps of `grid` (in order, on the ensemble itself, so they also serve as
     equilibration), keeping the eps with the highest mean acceptance over the ladder.
     Returns (eps, {eps: mean acceptance})."""
     table = {}
     for eps in grid:
-        run = PTRun([ens], n_hb, n_or, mode="coolheat", eps=eps, measure=False)
+        run = PTRun([ens], n_hb, n_or, mode="coolheat", eps=eps, measure=False, pairing=pairing)
         st0 = ens.swap_stats.cpu().numpy().copy()
         run.step(steps)
         run.synchronize()
