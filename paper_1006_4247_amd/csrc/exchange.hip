@@ -276,8 +276,8 @@ __global__ void k_anneal_copyback(hsg_ensemble e) {
 // chi = Q:Q / N (paper Sec. II); e = H/N by temperature.  Workgroup per (sample, b).
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e) {
-    __shared__ double red[NT / 64];
-    __shared__ double qs[9];
+    constexpr int NW = NT / 64;
+    __shared__ double red[9 * NW];
     const int N = e.L * e.L * e.L;
     const int R = e.n_temps, C = e.n_chains;
     const int smp = blockIdx.x / R, b = blockIdx.x % R;
@@ -288,26 +288,41 @@ __global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e) {
     if (C < 2 || e.Q == nullptr) return;  // uniform over the block
     const int s1 = (smp * C + 0) * R + label(e.slot_of_temp[(smp * C + 0) * R + b], R, e.guard);
     const int s2 = (smp * C + 1) * R + label(e.slot_of_temp[(smp * C + 1) * R + b], R, e.guard);
-    const T* a = static_cast<const T*>(e.spins) + static_cast<size_t>(s1) * 3 * N;
-    const T* c = static_cast<const T*>(e.spins) + static_cast<size_t>(s2) * 3 * N;
+    // 16-byte loads of W consecutive sites of a component (N is a multiple of 8 and
+    // every replica starts on a 16-byte boundary)
+    constexpr int W = 16 / static_cast<int>(sizeof(T));
+    struct alignas(16) Vec { T v[W]; };
+    const int NV = N / W;
+    const Vec* a = reinterpret_cast<const Vec*>(static_cast<const T*>(e.spins) + static_cast<size_t>(s1) * 3 * N);
+    const Vec* c = reinterpret_cast<const Vec*>(static_cast<const T*>(e.spins) + static_cast<size_t>(s2) * 3 * N);
     double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int x = threadIdx.x; x < N; x += NT) {
-        const double a0 = a[x], a1 = a[N + x], a2 = a[2 * N + x];
-        const double c0 = c[x], c1 = c[N + x], c2 = c[2 * N + x];
-        q[0] += a0 * c0; q[1] += a0 * c1; q[2] += a0 * c2;
-        q[3] += a1 * c0; q[4] += a1 * c1; q[5] += a1 * c2;
-        q[6] += a2 * c0; q[7] += a2 * c1; q[8] += a2 * c2;
+#pragma unroll 4  // all loads of a 16^3 replica pair issued before the first use
+    for (int v = threadIdx.x; v < NV; v += NT) {
+        const Vec a0 = a[v], a1 = a[NV + v], a2 = a[2 * NV + v];
+        const Vec c0 = c[v], c1 = c[NV + v], c2 = c[2 * NV + v];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const double x0 = a0.v[w], x1 = a1.v[w], x2 = a2.v[w];
+            const double y0 = c0.v[w], y1 = c1.v[w], y2 = c2.v[w];
+            q[0] = fma(x0, y0, q[0]); q[1] = fma(x0, y1, q[1]); q[2] = fma(x0, y2, q[2]);
+            q[3] = fma(x1, y0, q[3]); q[4] = fma(x1, y1, q[4]); q[5] = fma(x1, y2, q[5]);
+            q[6] = fma(x2, y0, q[6]); q[7] = fma(x2, y1, q[7]); q[8] = fma(x2, y2, q[8]);
+        }
     }
+    // nine sums at once: butterfly in each wave, then the waves in order
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const double t = block_sum<NT>(q[k], red);
-        if (threadIdx.x == 0) qs[k] = t;
+        const double w = wave_sum(q[k]);
+        if ((threadIdx.x & 63) == 0) red[k * NW + (threadIdx.x >> 6)] = w;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double chi = 0.0;
         for (int k = 0; k < 9; ++k) {
-            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = qs[k];
-            chi += qs[k] * qs[k];
+            double t = 0.0;
+            for (int w = 0; w < NW; ++w) t += red[k * NW + w];
+            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = t;
+            chi += t * t;
         }
         e.chi[static_cast<size_t>(smp) * R + b] = chi / static_cast<double>(N);
     }
