@@ -161,13 +161,15 @@ __device__ __forceinline__ ChItem ch_item(const hsg_ensemble& e, int b, int i0, 
 }
 
 // LDS-resident legs (L <= 16): the replica in LDS, couplings from global memory.
-template <typename T, int L>
-__global__ void __launch_bounds__(kChThreads) k_coolheat_leg_res(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+// NT threads: 256 where a launch holds many pairs, more for the single pair per
+// chain of an ascending round, whose legs then finish sooner.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, int i0, int istep, int npc) {
     constexpr int N = L * L * L, NH = N / 2;
     constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
-    __shared__ double red[kChThreads / 64];
+    __shared__ double red[NT / 64];
     const ChItem it = ch_item(e, blockIdx.x, i0, istep, npc);
     const int smp = it.ch / e.n_chains;
     const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg_res(hsg_ensemble e,
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
     uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<T*>(scr + sl.cand) + static_cast<size_t>(it.slot) * 3 * N);
     uint4* s4 = reinterpret_cast<uint4*>(sh);
-    for (int v = threadIdx.x; v < NV; v += kChThreads) s4[v] = src[v];
+    for (int v = threadIdx.x; v < NV; v += NT) s4[v] = src[v];
     __syncthreads();
     double ld = 0.0, en = 0.0;
     for (int step = 0; step < 2; ++step) {
@@ -187,7 +189,7 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg_res(hsg_ensemble e,
         T* w0 = sh + (0 * 2 + p) * NH;
         T* w1 = sh + (1 * 2 + p) * NH;
         T* w2 = sh + (2 * 2 + p) * NH;
-        for (int h = threadIdx.x; h < NH; h += kChThreads) {
+        for (int h = threadIdx.x; h < NH; h += NT) {
             const Nbr nb = neighbours<L>(h, p, L);
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
@@ -212,9 +214,9 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg_res(hsg_ensemble e,
         }
         __syncthreads();
     }
-    for (int v = threadIdx.x; v < NV; v += kChThreads) dst[v] = s4[v];
-    const double LD = block_sum<kChThreads>(ld, red);
-    const double H = -block_sum<kChThreads>(en, red);
+    for (int v = threadIdx.x; v < NV; v += NT) dst[v] = s4[v];
+    const double LD = block_sum<NT>(ld, red);
+    const double H = -block_sum<NT>(en, red);
     if (threadIdx.x == 0) {
         e.work[(static_cast<size_t>(it.ch) * (e.n_temps - 1) + it.i) * 2 + it.leg] = LD;
         reinterpret_cast<double*>(scr + sl.cand_energy)[it.slot] = H;
@@ -284,7 +286,9 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T e
 }
 
 // Decisions of the pairs i0 + istep m (m < npc) of one chain per thread; `last`
-// advances the exchange counter and the round trips (once per call).
+// advances the exchange counter and the round trips (once per call).  Entry
+// (chain, m, leg) of the flags array names the slot whose candidate replaces its
+// spins, or -1.
 __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, int last) {
     const int n_chains = e.n_samples * e.n_chains;
     const int ch = blockIdx.x * blockDim.x + threadIdx.x;
@@ -301,7 +305,7 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
     double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
     const uint32_t n = e.swap_ctr[ch];
     const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
-    for (int r = 0; r < R; ++r) flags[ch * R + r] = 0;
+    int* cp = flags + static_cast<size_t>(ch) * npc * 2;
     for (int m = 0; m < npc; ++m) {
         const int i = i0 + istep * m;
         const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
@@ -309,11 +313,12 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
         const double lnA = b1 * en[x] + b2 * en[y] - b1 * cen[ch * R + y] - b2 * cen[ch * R + x] + W[2 * i] - W[2 * i + 1];
         const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
         st[2 * i] += 1;
-        if (log(u01_52(w.w0, w.w1)) < lnA) {
+        const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
+        cp[2 * m] = ok ? x : -1;
+        cp[2 * m + 1] = ok ? y : -1;
+        if (ok) {
             en[x] = cen[ch * R + x];
             en[y] = cen[ch * R + y];
-            flags[ch * R + x] = 1;
-            flags[ch * R + y] = 1;
             sot[i] = y;
             sot[i + 1] = x;
             tos[x] = i + 1;
@@ -341,12 +346,16 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
     }
 }
 
+// Workgroup b copies candidate b of the decided pairs ((chain, m, leg) order), if
+// accepted, over the spins of its slot.
 template <typename T>
-__global__ void k_coolheat_copyback(hsg_ensemble e) {
-    const int slot = blockIdx.x;
+__global__ void k_coolheat_copyback(hsg_ensemble e, int npc) {
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    if (!reinterpret_cast<const int*>(scr + sl.flags)[slot]) return;
+    const int r = reinterpret_cast<const int*>(scr + sl.flags)[blockIdx.x];
+    if (r < 0) return;
+    const int ch = static_cast<int>(blockIdx.x) / (2 * npc);
+    const size_t slot = static_cast<size_t>(ch) * e.n_temps + r;
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
     const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
     uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
@@ -354,10 +363,10 @@ __global__ void k_coolheat_copyback(hsg_ensemble e) {
     for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
 }
 
-template <typename T, int L>
-static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
+template <typename T, int L, int NT>
+static hipError_t go_leg_nt(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
     constexpr size_t lds = 3 * L * L * L * sizeof(T);
-    auto kern = k_coolheat_leg_res<T, L>;
+    auto kern = k_coolheat_leg_res<T, L, NT>;
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
         hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -365,8 +374,21 @@ static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, in
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kChThreads), lds, st, e, eps, i0, istep, npc);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, eps, i0, istep, npc);
     return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
+    // one pair per chain: binary32 legs with 1024 threads, binary64 with 512 (its site
+    // maps need more than the 128 registers a thread of a 1024-thread workgroup gets)
+    constexpr int NH = L * L * L / 2;
+    constexpr int NTMAX = sizeof(T) == 4 ? 1024 : 512;
+    constexpr int NT1 = NH >= NTMAX ? NTMAX : ((NH + 63) / 64) * 64;
+    if constexpr (NT1 > kChThreads) {
+        if (npc == 1) return go_leg_nt<T, L, NT1>(e, eps, i0, istep, npc, blocks, st);
+    }
+    return go_leg_nt<T, L, kChThreads>(e, eps, i0, istep, npc, blocks, st);
 }
 
 template <typename T>
@@ -390,7 +412,6 @@ static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, 
 static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int istep, int npc, int last,
                                  hipStream_t st) {
     const int n_chains = e.n_samples * e.n_chains;
-    const int n_slots = n_chains * e.n_temps;
     hipError_t err = hipSuccess;
     if (npc > 0) {
         err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, st)
@@ -400,10 +421,11 @@ static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int 
     hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep, npc, last);
     err = hipGetLastError();
     if (err != hipSuccess || npc == 0) return err;
+    const int blocks = n_chains * npc * 2;
     if (e.precision == HSG_FP64)
-        hipLaunchKernelGGL(k_coolheat_copyback<double>, dim3(n_slots), dim3(256), 0, st, e);
+        hipLaunchKernelGGL(k_coolheat_copyback<double>, dim3(blocks), dim3(256), 0, st, e, npc);
     else
-        hipLaunchKernelGGL(k_coolheat_copyback<float>, dim3(n_slots), dim3(256), 0, st, e);
+        hipLaunchKernelGGL(k_coolheat_copyback<float>, dim3(blocks), dim3(256), 0, st, e, npc);
     return hipGetLastError();
 }
 

@@ -31,6 +31,26 @@ __device__ __forceinline__ double log_sinhc(double u) {
     return u + log(-expm1(-2.0 * u) / (2.0 * u));
 }
 
+// Binary32 form of a site's ln[rho(a) / rho(c)], rho(s) = expm1(-2 b2 s) / expm1(-2 b1 s)
+// (see the LDS-resident kernel; binary32 configurations): expm1(x),
+// x <= 0, by its Taylor series for x > -1, else e^x - 1 from the hardware exp2
+// (e^x <= 1/e, so the subtraction loses < 1 bit); rho as a product with the hardware
+// reciprocal; one hardware log2.  Each rho carries a relative error below ~8 ulp, so
+// the site term is off by < 1.5e-6 in absolute value (the lattice sum stays FP64).
+__device__ __forceinline__ float expm1_neg_f(float x) {
+    return x > -1.0f ? expm1_taylor(x) : __builtin_amdgcn_exp2f(1.44269504088896341f * x) - 1.0f;
+}
+
+__device__ __forceinline__ float dec_rho_f(float s, float b1, float b2, float r0) {
+    if (!(s > 0.0f)) return r0;
+    return expm1_neg_f(-2.0f * b2 * s) * __builtin_amdgcn_rcpf(expm1_neg_f(-2.0f * b1 * s));
+}
+
+__device__ __forceinline__ float dec_log_ratio_f(float a, float c, float b1, float b2, float r0) {
+    const float q = dec_rho_f(a, b1, b2, r0) * __builtin_amdgcn_rcpf(dec_rho_f(c, b1, b2, r0));
+    return 0.693147180559945309f * __builtin_amdgcn_logf(q);
+}
+
 // Local field of site h (sublattice p) from the other sublattice, in the order
 // +x, -x, +y, -y, +z, -z; the bond to -mu is stored at the neighbour.
 template <typename T>
@@ -114,6 +134,8 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
         T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
         T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
         const double b1 = e.betas[i], b2 = e.betas[i + 1];
+        const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
+        const float fr0 = static_cast<float>(b2 / b1);
 
         double acc = 0.0;
         for (int h = threadIdx.x; h < NH; h += kDecThreads) {
@@ -122,7 +144,11 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
             field<T>(sx, J, NH, h, d, nb, ax, ay, az);
             field<T>(sy, J, NH, h, d, nb, cx, cy, cz);
             const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
-            acc += (log_sinhc(b2 * a) - log_sinhc(b1 * a)) + (log_sinhc(b1 * c) - log_sinhc(b2 * c));
+            if constexpr (sizeof(T) == 4)  // the rearranged site term of the resident kernel
+                acc += fma(b2 - b1, a - c,
+                           static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0)));
+            else
+                acc += (log_sinhc(b2 * a) - log_sinhc(b1 * a)) + (log_sinhc(b1 * c) - log_sinhc(b2 * c));
         }
         const double lnA = block_sum<kDecThreads>(acc, red);
         if (threadIdx.x == 0) {
@@ -201,13 +227,16 @@ __device__ __forceinline__ double dec_rho(double s, double b1, double b2) {
     return expm1(-2.0 * b2 * s) / expm1(-2.0 * b1 * s);
 }
 
-template <typename T, int L>
-__global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimate_res(hsg_ensemble e, int pairing) {
+// NT threads: 256 for one pair per workgroup (even / odd pairs, many workgroups),
+// 1024 for one binary32 chain per workgroup (ascending pairs, each waiting for the
+// last one).
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 && NT <= 256 ? 3 : 1) k_decimate_res(hsg_ensemble e, int pairing) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
     constexpr int NVP = NH * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per plane
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* kept = reinterpret_cast<T*>(smem_raw);  // [2][3][NH]
-    __shared__ double red[kDecThreads / 64];
+    __shared__ double red[NT / 64];
     __shared__ int s_acc;
     const int R = e.n_temps, C = e.n_chains;
     int ch, i_begin, i_end;
@@ -239,11 +268,13 @@ __global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimat
         T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
         T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
         const double b1 = e.betas[i], b2 = e.betas[i + 1];
+        const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
+        const float fr0 = static_cast<float>(b2 / b1);
         {
             const uint4* srcx = reinterpret_cast<const uint4*>(sx);
             const uint4* srcy = reinterpret_cast<const uint4*>(sy);
             uint4* dst = reinterpret_cast<uint4*>(kept);
-            for (int v = threadIdx.x; v < 3 * NVP; v += kDecThreads) {
+            for (int v = threadIdx.x; v < 3 * NVP; v += NT) {
                 const int mu = v / NVP, r = v - mu * NVP;
                 const int src = (2 * mu + 1 - d) * NVP + r;
                 dst[v] = srcx[src];
@@ -252,7 +283,7 @@ __global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimat
         }
         __syncthreads();
         double lin = 0.0, lg = 0.0;
-        for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+        for (int h = threadIdx.x; h < NH; h += NT) {
             const Nbr nb = neighbours<L>(h, d, L);
             T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
 #pragma unroll
@@ -269,9 +300,12 @@ __global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimat
             }
             const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
             lin += a - c;
-            lg += log(dec_rho(a, b1, b2) / dec_rho(c, b1, b2));
+            if constexpr (sizeof(T) == 4)
+                lg += static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0));
+            else
+                lg += log(dec_rho(a, b1, b2) / dec_rho(c, b1, b2));
         }
-        const double lnA = block_sum<kDecThreads>(fma(b2 - b1, lin, lg), red);
+        const double lnA = block_sum<NT>(fma(b2 - b1, lin, lg), red);
         if (threadIdx.x == 0) {
             if (e.work) {
                 e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
@@ -298,7 +332,7 @@ __global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimat
             const uint32_t gs[2] = {e.slot_base + static_cast<uint32_t>(gx), e.slot_base + static_cast<uint32_t>(gy)};
             double en[2] = {0.0, 0.0};
             constexpr int NSITE = (sizeof(T) == 4) ? NQ : NH;  // one Philox block per site pair (binary32) or site
-            for (int q = threadIdx.x; q < NSITE; q += kDecThreads) {
+            for (int q = threadIdx.x; q < NSITE; q += NT) {
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
                     const Words w = philox(static_cast<uint32_t>(q), n, gs[r], c3, k0, k1);
@@ -335,8 +369,8 @@ __global__ void __launch_bounds__(kDecThreads, sizeof(T) == 4 ? 3 : 1) k_decimat
                     }
                 }
             }
-            const double Hx = -block_sum<kDecThreads>(en[0], red);
-            const double Hy = -block_sum<kDecThreads>(en[1], red);
+            const double Hx = -block_sum<NT>(en[0], red);
+            const double Hy = -block_sum<NT>(en[1], red);
             if (threadIdx.x == 0) {
                 e.energy[gx] = Hx;
                 e.energy[gy] = Hy;
@@ -378,10 +412,10 @@ __global__ void k_decimate_finish(hsg_ensemble e, int pairing) {
     }
 }
 
-template <typename T, int L>
-static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+template <typename T, int L, int NT>
+static hipError_t go_decimate_nt(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
     constexpr size_t lds = 2 * 3 * (L * L * L / 2) * sizeof(T);
-    auto kern = k_decimate_res<T, L>;
+    auto kern = k_decimate_res<T, L, NT>;
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
         hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -389,8 +423,15 @@ static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kDecThreads), lds, st, e, pairing);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, pairing);
     return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+    // binary64 site terms need more than the 128 registers of a 1024-thread workgroup
+    if (pairing == 0 && sizeof(T) == 4) return go_decimate_nt<T, L, 1024>(e, pairing, blocks, st);
+    return go_decimate_nt<T, L, kDecThreads>(e, pairing, blocks, st);
 }
 
 // LDS-resident variant for L <= 16 (its two kept sublattices fit one workgroup's

@@ -32,7 +32,7 @@ def _betas(R, lo=0.5, hi=3.0):
     return hsgref.geometric_betas(lo, hi, R)
 
 
-@pytest.mark.parametrize("L", [4, 6, 16, 20])
+@pytest.mark.parametrize("L", [4, 6, 12, 16, 20])
 @pytest.mark.parametrize("pairing", [0, 1, 2])
 def test_coolheat_parity_fp64(L, pairing):
     S, C, R = 2, 2, 5
@@ -106,6 +106,53 @@ def test_coolheat_parity_fp32(L, pairing):
                 if st["stats"][s, c, i, 1] == 0:
                     for slot in (sot[s, c, i], sot[s, c, i + 1]):
                         assert np.array_equal(st["spins"][s, c, slot], before[s, c, slot])
+    gpu.check()
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_coolheat_ascending_fp32(L):
+    """All pairs in ascending order (one round of legs per pair), FP32.  A
+    configuration can be mapped by several consecutive accepted pairs, so the
+    per-pair bars above are tripled.  Along each chain the pairs are compared in order
+    until the first decision binary32 cannot settle; the rest of that chain is skipped."""
+    S, C, R = 2, 3, 7
+    eps = EPS if L <= 8 else 0.006
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 400 + L, prec="fp32")
+    N = L ** 3
+    bar = LATTICE_BAR["fp32"]
+    checked = full = 0
+    for call in range(2):
+        kmax = _max_k(ref, eps)
+        tol_ld = 3.0 * N * (4.0 * kmax / (1.0 - kmax) ** 2 * bar + 2.4e-7)
+        ebound = energy_bound(L, ref.J, np.full(ref.spins.shape[:-1], 3.0 * np.sqrt(3.0) * bar), "fp32")
+        tol_lnA = 2.0 * tol_ld + ref.betas.max() * 2.0 * ebound.max()
+        n0 = ref.swap_ctr.copy()
+        stats0 = ref.stats.copy()
+        w = gpu.coolheat_swap(eps, 0)
+        lnA, ld = ref.coolheat_swap(eps, 0)
+        torch.cuda.synchronize()
+        wg = w.cpu().numpy()
+        st = gpu.host_state()
+        assert np.array_equal(st["swap_ctr"], ref.swap_ctr)
+        for s in range(S):
+            for c in range(C):
+                clean = True
+                for i in range(R - 1):
+                    if abs(lnA[s, c, i] - _log_u(ref, s * C + c, i, int(n0[s, c]))) <= tol_lnA:
+                        clean = False
+                        break
+                    checked += 1
+                    assert np.all(np.abs(wg[s, c, i] - ld[s, c, i]) <= tol_ld), (s, c, i, wg[s, c, i], ld[s, c, i])
+                    assert np.array_equal(st["stats"][s, c, i] - stats0[s, c, i], ref.stats[s, c, i] - stats0[s, c, i])
+                if clean:
+                    full += 1
+                    assert np.array_equal(st["temp_of_slot"][s, c], ref.temp_of_slot[s, c])
+                    assert np.abs(st["spins"][s, c] - ref.spins[s, c]).max() <= 3.0 * bar
+        ref.set_state(spins=st["spins"].astype(np.float64))
+        for k in ("temp_of_slot", "slot_of_temp", "stats", "rt_state", "rt_trips"):
+            getattr(ref, k)[...] = st[k]
+    assert checked >= S * C * (R - 1) and full >= S * C, (checked, full)
+    assert ref.stats[..., 1].sum() > 0
     gpu.check()
 
 

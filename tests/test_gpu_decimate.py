@@ -4,10 +4,12 @@ FP64: ln A of every pair to 1e-10 (relative), the decimated sublattice, decision
 labels, counters and statistics bit for bit, spins to 1e-12, over several calls in
 all three pair orders.
 
-FP32 (spins and fields in binary32, ln A in binary64): ln A of every pair within the
-rigorous bound of the field rounding, |d ln A| <= 2 sqrt(3) gamma_6 max(beta) sum_b |J_b|
+FP32 (spins and fields in binary32, each site's ln[rho(a)/rho(c)] in binary32 with
+the hardware exp2 / log2 / reciprocal, the lattice sum in binary64): ln A of every pair
+within the bound of the field rounding, |d ln A| <= 2 sqrt(3) gamma_6 max(beta) sum_b |J_b|
 (gamma_6 = 6u/(1-6u), u = 2^-24: six fused multiply-adds per field component; |h'| < 1
-for h(u) = ln(sinh(u)/u); every bond has one end on the decimated sublattice).  A
+for h(u) = ln(sinh(u)/u); every bond has one end on the decimated sublattice), plus
+1.5e-6 per decimated site for the binary32 site term (each rho within ~8 ulp).  A
 decision is compared where |ln A - ln u| exceeds that bound; with disjoint pairs each
 pair is then checked on its own: labels, statistics, the kept sublattice bit for bit
 and the re-inserted spins within the lattice-sweep bar.
@@ -29,6 +31,7 @@ from tests.gpu_pair import LATTICE_BAR, compare_ints, make_pair
 pytestmark = pytest.mark.gpu
 SEED = 0xDEC1
 GAMMA6 = 6 * 2.0 ** -24 / (1 - 6 * 2.0 ** -24)
+SITE_TERM_F32 = 1.5e-6  # binary32 ln[rho(a)/rho(c)] per decimated site
 
 
 def _betas(R, lo=0.5, hi=3.0):
@@ -43,7 +46,7 @@ def _log_u(ref, ch, i, n):
 def _lnA_bound(ref):
     """[S] bound on |ln A_gpu - ln A_ref| for FP32 fields (see the module docstring)."""
     sumJ = np.abs(ref.J).sum(axis=(1, 2))
-    return 2.0 * np.sqrt(3.0) * GAMMA6 * ref.betas.max() * sumJ + 1e-11 * ref.N
+    return 2.0 * np.sqrt(3.0) * GAMMA6 * ref.betas.max() * sumJ + SITE_TERM_F32 * ref.N / 2 + 1e-11 * ref.N
 
 
 @pytest.mark.parametrize("L", [4, 6, 16, 20])
@@ -116,6 +119,50 @@ def test_decimate_parity_fp32(L, pairing):
     gpu.check()
 
 
+@pytest.mark.parametrize("L", [8, 16])
+def test_decimate_ascending_fp32(L):
+    """All pairs in ascending order (one workgroup per chain), FP32: along each chain
+    the pairs are compared in order until the first decision binary32 cannot settle
+    (|ln A - ln u| within the bound); later pairs of that chain see states that may
+    legitimately differ and are skipped."""
+    S, C, R = 2, 3, 7
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 300 + L, prec="fp32")
+    bound = _lnA_bound(ref)
+    checked = full = 0
+    for call in range(2):
+        n0 = ref.swap_ctr.copy()
+        stats0 = ref.stats.copy()
+        w = gpu.decimate_swap(0)
+        lnA, role = ref.decimate_swap(0)
+        torch.cuda.synchronize()
+        wg = w.cpu().numpy()
+        st = gpu.host_state()
+        assert np.array_equal(st["swap_ctr"], ref.swap_ctr)
+        for s in range(S):
+            for c in range(C):
+                clean = True
+                for i in range(R - 1):
+                    if abs(lnA[s, c, i] - _log_u(ref, s * C + c, i, int(n0[s, c]))) <= bound[s]:
+                        clean = False
+                        break
+                    checked += 1
+                    assert int(wg[s, c, i, 1]) == role[s, c, i]
+                    assert abs(wg[s, c, i, 0] - lnA[s, c, i]) <= bound[s], (s, c, i)
+                    assert np.array_equal(st["stats"][s, c, i] - stats0[s, c, i], ref.stats[s, c, i] - stats0[s, c, i])
+                if clean:
+                    full += 1
+                    assert np.array_equal(st["temp_of_slot"][s, c], ref.temp_of_slot[s, c])
+                    d = np.abs(st["spins"][s, c] - ref.spins[s, c])
+                    assert np.quantile(d, 0.99) <= 1e-4 and d.max() <= 2e-2, (s, c, d.max())
+        # continue from the GPU's state so that the second call starts equal
+        ref.set_state(spins=st["spins"].astype(np.float64))
+        for k in ("temp_of_slot", "slot_of_temp", "stats", "rt_state", "rt_trips"):
+            getattr(ref, k)[...] = st[k]
+    assert checked >= S * C * (R - 1) and full >= S * C, (checked, full)
+    assert ref.stats[..., 1].sum() > 0
+    gpu.check()
+
+
 def test_decimate_no_selected_pair_only_advances_counters():
     gpu, ref = make_pair(4, 2, 2, _betas(2), SEED + 7, prec="fp64")
     gpu.decimate_swap(2)
@@ -144,7 +191,8 @@ def test_decimate_full_shape_sampled_pairs():
     st = gpu.host_state()
     rng = np.random.default_rng(3)
     par = np.array([hsgref.parity(L, x) for x in range(L ** 3)])
-    bound = 2.0 * np.sqrt(3.0) * GAMMA6 * betas.max() * np.abs(J).sum(axis=(1, 2)) + 1e-11 * L ** 3
+    bound = (2.0 * np.sqrt(3.0) * GAMMA6 * betas.max() * np.abs(J).sum(axis=(1, 2))
+             + SITE_TERM_F32 * L ** 3 / 2 + 1e-11 * L ** 3)
     n_acc = 0
     for k in range(8):
         s, c = int(rng.integers(S)), int(rng.integers(C))
