@@ -87,7 +87,8 @@ def kernel_sources_sha256():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    h.update(repr(hip_build.FLAGS).encode())
+    # the flags without the include directory, whose absolute path differs between hosts
+    h.update(repr([f for f in hip_build.FLAGS if not f.startswith("-I")]).encode())
     return h.hexdigest()
 
 
