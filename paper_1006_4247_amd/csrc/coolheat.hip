@@ -367,13 +367,8 @@ template <typename T, int L, int NT>
 static hipError_t go_leg_nt(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
     constexpr size_t lds = 3 * L * L * L * sizeof(T);
     auto kern = k_coolheat_leg_res<T, L, NT>;
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+    if (a != hipSuccess) return a;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, eps, i0, istep, npc);
     return hipGetLastError();
 }

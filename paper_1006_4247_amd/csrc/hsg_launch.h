@@ -9,6 +9,9 @@ namespace hsg {
 
 // Largest dynamic LDS a workgroup may use on this device (bytes).
 size_t max_block_lds();
+// Allows `kern` more than 64 KiB of dynamic LDS on the current device (once per
+// kernel and device; thread-safe).
+hipError_t allow_dynamic_lds(const void* kern, size_t lds);
 
 // LDS-resident path: true if one replica of `e` fits in a workgroup's LDS and
 // an instantiation for e.L exists.

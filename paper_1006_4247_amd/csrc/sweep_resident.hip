@@ -8,6 +8,10 @@
 // of one sublattice never interact (paper Sec. III.A), so a half-sweep is one
 // barrier-separated LDS pass; the energy H = -sum_{x in p} s_x.S_x is fused
 // into the last half-sweep of each sweep (every bond has one end in p).
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "hsg_device.h"
 #include "hsg_launch.h"
 
@@ -486,28 +490,75 @@ static int default_threads(int L) {
     return nt;
 }
 
-size_t max_block_lds() {
-    static size_t cached = 0;
-    if (cached == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cached = prop.sharedMemPerBlock;
-        if (cached == 0) cached = 65536;
-    }
-    return cached;
+// Per-device launch facts, filled on first use under a lock (the library may be
+// called from several host threads and on several devices).
+namespace {
+struct DeviceFacts {
+    size_t max_lds = 0;
+    int cus = 0;
+};
+std::mutex g_facts_mu;
+std::map<int, DeviceFacts> g_facts;
+std::map<std::pair<const void*, int>, int> g_kernel_ok;  // (kernel, device) -> blocks per CU
+
+int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    return dev;
 }
 
-static int num_cus() {
-    static int cached = 0;
-    if (cached == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cached = prop.multiProcessorCount;
-        if (cached <= 0) cached = 256;
+DeviceFacts device_facts() {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lock(g_facts_mu);
+    auto it = g_facts.find(dev);
+    if (it != g_facts.end()) return it->second;
+    DeviceFacts f;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        f.max_lds = prop.sharedMemPerBlock;
+        f.cus = prop.multiProcessorCount;
     }
-    return cached;
+    if (f.max_lds == 0) f.max_lds = 65536;
+    if (f.cus <= 0) f.cus = 256;
+    g_facts[dev] = f;
+    return f;
+}
+}  // namespace
+
+size_t max_block_lds() { return device_facts().max_lds; }
+
+static int num_cus() { return device_facts().cus; }
+
+hipError_t allow_dynamic_lds(const void* kern, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    const std::pair<const void*, int> key(kern, current_device());
+    std::lock_guard<std::mutex> lock(g_facts_mu);
+    if (g_kernel_ok.count(key)) return hipSuccess;
+    const hipError_t a = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(lds));
+    if (a == hipSuccess) g_kernel_ok[key] = 0;
+    return a;
+}
+
+// Workgroups of `kern` (NT threads, lds bytes) resident per CU, queried once per
+// device (not per launch, so that launches can be captured into graphs without
+// host-side queries in between).
+static hipError_t blocks_per_cu(const void* kern, int nt, size_t lds, int* out) {
+    hipError_t a = allow_dynamic_lds(kern, lds);
+    if (a != hipSuccess) return a;
+    const std::pair<const void*, int> key(kern, current_device());
+    std::lock_guard<std::mutex> lock(g_facts_mu);
+    auto it = g_kernel_ok.find(key);
+    if (it != g_kernel_ok.end() && it->second > 0) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int pc = 0;
+    a = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, nt, lds);
+    pc = (a != hipSuccess || pc < 1) ? 1 : pc;
+    g_kernel_ok[key] = pc;
+    *out = pc;
+    return hipSuccess;
 }
 
 template <typename T, int L, int NT>
@@ -516,20 +567,9 @@ static hipError_t go_persist(const hsg_ensemble& e, int n_sweeps, int n_hb, int 
     const size_t lds = 2 * 3 * N * sizeof(T);
     const int n_tasks = e.n_samples * e.n_chains * e.n_temps;
     auto kern = k_resident_persist<T, L, NT>;
-    // attribute and occupancy are queried once per instance (not per launch, so that
-    // launches can be captured into graphs without host-side queries in between)
-    static int per_cu = 0;
-    if (per_cu == 0) {
-        if (lds > 65536) {
-            hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               static_cast<int>(lds));
-            if (a != hipSuccess) return a;
-        }
-        int pc = 0;
-        hipError_t a = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(kern), NT, lds);
-        per_cu = (a != hipSuccess || pc < 1) ? 1 : pc;
-    }
+    int per_cu = 1;
+    hipError_t a = blocks_per_cu(reinterpret_cast<const void*>(kern), NT, lds, &per_cu);
+    if (a != hipSuccess) return a;
     int grid = num_cus() * per_cu;
     if (grid > n_tasks) grid = n_tasks;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, n_tasks);
@@ -550,14 +590,8 @@ static hipError_t go(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, in
         blocks = chains * ((R - parity) / 2) * 2;
     if (blocks <= 0) return hipSuccess;
     auto kern = k_resident<T, L, NT>;
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+    if (a != hipSuccess) return a;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, anneal,
                        parity);
     return hipGetLastError();
