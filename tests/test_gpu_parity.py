@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import inputs
-from gpu_pair import LATTICE_BAR, compare_states, make_pair, snapshot
+from gpu_pair import COMPOSITE_BASE, COMPOSITE_MAX, LATTICE_BAR, compare_states, energy_bound, make_pair, snapshot
 from oracle import hsgref
 
 import paper_1006_4247_amd as hsg
@@ -104,7 +104,7 @@ def test_multi_sweep_launch_equals_repeated_launches(prec, path):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("L,nt,rb", [(4, 64, 1), (8, 128, 4), (10, 64, 1), (16, 256, 2),
-                                     (24, 256, 1), (24, 256, 2), (32, 256, 4)])
+                                     (24, 256, 1), (24, 256, 2), (32, 256, 4), (64, 256, 1)])
 @pytest.mark.parametrize("kind", ["hb", "or", "hb+3or"])
 def test_sweep_parity_streaming(L, nt, rb, prec, kind):
     S, C, R = 1, 2, 2
@@ -118,6 +118,43 @@ def test_sweep_parity_streaming(L, nt, rb, prec, kind):
     compare_states(gpu, ref, prec, mode="composite" if kind == "hb+3or" else "lattice",
                    before=before, n_hb=n_hb, n_or=n_or,
                    what="L=%d %s streaming %s" % (L, prec, kind))
+
+
+def test_sweep_full_shape_sampled_replicas():
+    """The benchmark's workload and launch (L = 16, 64 samples x 2 chains x 24
+    temperatures, FP32, LDS-resident kernel with 512 threads per replica), one sweep of
+    1 HB + 3 OR: sampled replicas recomputed by the oracle one at a time from the GPU's
+    own state before the launch (same counters, binary32 uniforms), to the composite
+    bars; the fused energy of every sampled replica against the oracle's energy of the
+    GPU's final configuration, within the rounding bound."""
+    L, S, C, R = 16, 64, 2, 24
+    seed = 0x100642470002
+    betas = hsgref.geometric_betas(1.0, 8.0, R)
+    gpu = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
+    gpu.init_couplings()
+    gpu.init_spins()
+    gpu.sweep(3, 1, 3)
+    gpu.swap(0)
+    torch.cuda.synchronize()
+    st0 = gpu.host_state()
+    J = gpu.couplings_natural()
+    gpu.sweep(1, 1, 3)
+    torch.cuda.synchronize()
+    st = gpu.host_state()
+    assert np.array_equal(st["sweep_ctr"], st0["sweep_ctr"] + 1)
+    rng = np.random.default_rng(12)
+    picks = [(0, 0, 0), (S - 1, C - 1, R - 1)] + [tuple(int(v) for v in rng.integers((S, C, R))) for _ in range(6)]
+    for s, c, r in picks:
+        slot = (s * C + c) * R + r
+        x = st0["spins"][s, c, r].astype(np.float64).copy()
+        beta = betas[st0["temp_of_slot"][s, c, r]]
+        hsgref.sweep(L, J[s], x, 1, 3, beta, seed, slot, int(st0["sweep_ctr"][s, c, r]), rng32=True)
+        d = np.abs(st["spins"][s, c, r] - x)
+        assert np.quantile(d, 0.99) <= COMPOSITE_BASE["fp32"] * 27 and d.max() <= COMPOSITE_MAX["fp32"], (s, c, r, d.max())
+        Hg = hsgref.energy(L, J[s], st["spins"][s, c, r].astype(np.float64))
+        bound = energy_bound(L, J[s][None], np.zeros((1, 1, 1, L ** 3)), "fp32")[0, 0, 0]
+        assert abs(st["energy"][s, c, r] - Hg) <= bound, (s, c, r, st["energy"][s, c, r], Hg, bound)
+    gpu.check()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
