@@ -257,24 +257,36 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
     betas = 1.0 / temps
     C = 2
     res = {}
+
+    def steps(run, n, what, chunk=2000):
+        # in chunks, with a progress line after each (long studies run for minutes)
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            run.step(k)
+            run.synchronize()
+            done += k
+            print("[paper-ladder L=%d] %s %d/%d" % (L, what, done, n), file=sys.stderr, flush=True)
+
     for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat")):
         e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
         e.init_couplings()
         e.init_spins()
         t0 = time.perf_counter()
         eps, table = 0.0, None
-        runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False).step(equil // 2)
+        steps(runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False), equil // 2,
+              method + " equilibration (plain)")
         if mode == "coolheat":
             eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID, steps=300, n_hb=1, n_or=n_or, pairing=0)
-        runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, measure=False).step(equil - equil // 2)
+        steps(runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, measure=False), equil - equil // 2,
+              method + " equilibration")
         torch.cuda.synchronize()
         eq_s = time.perf_counter() - t0
         st0 = e.swap_stats.cpu().numpy().copy()
         rt0 = e.rt_trips.cpu().numpy().copy()
         run = runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, series_len=cycles)
         t0 = time.perf_counter()
-        run.step(cycles)
-        run.synchronize()
+        steps(run, cycles, method)
         dt = time.perf_counter() - t0
         e.check()
         chi, _ = run.series(0)  # [T][S][R]
