@@ -158,9 +158,9 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
         e.init_spins()
         return e
 
-    def timed(e, mode, steps, warm=300, eps=0.0):
+    def timed(e, mode, steps, eps=0.0):
         run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode, eps=eps)
-        run.step(warm)
+        run.step(max(300, steps // 10))  # equilibration, also of the round-trip state
         run.capture()
         run.synchronize()
         st0 = e.swap_stats.cpu().numpy().copy()
@@ -178,6 +178,8 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
                 "acceptance_min": round(float(acc.min()), 4), "acceptance_mean": round(float(acc.mean()), 4),
                 "accepted_swaps_per_gpu_s": round(float(st[..., 1].sum()) / dt, 1),
                 "round_trips": int(rt.sum()), "round_trips_per_gpu_s": round(float(rt.sum()) / dt, 2),
+                # counting error of the round trips (Poisson)
+                "round_trips_per_gpu_s_err": round(float(np.sqrt(max(rt.sum(), 1))) / dt, 2),
                 "_acc": acc}
 
     out = {"lattice": "L=%d, %d samples x %d chains, beta %.1f..%.1f" % (L, S, C, bmin, bmax)}
@@ -228,8 +230,11 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
             v.pop("_acc", None)
     for k in ("annealed_uniform_K", "annealed_learned", "decimated_dense_ladder", "decimated_own_ladder",
               "coolheat_dense_ladder"):
-        out[k]["round_trips_per_gpu_s_vs_plain"] = round(
-            out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12), 3)
+        ratio = out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12)
+        out[k]["round_trips_per_gpu_s_vs_plain"] = round(ratio, 3)
+        # relative counting errors of the two round-trip counts, added in quadrature
+        rel = np.sqrt(1.0 / max(out[k]["round_trips"], 1) + 1.0 / max(base["round_trips"], 1))
+        out[k]["round_trips_per_gpu_s_vs_plain_err"] = round(ratio * rel, 3)
         out[k]["accepted_swaps_per_gpu_s_vs_plain"] = round(
             out[k]["accepted_swaps_per_gpu_s"] / max(base["accepted_swaps_per_gpu_s"], 1e-12), 4)
     return out
@@ -355,7 +360,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exchange-comparison", action="store_true")
-    ap.add_argument("--compare-steps", type=int, nargs=2, default=[20000, 4000], metavar=("PLAIN", "ANNEAL"),
+    ap.add_argument("--compare-steps", type=int, nargs=2, default=[40000, 4000], metavar=("PLAIN", "ANNEAL"),
                     help="steps of the plain dense-ladder run and of each annealed run")
     ap.add_argument("--paper-ladder", type=int, default=0, metavar="L",
                     help="only run the study of standard / decimated / cooling-heating tempering on "
