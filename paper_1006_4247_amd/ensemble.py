@@ -207,6 +207,70 @@ class Ensemble:
     def check(self):
         _abi.check(_abi.lib().hsg_check(ctypes.byref(self.desc), 1, self._stream()))
 
+    # ------------------------------------------------------------ checkpoint / resume
+    # Every random number is a Philox block addressed by (site, sweep or exchange
+    # counter, slot or chain, tag) under the seed, and the counters live in the state
+    # arrays, so a run resumed from a checkpoint continues bit for bit as if it had
+    # never stopped.
+    _STATE = ["spins", "couplings", "betas", "temp_of_slot", "slot_of_temp", "energy", "sweep_ctr",
+              "swap_ctr", "swap_stats", "rt_state", "rt_trips", "guard", "anneal_K", "work", "Q",
+              "chi", "e_temp"]
+
+    def meta(self):
+        d = self.desc
+        return {"L": self.L, "n_samples": self.S, "n_chains": self.C, "n_temps": self.R,
+                "seed": self.seed, "precision": self.precision, "sample_base": int(d.sample_base),
+                "chain_base": int(d.chain_base), "slot_base": int(d.slot_base), "K_max": self.K_max,
+                "use_lambda": bool(self._use_lambda)}
+
+    def state_dict(self):
+        """Host copies of every state array (device layout) and the shape metadata."""
+        st = {k: getattr(self, k).detach().cpu().clone() for k in self._STATE}
+        if self.anneal_lambda is not None:
+            st["anneal_lambda"] = self.anneal_lambda.detach().cpu().clone()
+        return {"meta": self.meta(), "tensors": st}
+
+    def load_state_dict(self, sd):
+        m = sd["meta"]
+        mine = self.meta()
+        for k in ("L", "n_samples", "n_chains", "n_temps", "precision", "K_max"):
+            if m[k] != mine[k]:
+                raise ValueError("checkpoint %s = %r does not match this ensemble's %r" % (k, m[k], mine[k]))
+        t = sd["tensors"]
+        for k in self._STATE:
+            getattr(self, k).copy_(t[k].to(self.device))
+        if self.anneal_lambda is not None and "anneal_lambda" in t:
+            self.anneal_lambda.copy_(t["anneal_lambda"].to(self.device))
+        self._use_lambda = bool(m.get("use_lambda", False))
+        self.seed = int(m["seed"])
+        d = self.desc
+        d.seed = self.seed
+        d.sample_base, d.chain_base, d.slot_base = m["sample_base"], m["chain_base"], m["slot_base"]
+        self._fill_desc()
+
+    def save(self, path):
+        """Checkpoint to a safetensors file (tensors; metadata as JSON in its header)."""
+        import json
+        from safetensors.torch import save_file
+        sd = self.state_dict()
+        save_file({k: v.contiguous() for k, v in sd["tensors"].items()}, path,
+                  metadata={"hsg_meta": json.dumps(sd["meta"])})
+
+    @classmethod
+    def load(cls, path, device="cuda", stream=None):
+        """A new ensemble holding the state saved by save()."""
+        import json
+        from safetensors import safe_open
+        with safe_open(path, framework="pt") as f:
+            m = json.loads(f.metadata()["hsg_meta"])
+            tensors = {k: f.get_tensor(k) for k in f.keys()}
+        betas = tensors["betas"].double().numpy()
+        e = cls(m["L"], m["n_samples"], m["n_chains"], betas, m["seed"], precision=m["precision"],
+                device=device, sample_base=m["sample_base"], chain_base=m["chain_base"],
+                slot_base=m["slot_base"], K_max=m["K_max"], stream=stream)
+        e.load_state_dict({"meta": m, "tensors": tensors})
+        return e
+
     # ------------------------------------------------------------ host views (tests, I/O)
     def spins_natural(self):
         return device_to_natural(self.spins.detach().cpu().double().numpy(), self.L)

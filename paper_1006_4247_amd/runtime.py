@@ -133,6 +133,35 @@ class PTRun:
             if self.graph_steps % 2 == 1:
                 self.parity ^= 1
 
+    # ------------------------------------------------------------ checkpoint / resume
+    def save(self, prefix):
+        """Checkpoint every size class (prefix + '.<i>.safetensors') and the run's own
+        position (which parity the alternating exchanges take next) in prefix + '.json'."""
+        import json
+        self.synchronize()
+        for i, e in enumerate(self.ens):
+            e.save("%s.%d.safetensors" % (prefix, i))
+        with open(prefix + ".json", "w") as fh:
+            json.dump({"parity": self.parity, "steps_done": self.steps_done, "n_classes": len(self.ens),
+                       "mode": self.mode, "pairing": self.pairing, "n_hb": self.n_hb, "n_or": self.n_or,
+                       "eps": self.eps}, fh)
+
+    def restore(self, prefix):
+        """Load the state written by save() into this run's ensembles (same shapes)."""
+        import json
+        from safetensors import safe_open
+        with open(prefix + ".json") as fh:
+            pos = json.load(fh)
+        if pos["n_classes"] != len(self.ens):
+            raise ValueError("checkpoint holds %d size classes, this run %d" % (pos["n_classes"], len(self.ens)))
+        for i, e in enumerate(self.ens):
+            with safe_open("%s.%d.safetensors" % (prefix, i), framework="pt") as f:
+                m = json.loads(f.metadata()["hsg_meta"])
+                e.load_state_dict({"meta": m, "tensors": {k: f.get_tensor(k) for k in f.keys()}})
+        self.parity = int(pos["parity"])
+        self.steps_done = int(pos["steps_done"])
+        self.synchronize()
+
     # ------------------------------------------------------------ results
     def synchronize(self):
         torch.cuda.synchronize(self.device)
