@@ -332,6 +332,56 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
     return out
 
 
+# The uneven batch: five size classes, one geometric ladder beta 1..8 each, 424 MB of
+# FP32 spins in all (more than the 256 MB MALL, so the sweeps' bytes come from HBM).
+UNEVEN = dict(Ls=[8, 12, 16, 24, 32], samples=[128, 64, 32, 16, 8], temps=[8, 12, 16, 24, 32],
+              seed=0x100642470004)
+
+
+def uneven_study(torch, hsg, steps, warm=20):
+    """Steps of the uneven batch (sweep 1 HB + 3 OR, plain exchange, measurement per
+    class, the classes on their own streams) replayed from a HIP graph: site updates per
+    ns over the batch, and the algorithmic HBM bytes of its sweeps per second (LDS-resident
+    classes: the parity-1 half of every replica read and all of it written once per
+    sweep, couplings once; streaming classes, one launch per half-sweep: per half-sweep
+    the updated half read and written and the other half read, couplings once per
+    sample)."""
+    from paper_1006_4247_amd import runtime
+    ens = runtime.uneven_batch(UNEVEN["Ls"], UNEVEN["samples"], UNEVEN["temps"], UNEVEN["seed"])
+    for e in ens:
+        e.init_couplings()
+        e.init_spins()
+    run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0)
+    run.step(warm)
+    run.capture()
+    run.replay(warm)
+    run.synchronize()
+    t0 = time.perf_counter()
+    run.replay(steps)
+    run.synchronize()
+    dt = time.perf_counter() - t0
+    run.check()
+    upd = run.site_updates_per_step() * steps
+    nbytes = 0
+    classes = []
+    for e in ens:
+        N, slots = e.N, e.n_slots
+        resident = e.L <= 16
+        if resident:  # one launch per sweep
+            b = slots * (3 * (N // 2) * 4 + 3 * N * 4) + e.S * 3 * N * 4
+        else:  # 8 half-sweeps, each reading the whole replica and writing half of it
+            b = 8 * (slots * (3 * N * 4 + 3 * (N // 2) * 4) + e.S * 3 * N * 4)
+        nbytes += b * steps
+        classes.append({"L": e.L, "samples": e.S, "temperatures": e.R, "path": "resident" if resident else "streaming",
+                        "spin_MB": round(slots * 3 * N * 4 / 1e6, 1)})
+    gbs = nbytes / dt / 1e9
+    return {"study": "uneven-batch", "classes": classes, "chains": 2, "steps": steps,
+            "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
+            "site_updates_per_ns": round(upd / dt / 1e9, 2), "ms_per_step": round(dt / steps * 1e3, 4),
+            "sweep_algorithmic_hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % UNEVEN["seed"]}
+
+
 def copy_probe(torch, mib, reps=10):
     """Plain device-to-device copy of `mib` MiB: prints the achieved bandwidth (read + write)."""
     n = mib * (1 << 20) // 4
@@ -368,6 +418,9 @@ def main():
     ap.add_argument("--study-sets", type=int, default=64, help="coupling sets of the paper-ladder study")
     ap.add_argument("--study-cycles", type=int, nargs=2, default=[10000, 20000], metavar=("EQUIL", "MEASURE"),
                     help="equilibration and measurement cycles of the paper-ladder study")
+    ap.add_argument("--uneven", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS steps of the uneven batch (five size classes, 424 MB of "
+                         "spins) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM bandwidth probe and the "
                          "calibration of rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -383,6 +436,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)
+        return
+    if args.uneven:
+        print(json.dumps(uneven_study(torch, hsg, args.uneven)), flush=True)
         return
     if args.paper_ladder:
         if args.paper_ladder not in PAPER_LADDERS:
