@@ -109,10 +109,20 @@ def measured_traffic(workload):
     return None
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
-    from oracle import hsgref
-    S = min(2, w["S"])
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(hsgref, w, S, budget_s):
+    """Steps of the oracle on S samples of the workload for about budget_s seconds:
+    (site updates per ns, steps, seconds)."""
     betas = hsgref.geometric_betas(w["bmin"], w["bmax"], w["R"])
     ens = hsgref.RefEnsemble(w["L"], S, w["C"], betas, w["seed"], prec=w["prec"])
     ens.init_couplings()
@@ -122,16 +132,33 @@ def cpu_baseline(w, budget_s):
     t0 = time.perf_counter()
     while True:
         ens.sweep(1, w["n_hb"], w["n_or"])
-        ens.swap(0)
         ens.measure()
+        ens.swap(0)
         n += 1
         dt = time.perf_counter() - t0
         if dt >= budget_s or n >= 100000:
             break
-    return {"value": n * per / dt / 1e9, "unit": "site-updates/ns",
-            "cores": int(hsgref.lib().hsgref_num_threads()), "kind": "oracle",
-            "sample": "%d of %d samples x %d chains x %d temps, L=%d, %d steps (sweep + exchange + "
-                      "measurement), %.1f s" % (S, w["S"], w["C"], w["R"], w["L"], n, dt)}
+    return n * per / dt / 1e9, n, dt
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: on every host
+    thread (the reported value) and on one thread."""
+    from oracle import hsgref
+    S = min(2, w["S"])
+    threads = int(hsgref.lib().hsgref_num_threads())
+    v, n, dt = _time_oracle(hsgref, w, S, budget_s)
+    hsgref.lib().hsgref_set_num_threads(1)
+    try:
+        v1, n1, dt1 = _time_oracle(hsgref, w, 1, budget_s / 3.0)
+    finally:
+        hsgref.lib().hsgref_set_num_threads(threads)
+    return {"value": v, "unit": "site-updates/ns", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d samples x %d chains x %d temps, L=%d, %d steps (sweep + measurement + "
+                      "exchange), %.1f s" % (S, w["S"], w["C"], w["R"], w["L"], n, dt),
+            "value_one_thread": v1,
+            "sample_one_thread": "1 sample, %d steps, %.1f s" % (n1, dt1),
+            "cpu": _cpu_model()}
 
 
 def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):

@@ -970,3 +970,14 @@ int hsgref_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops from now on (n >= 1); the timing of a reference run
+ * on one thread uses it. */
+void hsgref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

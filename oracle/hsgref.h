@@ -97,6 +97,8 @@ void hsgref_measure_batch(int L, int S, int C, int R, const double* spins, const
 void hsgref_roundtrip_update(int R, const int32_t* temp_of_slot, int32_t* rt_state,
                              int64_t* rt_trips);
 int  hsgref_num_threads(void);
+/* Threads of the parallel loops from now on (n >= 1). */
+void hsgref_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -85,6 +85,7 @@ def lib():
                                             _dp, _dp]),
             "hsgref_roundtrip_update": (None, [_c_int, _i32p, _i32p, _i64p]),
             "hsgref_num_threads": (_c_int, []),
+            "hsgref_set_num_threads": (None, [_c_int]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
