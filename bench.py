@@ -257,13 +257,14 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
             v.pop("_acc", None)
     for k in ("annealed_uniform_K", "annealed_learned", "decimated_dense_ladder", "decimated_own_ladder",
               "coolheat_dense_ladder"):
-        ratio = out[k]["round_trips_per_gpu_s"] / max(base["round_trips_per_gpu_s"], 1e-12)
-        out[k]["round_trips_per_gpu_s_vs_plain"] = round(ratio, 3)
-        # relative counting errors of the two round-trip counts, added in quadrature
-        rel = np.sqrt(1.0 / max(out[k]["round_trips"], 1) + 1.0 / max(base["round_trips"], 1))
-        out[k]["round_trips_per_gpu_s_vs_plain_err"] = round(ratio * rel, 3)
         out[k]["accepted_swaps_per_gpu_s_vs_plain"] = round(
             out[k]["accepted_swaps_per_gpu_s"] / max(base["accepted_swaps_per_gpu_s"], 1e-12), 4)
+    # Round trips on these ladders take far longer than these runs (beta 1..8 spans the
+    # whole low-temperature phase), so the counts above describe the approach to steady
+    # state, not its rate; steady-state round-trip times per GPU-second come from the
+    # paper-ladder study (--paper-ladder L).
+    out["round_trips_note"] = ("transient counts: each run is short against the round-trip time of its "
+                               "ladder; steady-state round-trip speed-ups are in the paper-ladder study")
     return out
 
 
@@ -351,10 +352,14 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
             d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
         if m != "standard":
+            cost = (r["gpu_s"] / cycles) / (std["gpu_s"] / cycles)  # GPU time per cycle vs standard
             d["speedup_vs_standard"] = {
                 "acceptance": round(float(np.mean(r["acc_set"] / np.maximum(std["acc_set"], 1e-12))), 3),
                 "round_trip": round(float(np.mean(std["t_R"] / r["t_R"])), 3),
-                "tau_int_chi": round(float(np.mean(std["tau"] / r["tau"])), 3)}
+                "tau_int_chi": round(float(np.mean(std["tau"] / r["tau"])), 3),
+                # the same per GPU-second: per-cycle speed-ups over the relative cost of a cycle
+                "round_trip_per_gpu_s": round(float(np.mean(std["t_R"] / r["t_R"])) / cost, 3),
+                "tau_int_chi_per_gpu_s": round(float(np.mean(std["tau"] / r["tau"])) / cost, 3)}
         out[m] = d
     return out
 
@@ -437,7 +442,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exchange-comparison", action="store_true")
-    ap.add_argument("--compare-steps", type=int, nargs=2, default=[40000, 4000], metavar=("PLAIN", "ANNEAL"),
+    ap.add_argument("--compare-steps", type=int, nargs=2, default=[20000, 4000], metavar=("PLAIN", "ANNEAL"),
                     help="steps of the plain dense-ladder run and of each annealed run")
     ap.add_argument("--paper-ladder", type=int, default=0, metavar="L",
                     help="only run the study of standard / decimated / cooling-heating tempering on "

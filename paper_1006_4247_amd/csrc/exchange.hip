@@ -148,14 +148,19 @@ __device__ __forceinline__ double swap_uniform(const hsg_ensemble& e, int i, uin
 
 // Eq. (1): accept iff ln u < (beta_{i+1} - beta_i)(H_{i+1} - H_i).  One wave per
 // chain: labels and energies are staged in LDS and every pair's uniform and its
-// logarithm are computed in parallel; one lane then takes the decisions in pair
-// order (each pair sees the labels the previous pair left), and the wave writes
-// labels, statistics and round-trip state back in parallel.
+// logarithm are computed in parallel.  Even or odd pairs are disjoint: each lane
+// decides its own.  In ascending order pair i sees at temperature i the
+// configuration the previous pair left there (the "carry": the one it moved up, or
+// the one it kept), and at i + 1 the configuration that was there before the pass;
+// so the per-pair inputs (ln u, the beta step, the upper configuration and its
+// energy) are all staged in parallel and one lane runs the carry through the pairs
+// with no load that depends on an earlier decision.  The wave then writes labels,
+// statistics and round-trip state back in parallel.
 constexpr int kSwapMaxR = 256;
 
 __global__ void __launch_bounds__(64) k_swap(hsg_ensemble e, int pairing) {
-    __shared__ int s_sot[kSwapMaxR], s_tos[kSwapMaxR];
-    __shared__ double s_en[kSwapMaxR], s_lu[kSwapMaxR], s_db[kSwapMaxR];
+    __shared__ int s_sot[kSwapMaxR], s_tos[kSwapMaxR], s_up[kSwapMaxR];
+    __shared__ double s_en[kSwapMaxR], s_lu[kSwapMaxR], s_db[kSwapMaxR], s_eup[kSwapMaxR];
     __shared__ unsigned char s_acc[kSwapMaxR];
     const int ch = blockIdx.x;
     const int lane = threadIdx.x;
@@ -177,8 +182,30 @@ __global__ void __launch_bounds__(64) k_swap(hsg_ensemble e, int pairing) {
         s_acc[i] = sel ? 2 : 0;  // 2 = attempted, 3 = accepted
     }
     __syncthreads();
-    if (lane == 0) {
-        for (int i = 0; i < R - 1; ++i) {
+    if (pairing == 0) {
+        for (int i = lane; i < R - 1; i += 64) {  // the configuration above pair i before the pass
+            s_up[i] = s_sot[i + 1];
+            s_eup[i] = s_en[s_sot[i + 1]];
+        }
+        __syncthreads();
+        if (lane == 0) {
+            int carry = s_sot[0];
+            double ec = s_en[carry];
+            for (int i = 0; i < R - 1; ++i) {
+                const int y = s_up[i];
+                const double ey = s_eup[i];
+                const bool ok = s_lu[i] < s_db[i] * (ey - ec);
+                s_sot[i] = ok ? y : carry;
+                s_acc[i] = ok ? 3 : 2;
+                if (!ok) {
+                    carry = y;
+                    ec = ey;
+                }
+            }
+            s_sot[R - 1] = carry;
+        }
+    } else {
+        for (int i = lane; i < R - 1; i += 64) {  // disjoint pairs
             if (!s_acc[i]) continue;
             const int x = s_sot[i], y = s_sot[i + 1];
             if (s_lu[i] < s_db[i] * (s_en[y] - s_en[x])) {
