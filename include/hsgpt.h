@@ -115,7 +115,9 @@ typedef struct hsg_tuning {
     int32_t path;           /* 0 auto (3 if a replica fits in one workgroup's LDS, else 2);
                                1 LDS-resident lattice on persistent double-buffered
                                workgroups; 2 streaming half-sweeps; 3 LDS-resident lattice,
-                               one workgroup per replica */
+                               one workgroup per replica; 4 wavefront: one workgroup per
+                               replica walking its z-planes, one HBM pass per lattice
+                               sweep (L 18..40 binary32, 18..28 binary64) */
     int32_t block_threads;  /* threads per workgroup */
     int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */
     int32_t reserved;

@@ -25,6 +25,12 @@ bool persistent_supported(const hsg_ensemble& e);
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
                            int parity, int block_threads, hipStream_t st);
 
+// Wavefront path: one workgroup per replica walking its z-planes, one HBM pass per
+// lattice sweep (L = 18 .. 40 in binary32, .. 28 in binary64, LDS permitting); a
+// tuning option, slower than the streaming path where measured.
+bool wave_supported(const hsg_ensemble& e);
+hipError_t launch_wave_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st);
+
 // Streaming path: one launch per half-sweep, any even L.
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
                                 int block_threads, int replicas_per_block, hipStream_t st);

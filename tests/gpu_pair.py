@@ -69,7 +69,13 @@ def energy_bound(L, J, ds, prec):
 
 def _ill_conditioned_sites(ref_before, ref, s, c, r, n_hb, n_or):
     """Sites whose oracle field is ill-conditioned when they are updated, replaying the
-    oracle's own half-sweeps of slot (s, c, r) from its state before the call."""
+    oracle's own half-sweeps of slot (s, c, r) from its state before the call: the field
+    is small (|S| < 0.1), on the heat-bath frame's seam, or its rounding can move the
+    update by more than the bar.  Both updates depend on the direction of S only; each
+    component of S carries at most gamma_6 sum_d |J_d| (six fused multiply-adds of unit
+    spins), so the direction moves by up to sqrt(3) gamma_6 A, A = sum_d |J_d| / |S|,
+    and a reflection 2 (s.n) n - s by up to 4 sqrt(3) gamma_6 A: beyond the 1e-5 bar
+    once A > 4 in binary32 (beyond 1e-12 once A > 200 in binary64)."""
     L, N = ref.L, ref.N
     st = ref_before["spins"][s, c, r].copy()
     beta = ref.betas[ref.temp_of_slot[s, c, r]]
@@ -77,6 +83,11 @@ def _ill_conditioned_sites(ref_before, ref, s, c, r, n_hb, n_or):
     g = ref.slot_base + (s * ref.C + c) * ref.R + r
     seq = [(p, 0, 2 * h + p) for h in range(n_hb) for p in (0, 1)] + \
           [(p, 1, 0) for _ in range(n_or) for p in (0, 1)]
+    a_max = 4.0 if ref.rng32 else 200.0
+    Js = ref.J[s]
+    sum_j = np.abs(Js).sum(axis=1)  # bonds to +mu at each site
+    for mu in range(3):  # bonds to -mu, stored at the -mu neighbour
+        sum_j += np.abs(Js[[hsgref.neighbor(L, x, 2 * mu + 1) for x in range(N)], mu])
     ill = set()
     for (p, kind, hs) in seq:
         for x in range(N):
@@ -84,7 +95,8 @@ def _ill_conditioned_sites(ref_before, ref, s, c, r, n_hb, n_or):
                 continue
             S = hsgref.local_field(L, ref.J[s], st, x)
             nrm = np.linalg.norm(S)
-            if nrm < 0.1 or (kind == 0 and abs(S[2]) < 1e-4 * nrm):
+            if (nrm < 0.1 or (kind == 0 and abs(S[2]) < 1e-4 * nrm)
+                    or sum_j[x] > a_max * nrm):
                 ill.add(x)
         hsgref.halfsweep(L, ref.J[s], st, p, kind, beta, ref.seed, g, t, hs, ref.rng32)
     return ill

@@ -157,6 +157,42 @@ def test_sweep_full_shape_sampled_replicas():
     gpu.check()
 
 
+@pytest.mark.parametrize("prec,L", [("fp32", 18), ("fp32", 24), ("fp32", 32), ("fp32", 40), ("fp64", 18),
+                                    ("fp64", 28)])
+@pytest.mark.parametrize("kind", ["hb", "or", "hb+3or"])
+def test_sweep_parity_wavefront(L, prec, kind):
+    """The wavefront path (one workgroup per replica walking its z-planes, the default
+    for 16 < L <= 40) against the oracle, several samples so the grid spans samples."""
+    S, C, R = 2, 2, 2
+    n_hb, n_or = {"hb": (1, 0), "or": (0, 1), "hb+3or": (1, 3)}[kind]
+    gpu, ref = make_pair(L, S, C, _betas(R, 1.0, 8.0), SEED + 300 + L, prec=prec)
+    _set_counters(gpu, ref, 9)
+    before = snapshot(ref)
+    gpu.sweep(1, n_hb, n_or, tuning={"path": 4})
+    ref.sweep(1, n_hb, n_or)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, prec, mode="composite" if kind == "hb+3or" else "lattice",
+                   before=before, n_hb=n_hb, n_or=n_or, what="L=%d %s wavefront %s" % (L, prec, kind))
+
+
+@pytest.mark.parametrize("L", [24, 32])
+def test_wavefront_equals_streaming(L):
+    """Same site arithmetic and random numbers as the streaming kernels: spins bit for
+    bit over two calls of two sweeps, energies to the summation order."""
+    out = []
+    for tune in ({"path": 4}, {"path": 2, "block_threads": 256, "replicas_per_block": 2}):
+        e = hsg.Ensemble(L, 2, 2, hsg.geometric_betas(1.0, 8.0, 4), SEED + L, precision="fp32")
+        e.init_couplings()
+        e.init_spins()
+        for _ in range(2):
+            e.sweep(2, 1, 3, tuning=tune)
+        torch.cuda.synchronize()
+        out.append((e.spins.cpu().numpy(), e.energy.cpu().numpy(), e.sweep_ctr.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][2], out[1][2])
+    assert np.allclose(out[0][1], out[1][1], rtol=1e-12, atol=1e-9)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("n_hb,n_or", [(2, 0), (2, 1), (1, 5)])
 def test_sweep_compositions(n_hb, n_or, prec):

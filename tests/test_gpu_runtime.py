@@ -77,12 +77,12 @@ def test_classes_on_streams_equal_classes_alone():
     _equal(together, alone)
 
 
-@pytest.mark.parametrize("prec,L", [("fp32", 8), ("fp32", 16), ("fp64", 8)])
+@pytest.mark.parametrize("prec,L", [("fp32", 8), ("fp32", 16), ("fp64", 8), ("fp32", 24), ("fp64", 18)])
 def test_sweep_variants_agree(prec, L):
     """Sites of one sublattice do not interact, so every kernel variant (tile shape,
     workgroup order, persistence) must produce the same spins bit for bit."""
     out = []
-    for tune in [{"path": 3}, {"path": 1}, {"path": 2, "block_threads": 128, "replicas_per_block": 4},
+    for tune in [{"path": 3}, {"path": 4}, {"path": 1}, {"path": 2, "block_threads": 128, "replicas_per_block": 4},
                  {"path": 2, "block_threads": 256, "replicas_per_block": 2},
                  {"path": 3, "block_threads": 256}, {"path": 3, "block_threads": 1024}]:
         e = hsg.Ensemble(L, 2, 2, hsg.geometric_betas(1.0, 8.0, 3), SEED, precision=prec)
@@ -96,6 +96,8 @@ def test_sweep_variants_agree(prec, L):
         torch.cuda.synchronize()
         out.append((tune, e.spins.cpu().numpy(), e.energy.cpu().numpy()))
     assert len(out) >= 3
+    if L > 16:
+        assert [t for t, _, _ in out if t.get("path") == 4], "wavefront path did not run"
     for tune, s, en in out[1:]:
         assert np.array_equal(s, out[0][1]), tune
         assert np.allclose(en, out[0][2], rtol=1e-12, atol=1e-9), tune
