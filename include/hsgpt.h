@@ -221,6 +221,16 @@ hsg_status hsg_coolheat_swap(const hsg_ensemble* ens, int n_ens, int pairing, do
  * e_temp = H/N by temperature (the paper's E is -e).  Q and chi need C >= 2. */
 hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream);
 
+/* hsg_sweep(ens, n_ens, n_sweeps, n_hb, n_or) followed by hsg_measure(ens, n_ens):
+ * the same spins and counters, and the same energies and measurements up to the
+ * rounding order of their FP64 sums.  Ensembles of exactly two chains with L <= 10
+ * (binary32) or L <= 12 (binary64) take one launch, in which a workgroup sweeps both
+ * chains' replicas of a temperature and measures them from LDS (measured faster
+ * there); other ensembles take the two launches.  Needs what both calls need;
+ * n_sweeps = 0 measures only. */
+hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                             void* stream);
+
 /* Synchronise `stream`, then report the guards: HSG_ERR_NUMERIC if any is set. */
 hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream);
 

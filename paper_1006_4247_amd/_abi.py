@@ -55,6 +55,7 @@ SIGNATURES = {
     "hsg_decimate_swap": (_i, [_E, _i, _i, _vp]),
     "hsg_coolheat_swap": (_i, [_E, _i, _i, ctypes.c_double, _vp]),
     "hsg_measure": (_i, [_E, _i, _vp]),
+    "hsg_sweep_measure": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_check": (_i, [_E, _i, _vp]),
     "hsg_mlp_forward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp]),
     "hsg_mlp_backward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp]),

@@ -275,6 +275,36 @@ hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream) {
     return ok();
 }
 
+hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                             void* stream) {
+    if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
+        return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
+                    n_sweeps, n_hb, n_or);
+    hsg_status s = check_all(ens, n_ens, kState | kMeasure);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i) {
+        if (!use_resident(ens[i], nullptr)) {
+            s = check_one(ens[i], i, kScratch);
+            if (s != HSG_OK) return s;
+        }
+    }
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err;
+        if (n_sweeps > 0 && hsg::resident_pair_supported(ens[i])) {
+            err = hsg::launch_resident_pair(ens[i], n_sweeps, n_hb, n_or, as_stream(stream));
+            if (err != hipSuccess) return device(err, "sweep and measure");
+            continue;
+        }
+        if (n_sweeps > 0) {
+            s = hsg_sweep(&ens[i], 1, n_sweeps, n_hb, n_or, stream);
+            if (s != HSG_OK) return s;
+        }
+        err = hsg::launch_measure(ens[i], as_stream(stream));
+        if (err != hipSuccess) return device(err, "measure");
+    }
+    return ok();
+}
+
 hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream) {
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;

@@ -25,6 +25,13 @@ bool persistent_supported(const hsg_ensemble& e);
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
                            int parity, int block_threads, hipStream_t st);
 
+// Regular sweeps of both chains' replicas at one temperature per workgroup followed
+// by the measurement of that temperature (the results of launch_resident with
+// anneal = 0 and then launch_measure): ensembles of exactly two chains at the sizes
+// where this one launch is faster (binary32 L <= 10, binary64 L <= 12).
+bool resident_pair_supported(const hsg_ensemble& e);
+hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st);
+
 // Wavefront path: one workgroup per replica walking its z-planes, one HBM pass per
 // lattice sweep (L = 18 .. 40 in binary32, .. 28 in binary64, LDS permitting); a
 // tuning option, slower than the streaming path where measured.

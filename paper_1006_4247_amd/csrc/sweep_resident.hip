@@ -47,9 +47,8 @@ struct FirstNbr {
 };
 
 template <int L, int NT>
-__device__ __forceinline__ FirstNbr first_neighbours() {
+__device__ __forceinline__ FirstNbr first_neighbours(int t) {
     using M = SiteMap<L, NT>;
-    const int t = static_cast<int>(threadIdx.x);
     FirstNbr f;
     const Nbr a = neighbours<L>(t, 0, L), b = neighbours<L>(t, 1, L);
     f.x[0][0] = a.n[0];
@@ -74,12 +73,11 @@ __device__ __forceinline__ int loaded_vec(int v, bool parity1_only) {
 
 // Neighbours of owned site (m, half) of parity p, h = t + NT m + NQ half.
 template <int L, int NT, int MQ>
-__device__ __forceinline__ Nbr site_nbrs(const FirstNbr& fn, int p, int m, int half, int h) {
+__device__ __forceinline__ Nbr site_nbrs(const FirstNbr& fn, int p, int m, int half, int h, int t) {
     using M = SiteMap<L, NT>;
     Nbr nb;
     if constexpr (M::invariant) {
         const int c = NT * m + M::NQ * half;
-        const int t = static_cast<int>(threadIdx.x);
         nb.n[0] = fn.x[p][0] + c;
         nb.n[1] = fn.x[p][1] + c;
         nb.n[2] = fn.yp + c;
@@ -97,7 +95,7 @@ __device__ __forceinline__ Nbr site_nbrs(const FirstNbr& fn, int p, int m, int h
 // at the -mu neighbour.
 template <typename T, int L, int NT, int MQ>
 __device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restrict__ J,
-                                           const FirstNbr& fn) {
+                                           const FirstNbr& fn, int t) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -105,9 +103,9 @@ __device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restric
         for (int m = 0; m < MQ; ++m)
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
-                const int q = static_cast<int>(threadIdx.x) + NT * m;
+                const int q = t + NT * m;
                 const int h = (q < NQ ? q : 0) + half * NQ;
-                const Nbr nb = site_nbrs<L, NT, MQ>(fn, p, m, half, h);
+                const Nbr nb = site_nbrs<L, NT, MQ>(fn, p, m, half, h, t);
 #pragma unroll
                 for (int mu = 0; mu < 3; ++mu) {
                     own.j[p][m][half][2 * mu] = J[(mu * 2 + p) * NH + h];
@@ -121,7 +119,7 @@ template <typename T, int L, int NT, int MQ, int P>
 __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T, MQ>& own,
                                               const FirstNbr& fn, bool hb, int hs, T beta,
                                               uint32_t tsw, uint32_t g, uint32_t k0, uint32_t k1,
-                                              bool want, double& acc, bool& bad) {
+                                              bool want, double& acc, bool& bad, int t) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
     constexpr bool INV = SiteMap<L, NT>::invariant;
     const T* __restrict__ o0 = sh + (0 * 2 + (1 - P)) * NH;
@@ -133,7 +131,7 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
     const uint32_t c3 = heatbath_c3(hs);
 #pragma unroll
     for (int m = 0; m < MQ; ++m) {
-        int q = static_cast<int>(threadIdx.x) + NT * m;
+        int q = t + NT * m;
         // Generic geometry: an opaque copy keeps the site arithmetic (neighbour
         // offsets, LDS addresses) inside each half-sweep instead of letting it be
         // hoisted and held live in registers across the whole kernel (empty asm,
@@ -145,7 +143,7 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int h = q + half * NQ;
-            const Nbr nb = site_nbrs<L, NT, MQ>(fn, P, m, half, h);
+            const Nbr nb = site_nbrs<L, NT, MQ>(fn, P, m, half, h, t);
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
@@ -256,7 +254,7 @@ __global__ void __launch_bounds__(NT)
     // registers, the replica's loads are issued right after the couplings' loads
     // and stay in flight while the couplings pass through LDS.
     Owned<T, MQ> own;
-    const FirstNbr fn = first_neighbours<L, NT>();
+    const FirstNbr fn = first_neighbours<L, NT>(static_cast<int>(threadIdx.x));
     {
         constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // vectors per replica
         constexpr int NVP = NV / 6;                                    // per plane
@@ -285,7 +283,7 @@ __global__ void __launch_bounds__(NT)
                 if (v < NV) dst[v] = jv[k];
             }
             lds_barrier();
-            load_owned<T, L, NT, MQ>(own, sh, fn);
+            load_owned<T, L, NT, MQ>(own, sh, fn, static_cast<int>(threadIdx.x));
             lds_barrier();  // every thread holds its couplings before the LDS is reused
 #pragma unroll
             for (int k = 0; k < PV; ++k) {
@@ -298,7 +296,7 @@ __global__ void __launch_bounds__(NT)
         } else {
             for (int v = threadIdx.x; v < NV; v += NT) dst[v] = js[v];
             __syncthreads();
-            load_owned<T, L, NT, MQ>(own, sh, fn);
+            load_owned<T, L, NT, MQ>(own, sh, fn, static_cast<int>(threadIdx.x));
             __syncthreads();
             for (int v = threadIdx.x; v < n_load; v += NT) {
                 const int o = loaded_vec<NVP>(v, hb_first);
@@ -334,9 +332,9 @@ __global__ void __launch_bounds__(NT)
             const int p = pos & 1;
             const bool want = need_e && (step == nhalf - 1);
             if (p == 0)
-                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
             else
-                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
             __syncthreads();
         }
         if (need_e) {
@@ -365,6 +363,164 @@ __global__ void __launch_bounds__(NT)
             e.energy[slot] = H;
             e.sweep_ctr[slot] = t0 + static_cast<uint32_t>(n_sweeps);
         }
+    }
+}
+
+// Regular sweeps and the measurement of one (sample, temperature) in one launch, for
+// ensembles of two chains: workgroup of 2 NT threads, threads [0, NT) running chain
+// 0's replica at that temperature and [NT, 2 NT) chain 1's, each half taking exactly
+// the steps of k_resident<T, L, NT> on its replica (same site order, random numbers
+// and energy reduction, hence the same spins and energy bit for bit).  With both
+// final configurations in LDS the workgroup then measures that temperature: the
+// energy per site of both chains, the overlap tensor Q^{mu nu} = sum_x s1^mu(x)
+// s2^nu(x) and chi = (1/N) sum Q^2 (paper Sec. IV), so the measurement reads no
+// spins from HBM.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(2 * NT)
+    k_resident_pair(hsg_ensemble e, int n_sweeps, int n_hb, int n_or) {
+    static_assert(NT % 64 == 0, "each half of the workgroup is a whole number of waves");
+    constexpr int N = L * L * L, NQ = N / 4;
+    constexpr int MQ = (NQ + NT - 1) / NT;
+    constexpr int NW = NT / 64;  // waves per replica
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[9 * 2 * NW];
+    __shared__ double s_H[2];
+
+    const int rep = static_cast<int>(threadIdx.x) >= NT ? 1 : 0;
+    const int t = static_cast<int>(threadIdx.x) - rep * NT;
+    T* sh = reinterpret_cast<T*>(smem_raw) + rep * 3 * N;
+    const int R = e.n_temps;
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int smp = item / R, b = item - smp * R;
+    const int chain = smp * 2 + rep;
+    const int slot = chain * R + label(e.slot_of_temp[chain * R + b], R, e.guard);
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    T* gs = static_cast<T*>(e.spins) + static_cast<size_t>(slot) * 3 * N;
+    const uint32_t g = e.slot_base + static_cast<uint32_t>(slot);
+    const uint32_t t0 = e.sweep_ctr[slot];
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+
+    // couplings and replica into LDS, as in k_resident (regular sweeps)
+    Owned<T, MQ> own;
+    const FirstNbr fn = first_neighbours<L, NT>(t);
+    {
+        constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
+        constexpr int NVP = NV / 6;
+        constexpr int PV = (NV + NT - 1) / NT;
+        constexpr bool PREFETCH = PV <= 6;
+        const bool hb_first = n_hb > 0;
+        const uint4* js = reinterpret_cast<const uint4*>(J);
+        const uint4* src = reinterpret_cast<const uint4*>(gs);
+        uint4* dst = reinterpret_cast<uint4*>(sh);
+        const int n_load = hb_first ? NV / 2 : NV;
+        if constexpr (PREFETCH) {
+            uint4 jv[PV], sv[PV];
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int v = t + k * NT;
+                jv[k] = (v < NV) ? js[v] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int v = t + k * NT;
+                sv[k] = (v < n_load) ? src[loaded_vec<NVP>(v, hb_first)] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int v = t + k * NT;
+                if (v < NV) dst[v] = jv[k];
+            }
+            lds_barrier();
+            load_owned<T, L, NT, MQ>(own, sh, fn, t);
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int v = t + k * NT;
+                if (v < n_load) dst[loaded_vec<NVP>(v, hb_first)] = sv[k];
+            }
+        } else {
+            for (int v = t; v < NV; v += NT) dst[v] = js[v];
+            __syncthreads();
+            load_owned<T, L, NT, MQ>(own, sh, fn, t);
+            __syncthreads();
+            for (int v = t; v < n_load; v += NT) {
+                const int o = loaded_vec<NVP>(v, hb_first);
+                dst[o] = src[o];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int nhalf = 2 * (n_hb + n_or);
+    const T beta = static_cast<T>(e.betas[label(e.temp_of_slot[slot], R, e.guard)]);
+    double H = 0.0;
+    bool bad = false;
+    for (int k = 0; k < n_sweeps; ++k) {
+        const bool need_e = k == n_sweeps - 1;
+        const uint32_t tsw = t0 + static_cast<uint32_t>(k);
+        double acc = 0.0;
+        for (int step = 0; step < nhalf; ++step) {
+            const bool hb = step < 2 * n_hb;
+            const bool want = need_e && (step == nhalf - 1);
+            if ((step & 1) == 0)
+                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, step, beta, tsw, g, k0, k1, want, acc, bad, t);
+            else
+                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, step, beta, tsw, g, k0, k1, want, acc, bad, t);
+            __syncthreads();
+        }
+        if (need_e) {  // each half sums its own waves, in wave order
+            const double w = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+            __syncthreads();
+            if (t == 0) {
+                double s = 0.0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) s += red[rep * NW + v];
+                s_H[rep] = -s;
+            }
+            __syncthreads();
+            H = s_H[rep];
+        }
+    }
+    if (bad || !isfinite(H)) atomicOr(e.guard, 1);
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(sh);
+        uint4* dst = reinterpret_cast<uint4*>(gs);
+        constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
+        for (int v = t; v < NV; v += NT) dst[v] = src[v];
+    }
+    if (t == 0) {
+        e.energy[slot] = H;
+        e.sweep_ctr[slot] = t0 + static_cast<uint32_t>(n_sweeps);
+        e.e_temp[static_cast<size_t>(chain) * R + b] = H / static_cast<double>(N);
+    }
+
+    // overlap of the two replicas, site by site in the common LDS layout [3][2][N/2]
+    const T* a = reinterpret_cast<const T*>(smem_raw);
+    const T* c = a + 3 * N;
+    double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = static_cast<int>(threadIdx.x); x < N; x += 2 * NT) {
+        const double x0 = a[x], x1 = a[N + x], x2 = a[2 * N + x];
+        const double y0 = c[x], y1 = c[N + x], y2 = c[2 * N + x];
+        q[0] = fma(x0, y0, q[0]); q[1] = fma(x0, y1, q[1]); q[2] = fma(x0, y2, q[2]);
+        q[3] = fma(x1, y0, q[3]); q[4] = fma(x1, y1, q[4]); q[5] = fma(x1, y2, q[5]);
+        q[6] = fma(x2, y0, q[6]); q[7] = fma(x2, y1, q[7]); q[8] = fma(x2, y2, q[8]);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double w = wave_sum(q[k]);
+        if ((threadIdx.x & 63) == 0) red[k * 2 * NW + (threadIdx.x >> 6)] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double chi = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            double s = 0.0;
+            for (int v = 0; v < 2 * NW; ++v) s += red[k * 2 * NW + v];
+            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = s;
+            chi += s * s;
+        }
+        e.chi[static_cast<size_t>(smp) * R + b] = chi / static_cast<double>(N);
     }
 }
 
@@ -401,7 +557,7 @@ __global__ void __launch_bounds__(NT)
     for (int v = threadIdx.x; v < NV; v += NT) buf0[v] = gsrc[static_cast<size_t>(t_begin) * NV + v];
     int cur_sample = -1;
     Owned<T, MQ> own;
-    const FirstNbr fn = first_neighbours<L, NT>();
+    const FirstNbr fn = first_neighbours<L, NT>(static_cast<int>(threadIdx.x));
     uint4 pf[PF];
     int sel = 0;
     for (int slot = t_begin; slot < t_end; ++slot) {
@@ -410,7 +566,7 @@ __global__ void __launch_bounds__(NT)
         const int smp = slot / (C * R);
         if (smp != cur_sample) {
             const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
-            load_owned<T, L, NT, MQ>(own, J, fn);
+            load_owned<T, L, NT, MQ>(own, J, fn, static_cast<int>(threadIdx.x));
             cur_sample = smp;
         }
         const bool has_next = slot + 1 < t_end;
@@ -433,9 +589,9 @@ __global__ void __launch_bounds__(NT)
             for (int pos = 0; pos < stop; ++pos) {
                 const bool hb = pos < 2 * n_hb;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad);
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
                 lds_barrier();
             }
         }
@@ -452,9 +608,9 @@ __global__ void __launch_bounds__(NT)
                 const bool hb = pos < 2 * n_hb;
                 const bool want = pos == nhalf - 1;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad);
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
                 lds_barrier();
             }
         }
@@ -639,6 +795,47 @@ static hipError_t dispatch(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_
     }
 }
 
+template <typename T, int L>
+static hipError_t go_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    // per replica the default workgroup size of k_resident, at most 512 threads in
+    // binary32 and 256 in binary64 (whose site updates need more than the 128
+    // registers a thread of a 1024-thread workgroup gets)
+    constexpr int NQ = L * L * L / 4;
+    constexpr int DEF = ((NQ + 63) / 64) * 64;
+    constexpr int CAP = sizeof(T) == 4 ? 512 : 256;
+    constexpr int NT = DEF > CAP ? CAP : DEF;
+    const size_t lds = 2 * 3 * static_cast<size_t>(L) * L * L * sizeof(T);
+    const int blocks = e.n_samples * e.n_temps;
+    if (blocks <= 0 || n_sweeps <= 0) return hipSuccess;
+    auto kern = k_resident_pair<T, L, NT>;
+    const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+    if (a != hipSuccess) return a;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(2 * NT), lds, st, e, n_sweeps, n_hb, n_or);
+    return hipGetLastError();
+}
+
+// Sizes where the one launch was measured faster than the sweep and measurement
+// launches (binary32 L <= 10, binary64 L <= 12).  From binary32 L = 12 and binary64
+// L = 14 up the single-replica sweep keeps more workgroups per CU, whose load and
+// store phases overlap each other's arithmetic, and the two launches win (at
+// binary32 L = 16: 0.149 ms against 0.187 ms per step).
+constexpr int pair_max_L(bool fp64) { return fp64 ? 12 : 10; }
+
+template <typename T>
+static hipError_t dispatch_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    switch (e.L) {
+    case 2: return go_pair<T, 2>(e, n_sweeps, n_hb, n_or, st);
+    case 4: return go_pair<T, 4>(e, n_sweeps, n_hb, n_or, st);
+    case 6: return go_pair<T, 6>(e, n_sweeps, n_hb, n_or, st);
+    case 8: return go_pair<T, 8>(e, n_sweeps, n_hb, n_or, st);
+    case 10: return go_pair<T, 10>(e, n_sweeps, n_hb, n_or, st);
+    case 12:
+        if constexpr (sizeof(T) == 8) return go_pair<T, 12>(e, n_sweeps, n_hb, n_or, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
 bool resident_supported(const hsg_ensemble& e) {
     if (e.L < 2 || e.L > 16 || (e.L & 1)) return false;
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
@@ -650,6 +847,18 @@ bool persistent_supported(const hsg_ensemble& e) {
     if (!resident_supported(e)) return false;
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
     return 2 * 3 * N * (e.precision == HSG_FP64 ? 8 : 4) <= max_block_lds();
+}
+
+bool resident_pair_supported(const hsg_ensemble& e) {
+    if (!resident_supported(e) || e.n_chains != 2 || !e.Q || !e.chi || !e.e_temp) return false;
+    if (e.L > pair_max_L(e.precision == HSG_FP64)) return false;
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    return 2 * 3 * N * (e.precision == HSG_FP64 ? 8 : 4) <= max_block_lds();
+}
+
+hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    if (e.precision == HSG_FP64) return dispatch_pair<double>(e, n_sweeps, n_hb, n_or, st);
+    return dispatch_pair<float>(e, n_sweeps, n_hb, n_or, st);
 }
 
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,

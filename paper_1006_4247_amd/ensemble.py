@@ -204,6 +204,13 @@ class Ensemble:
         _abi.check(_abi.lib().hsg_measure(ctypes.byref(self.desc), 1, self._stream()))
         return self.Q, self.chi, self.e_temp
 
+    def sweep_measure(self, n_sweeps=1, n_hb=1, n_or=3):
+        """sweep(n_sweeps, n_hb, n_or) then measure(); one launch where the ensemble has
+        two chains whose replicas fit one workgroup's LDS together."""
+        _abi.check(_abi.lib().hsg_sweep_measure(ctypes.byref(self.desc), 1, n_sweeps, n_hb, n_or,
+                                                self._stream()))
+        return self.Q, self.chi, self.e_temp
+
     def check(self):
         _abi.check(_abi.lib().hsg_check(ctypes.byref(self.desc), 1, self._stream()))
 

@@ -1,7 +1,9 @@
 """Drivers for parallel-tempering runs on one GPU.
 
 `PTRun` steps one or several size classes (`Ensemble`s) through the hot path:
-sweep -> exchange (plain, Eq. (1), or annealed) -> measurement.  Each size class runs
+sweep and measurement of the swept configurations (one launch where an ensemble's two
+chains fit one workgroup per temperature) -> exchange (plain, Eq. (1), annealed,
+decimated or cooling / heating).  Each size class runs
 on its own HIP stream, so the kernels of an uneven batch (several L, sample counts and
 ladders) overlap on the chip; `capture()` records one or two steps of every class into
 a HIP graph (torch's graph API drives the capture; every kernel is ours) so that
@@ -57,7 +59,15 @@ class PTRun:
     # ------------------------------------------------------------ one step
     def _step_one(self, i, parity, slot):
         e = self.ens[i]
-        e.sweep(1, self.n_hb, self.n_or, tuning=self.tunings[i])
+        if self.measure and self.tunings[i] is None:
+            e.sweep_measure(1, self.n_hb, self.n_or)
+        else:
+            e.sweep(1, self.n_hb, self.n_or, tuning=self.tunings[i])
+            if self.measure:
+                e.measure()
+        if self.measure and self.series_len and slot is not None:
+            self.chi_series[i][slot].copy_(e.chi)
+            self.e_series[i][slot].copy_(e.e_temp)
         if self.mode == "plain":
             e.swap(self.pairing)
         elif self.mode == "decimate":
@@ -66,11 +76,6 @@ class PTRun:
             e.coolheat_swap(self.eps, self.pairing if self.pairing >= 0 else parity + 1)
         else:
             e.anneal_swap(parity, *self.anneal_sweep)
-        if self.measure:
-            e.measure()
-            if self.series_len and slot is not None:
-                self.chi_series[i][slot].copy_(e.chi)
-                self.e_series[i][slot].copy_(e.e_temp)
 
     def _fork(self, fn):
         cur = torch.cuda.current_stream(self.device)

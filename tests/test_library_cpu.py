@@ -30,7 +30,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for need in ["hsg_init_couplings", "hsg_init_spins", "hsg_sweep", "hsg_energy", "hsg_swap",
-                 "hsg_anneal_swap", "hsg_measure", "hsg_check", "hsg_mlp_forward",
+                 "hsg_anneal_swap", "hsg_measure", "hsg_sweep_measure", "hsg_check", "hsg_mlp_forward",
                  "hsg_mlp_backward", "hsg_mlp_adam"]:
         assert need in names
 
