@@ -285,19 +285,15 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T e
     }
 }
 
-// Decisions of the pairs i0 + istep m (m < npc) of one chain per thread; `last`
-// advances the exchange counter and the round trips (once per call).  Entry
-// (chain, m, leg) of the flags array names the slot whose candidate replaces its
-// spins, or -1.
-__global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, int last) {
-    const int n_chains = e.n_samples * e.n_chains;
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n_chains) return;
+// Decisions of the pairs i0 + istep m (m < npc) of chain ch; `last` advances the
+// exchange counter and the round trips (once per call).  cp[2 m + leg] receives the
+// slot whose candidate replaces its spins, or -1.
+__device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int istep, int npc, int last,
+                                      int* cp) {
     const int R = e.n_temps;
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
     const double* cen = reinterpret_cast<const double*>(scr + sl.cand_energy);
-    int* flags = reinterpret_cast<int*>(scr + sl.flags);
     int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
     int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
     double* en = e.energy + static_cast<size_t>(ch) * R;
@@ -305,7 +301,6 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
     double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
     const uint32_t n = e.swap_ctr[ch];
     const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
-    int* cp = flags + static_cast<size_t>(ch) * npc * 2;
     for (int m = 0; m < npc; ++m) {
         const int i = i0 + istep * m;
         const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
@@ -343,6 +338,43 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
         } else if (Tr == R - 1) {
             if (rs[r] == 1) rs[r] = 2;
         }
+    }
+}
+
+// Decisions of the pairs i0 + istep m (m < npc) of one chain per thread; entry
+// (chain, m, leg) of the flags array names the slot whose candidate replaces its
+// spins, or -1.
+__global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, int last) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n_chains) return;
+    const ScratchLayout sl = scratch_layout(e);
+    int* flags = reinterpret_cast<int*>(static_cast<unsigned char*>(e.scratch) + sl.flags);
+    coolheat_decide_chain(e, ch, i0, istep, npc, last, flags + static_cast<size_t>(ch) * npc * 2);
+}
+
+// Ascending rounds (pair i of every chain): one workgroup per chain decides its pair
+// and copies the accepted candidates over the spins of their slots.
+constexpr int kDecideCopyThreads = 512;
+
+template <typename T>
+__global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg_ensemble e, int i, int last) {
+    __shared__ int s_slot[2];
+    const int ch = static_cast<int>(blockIdx.x);
+    if (threadIdx.x == 0) coolheat_decide_chain(e, ch, i, 1, 1, last, s_slot);
+    __syncthreads();
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
+    const size_t nv = 3 * N * sizeof(T) / 16;
+#pragma unroll
+    for (int leg = 0; leg < 2; ++leg) {
+        const int r = s_slot[leg];
+        if (r < 0) continue;  // uniform over the workgroup
+        const size_t slot = static_cast<size_t>(ch) * e.n_temps + r;
+        const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
+        uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
+        for (size_t v = threadIdx.x; v < nv; v += kDecideCopyThreads) dst[v] = src[v];
     }
 }
 
@@ -412,6 +444,15 @@ static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int 
         err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, st)
                                       : go_legs<float>(e, eps, i0, istep, npc, st);
         if (err != hipSuccess) return err;
+    }
+    if (npc == 1) {  // one pair per chain: decision and copy-back in one launch
+        if (e.precision == HSG_FP64)
+            hipLaunchKernelGGL(k_coolheat_decide_copy<double>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e,
+                               i0, last);
+        else
+            hipLaunchKernelGGL(k_coolheat_decide_copy<float>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e,
+                               i0, last);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep, npc, last);
     err = hipGetLastError();
