@@ -354,27 +354,51 @@ __global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, in
 }
 
 // Ascending rounds (pair i of every chain): one workgroup per chain decides its pair
-// and copies the accepted candidates over the spins of their slots.
+// and copies the accepted candidates over the spins of their slots.  While thread 0
+// decides, every thread loads the first kPre vectors of its share of both candidates
+// (a 16^3 binary32 replica entirely), so the copy's loads overlap the decision.
 constexpr int kDecideCopyThreads = 512;
+constexpr int kPre = 6;
 
 template <typename T>
 __global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg_ensemble e, int i, int last) {
     __shared__ int s_slot[2];
     const int ch = static_cast<int>(blockIdx.x);
-    if (threadIdx.x == 0) coolheat_decide_chain(e, ch, i, 1, 1, last, s_slot);
-    __syncthreads();
+    const int R = e.n_temps;
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
-    const size_t nv = 3 * N * sizeof(T) / 16;
+    const int nv = static_cast<int>(3 * N * sizeof(T) / 16);
+    const int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    // the pair's slots before the decision: x at beta_i (leg 0), y at beta_{i+1} (leg 1)
+    const int xy[2] = {label(sot[i], R, e.guard), label(sot[i + 1], R, e.guard)};
+    __syncthreads();  // every thread holds them before thread 0 may swap the labels
+    uint4 pre[2][kPre];
 #pragma unroll
     for (int leg = 0; leg < 2; ++leg) {
-        const int r = s_slot[leg];
-        if (r < 0) continue;  // uniform over the workgroup
-        const size_t slot = static_cast<size_t>(ch) * e.n_temps + r;
+        const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) +
+                                                          (static_cast<size_t>(ch) * R + xy[leg]) * 3 * N);
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int v = static_cast<int>(threadIdx.x) + k * kDecideCopyThreads;
+            pre[leg][k] = v < nv ? src[v] : make_uint4(0, 0, 0, 0);
+        }
+    }
+    if (threadIdx.x == 0) coolheat_decide_chain(e, ch, i, 1, 1, last, s_slot);
+    __syncthreads();
+#pragma unroll
+    for (int leg = 0; leg < 2; ++leg) {
+        if (s_slot[leg] < 0) continue;  // uniform over the workgroup; else s_slot[leg] == xy[leg]
+        const size_t slot = static_cast<size_t>(ch) * R + xy[leg];
         const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
         uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
-        for (size_t v = threadIdx.x; v < nv; v += kDecideCopyThreads) dst[v] = src[v];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int v = static_cast<int>(threadIdx.x) + k * kDecideCopyThreads;
+            if (v < nv) dst[v] = pre[leg][k];
+        }
+        for (int v = static_cast<int>(threadIdx.x) + kPre * kDecideCopyThreads; v < nv; v += kDecideCopyThreads)
+            dst[v] = src[v];
     }
 }
 
