@@ -160,25 +160,74 @@ __device__ __forceinline__ ChItem ch_item(const hsg_ensemble& e, int b, int i0, 
     return it;
 }
 
+__device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int istep, int npc, int last,
+                                      int* cp);
+
 // LDS-resident legs (L <= 16): the replica in LDS, couplings from global memory.
 // NT threads: 256 where a launch holds many pairs, more for the single pair per
 // chain of an ascending round, whose legs then finish sooner.
-template <typename T, int L, int NT>
+//
+// PREV (ascending rounds i0 >= 1, one pair per chain): the cooling leg's workgroup
+// first decides pair i0 - 1 of its chain and copies that pair's accepted candidates
+// over their spins, then cools the configuration the decision left at beta_{i0}
+// (read from the candidate buffer if the exchange was accepted).  Only that leg
+// depends on pair i0 - 1; the heating leg takes the configuration at beta_{i0+1},
+// which pair i0 - 1 does not touch, and runs meanwhile.
+template <typename T, int L, int NT, bool PREV>
 __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, int i0, int istep, int npc) {
     constexpr int N = L * L * L, NH = N / 2;
     constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
     __shared__ double red[NT / 64];
-    const ChItem it = ch_item(e, blockIdx.x, i0, istep, npc);
-    const int smp = it.ch / e.n_chains;
-    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
-    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) + static_cast<size_t>(it.slot) * 3 * N);
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<T*>(scr + sl.cand) + static_cast<size_t>(it.slot) * 3 * N);
+    T* cand = reinterpret_cast<T*>(scr + sl.cand);
+    T* spins = static_cast<T*>(e.spins);
+    ChItem it;
+    bool from_cand = false;
+    if constexpr (PREV) {
+        __shared__ int s_prev[3];
+        const int R = e.n_temps;
+        it.ch = static_cast<int>(blockIdx.x) >> 1;
+        it.leg = static_cast<int>(blockIdx.x) & 1;
+        it.i = i0;
+        if (it.leg == 0) {  // uniform over the workgroup
+            if (threadIdx.x == 0) {
+                coolheat_decide_chain(e, it.ch, i0 - 1, 1, 1, 0, s_prev);
+                s_prev[2] = label(e.slot_of_temp[it.ch * R + i0], R, e.guard);
+            }
+            __syncthreads();
+            it.slot = it.ch * R + s_prev[2];
+            from_cand = s_prev[0] >= 0;  // then s_prev[2] == s_prev[0]
+            if (s_prev[1] >= 0) {        // C^-1 y, now at beta_{i0-1}, back over its spins
+                const size_t y = static_cast<size_t>(it.ch) * R + s_prev[1];
+                const uint4* cs = reinterpret_cast<const uint4*>(cand + y * 3 * N);
+                uint4* cd = reinterpret_cast<uint4*>(spins + y * 3 * N);
+                for (int v = threadIdx.x; v < NV; v += NT) cd[v] = cs[v];
+            }
+        } else {
+            it.slot = it.ch * R + label(e.slot_of_temp[it.ch * R + i0 + 1], R, e.guard);
+        }
+    } else {
+        it = ch_item(e, blockIdx.x, i0, istep, npc);
+    }
+    const int smp = it.ch / e.n_chains;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    T* own = spins + static_cast<size_t>(it.slot) * 3 * N;
+    uint4* dst = reinterpret_cast<uint4*>(cand + static_cast<size_t>(it.slot) * 3 * N);
     uint4* s4 = reinterpret_cast<uint4*>(sh);
-    for (int v = threadIdx.x; v < NV; v += NT) s4[v] = src[v];
+    if (from_cand) {  // C x of pair i0 - 1: into LDS and back over the spins of its slot
+        uint4* back = reinterpret_cast<uint4*>(own);
+        for (int v = threadIdx.x; v < NV; v += NT) {
+            const uint4 a = dst[v];
+            s4[v] = a;
+            back[v] = a;
+        }
+    } else {
+        const uint4* src = reinterpret_cast<const uint4*>(own);
+        for (int v = threadIdx.x; v < NV; v += NT) s4[v] = src[v];
+    }
     __syncthreads();
     double ld = 0.0, en = 0.0;
     for (int step = 0; step < 2; ++step) {
@@ -419,10 +468,10 @@ __global__ void k_coolheat_copyback(hsg_ensemble e, int npc) {
     for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
 }
 
-template <typename T, int L, int NT>
+template <typename T, int L, int NT, bool PREV>
 static hipError_t go_leg_nt(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
     constexpr size_t lds = 3 * L * L * L * sizeof(T);
-    auto kern = k_coolheat_leg_res<T, L, NT>;
+    auto kern = k_coolheat_leg_res<T, L, NT, PREV>;
     const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
     if (a != hipSuccess) return a;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, eps, i0, istep, npc);
@@ -430,34 +479,53 @@ static hipError_t go_leg_nt(const hsg_ensemble& e, T eps, int i0, int istep, int
 }
 
 template <typename T, int L>
-static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
+static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, bool prev,
+                             hipStream_t st) {
     // one pair per chain: binary32 legs with 1024 threads, binary64 with 512 (its site
     // maps need more than the 128 registers a thread of a 1024-thread workgroup gets)
     constexpr int NH = L * L * L / 2;
     constexpr int NTMAX = sizeof(T) == 4 ? 1024 : 512;
     constexpr int NT1 = NH >= NTMAX ? NTMAX : ((NH + 63) / 64) * 64;
-    if constexpr (NT1 > kChThreads) {
-        if (npc == 1) return go_leg_nt<T, L, NT1>(e, eps, i0, istep, npc, blocks, st);
+    constexpr int NTS = NT1 > kChThreads ? NT1 : kChThreads;
+    if (npc == 1) {
+        if (prev) return go_leg_nt<T, L, NTS, true>(e, eps, i0, istep, npc, blocks, st);
+        return go_leg_nt<T, L, NTS, false>(e, eps, i0, istep, npc, blocks, st);
     }
-    return go_leg_nt<T, L, kChThreads>(e, eps, i0, istep, npc, blocks, st);
+    if (prev) return hipErrorInvalidValue;
+    return go_leg_nt<T, L, kChThreads, false>(e, eps, i0, istep, npc, blocks, st);
 }
 
+// Legs of the pairs i0 + istep m; prev (ascending, one pair per chain, L <= 16): the
+// cooling legs first decide and copy pair i0 - 1.
 template <typename T>
-static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, int npc, hipStream_t st) {
+static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, int npc, bool prev,
+                          hipStream_t st) {
     const int blocks = e.n_samples * e.n_chains * npc * 2;
     const T te = static_cast<T>(eps);
     switch (e.L) {
-        case 4: return go_leg_res<T, 4>(e, te, i0, istep, npc, blocks, st);
-        case 6: return go_leg_res<T, 6>(e, te, i0, istep, npc, blocks, st);
-        case 8: return go_leg_res<T, 8>(e, te, i0, istep, npc, blocks, st);
-        case 10: return go_leg_res<T, 10>(e, te, i0, istep, npc, blocks, st);
-        case 12: return go_leg_res<T, 12>(e, te, i0, istep, npc, blocks, st);
-        case 14: return go_leg_res<T, 14>(e, te, i0, istep, npc, blocks, st);
-        case 16: return go_leg_res<T, 16>(e, te, i0, istep, npc, blocks, st);
+        case 4: return go_leg_res<T, 4>(e, te, i0, istep, npc, blocks, prev, st);
+        case 6: return go_leg_res<T, 6>(e, te, i0, istep, npc, blocks, prev, st);
+        case 8: return go_leg_res<T, 8>(e, te, i0, istep, npc, blocks, prev, st);
+        case 10: return go_leg_res<T, 10>(e, te, i0, istep, npc, blocks, prev, st);
+        case 12: return go_leg_res<T, 12>(e, te, i0, istep, npc, blocks, prev, st);
+        case 14: return go_leg_res<T, 14>(e, te, i0, istep, npc, blocks, prev, st);
+        case 16: return go_leg_res<T, 16>(e, te, i0, istep, npc, blocks, prev, st);
         default:
+            if (prev) return hipErrorInvalidValue;
             hipLaunchKernelGGL(k_coolheat_leg<T>, dim3(blocks), dim3(kChThreads), 0, st, e, te, i0, istep, npc);
             return hipGetLastError();
     }
+}
+
+static hipError_t launch_decide_copy(const hsg_ensemble& e, int i, int last, hipStream_t st) {
+    const int n_chains = e.n_samples * e.n_chains;
+    if (e.precision == HSG_FP64)
+        hipLaunchKernelGGL(k_coolheat_decide_copy<double>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e, i,
+                           last);
+    else
+        hipLaunchKernelGGL(k_coolheat_decide_copy<float>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e, i,
+                           last);
+    return hipGetLastError();
 }
 
 static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int istep, int npc, int last,
@@ -465,19 +533,11 @@ static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int 
     const int n_chains = e.n_samples * e.n_chains;
     hipError_t err = hipSuccess;
     if (npc > 0) {
-        err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, st)
-                                      : go_legs<float>(e, eps, i0, istep, npc, st);
+        err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, false, st)
+                                      : go_legs<float>(e, eps, i0, istep, npc, false, st);
         if (err != hipSuccess) return err;
     }
-    if (npc == 1) {  // one pair per chain: decision and copy-back in one launch
-        if (e.precision == HSG_FP64)
-            hipLaunchKernelGGL(k_coolheat_decide_copy<double>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e,
-                               i0, last);
-        else
-            hipLaunchKernelGGL(k_coolheat_decide_copy<float>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e,
-                               i0, last);
-        return hipGetLastError();
-    }
+    if (npc == 1) return launch_decide_copy(e, i0, last, st);  // decision and copy-back in one launch
     hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep, npc, last);
     err = hipGetLastError();
     if (err != hipSuccess || npc == 0) return err;
@@ -494,6 +554,14 @@ hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipSt
     if (e.n_samples * e.n_chains <= 0 || R < 2) return hipSuccess;
     if (pairing == 0) {
         // ascending order: each pair sees the states the previous pair left
+        if (e.L >= 4 && e.L <= 16) {  // LDS-resident legs: pair i - 1 decided inside pair i's launch
+            for (int i = 0; i < R - 1; ++i) {
+                hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i, 1, 1, i > 0, st)
+                                                         : go_legs<float>(e, eps, i, 1, 1, i > 0, st);
+                if (err != hipSuccess) return err;
+            }
+            return launch_decide_copy(e, R - 2, 1, st);
+        }
         for (int i = 0; i < R - 1; ++i) {
             hipError_t err = coolheat_round(e, eps, i, 1, 1, i == R - 2, st);
             if (err != hipSuccess) return err;
