@@ -273,22 +273,59 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, 
     }
 }
 
-// Generic legs (any even L): the candidate in global memory.
-template <typename T>
-__global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T eps, int i0, int istep, int npc) {
-    __shared__ double red[kChThreads / 64];
+// Generic legs (any even L): the candidate in global memory.  NT threads: 256 where a
+// launch holds many pairs, more for the single pair per chain of an ascending round.
+// PREV as for the LDS-resident legs: the cooling workgroup first decides and copies
+// pair i0 - 1; where that exchange was accepted, the configuration at beta_{i0} already
+// sits in this slot's candidate buffer and is copied back over its spins before the
+// map overwrites it.
+template <typename T, int NT, bool PREV>
+__global__ void __launch_bounds__(NT) k_coolheat_leg(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+    __shared__ double red[NT / 64];
     const int L = e.L, N = L * L * L, NH = N / 2;
-    const ChItem it = ch_item(e, blockIdx.x, i0, istep, npc);
-    const int smp = it.ch / e.n_chains;
-    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    const int nv = 3 * N * static_cast<int>(sizeof(T)) / 16;
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    T* c = reinterpret_cast<T*>(scr + sl.cand) + static_cast<size_t>(it.slot) * 3 * N;
+    T* cand = reinterpret_cast<T*>(scr + sl.cand);
+    T* spins = static_cast<T*>(e.spins);
+    ChItem it;
+    bool from_cand = false;
+    if constexpr (PREV) {
+        __shared__ int s_prev[3];
+        const int R = e.n_temps;
+        it.ch = static_cast<int>(blockIdx.x) >> 1;
+        it.leg = static_cast<int>(blockIdx.x) & 1;
+        it.i = i0;
+        if (it.leg == 0) {  // uniform over the workgroup
+            if (threadIdx.x == 0) {
+                coolheat_decide_chain(e, it.ch, i0 - 1, 1, 1, 0, s_prev);
+                s_prev[2] = label(e.slot_of_temp[it.ch * R + i0], R, e.guard);
+            }
+            __syncthreads();
+            it.slot = it.ch * R + s_prev[2];
+            from_cand = s_prev[0] >= 0;  // then s_prev[2] == s_prev[0]
+            if (s_prev[1] >= 0) {        // C^-1 y, now at beta_{i0-1}, back over its spins
+                const size_t y = static_cast<size_t>(it.ch) * R + s_prev[1];
+                const uint4* cs = reinterpret_cast<const uint4*>(cand + y * 3 * N);
+                uint4* cd = reinterpret_cast<uint4*>(spins + y * 3 * N);
+                for (int v = threadIdx.x; v < nv; v += NT) cd[v] = cs[v];
+            }
+        } else {
+            it.slot = it.ch * R + label(e.slot_of_temp[it.ch * R + i0 + 1], R, e.guard);
+        }
+    } else {
+        it = ch_item(e, blockIdx.x, i0, istep, npc);
+    }
+    const int smp = it.ch / e.n_chains;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+    T* c = cand + static_cast<size_t>(it.slot) * 3 * N;
     {
-        const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) + static_cast<size_t>(it.slot) * 3 * N);
-        uint4* dst = reinterpret_cast<uint4*>(c);
-        const int nv = 3 * N * static_cast<int>(sizeof(T)) / 16;
-        for (int v = threadIdx.x; v < nv; v += kChThreads) dst[v] = src[v];
+        uint4* cv = reinterpret_cast<uint4*>(c);
+        uint4* sv = reinterpret_cast<uint4*>(spins + static_cast<size_t>(it.slot) * 3 * N);
+        if (from_cand)  // C x of pair i0 - 1 becomes its slot's spins; the map starts from it
+            for (int v = threadIdx.x; v < nv; v += NT) sv[v] = cv[v];
+        else
+            for (int v = threadIdx.x; v < nv; v += NT) cv[v] = sv[v];
     }
     __syncthreads();
     double ld = 0.0, en = 0.0;
@@ -300,7 +337,7 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T e
         T* w0 = c + (0 * 2 + p) * NH;
         T* w1 = c + (1 * 2 + p) * NH;
         T* w2 = c + (2 * 2 + p) * NH;
-        for (int h = threadIdx.x; h < NH; h += kChThreads) {
+        for (int h = threadIdx.x; h < NH; h += NT) {
             const Nbr nb = neighbours<0>(h, p, L);
             T Sx = T(0), Sy = T(0), Sz = T(0);
 #pragma unroll
@@ -325,8 +362,8 @@ __global__ void __launch_bounds__(kChThreads) k_coolheat_leg(hsg_ensemble e, T e
         }
         __syncthreads();  // the next half-step reads this one's spins
     }
-    const double LD = block_sum<kChThreads>(ld, red);
-    const double H = -block_sum<kChThreads>(en, red);
+    const double LD = block_sum<NT>(ld, red);
+    const double H = -block_sum<NT>(en, red);
     if (threadIdx.x == 0) {
         e.work[(static_cast<size_t>(it.ch) * (e.n_temps - 1) + it.i) * 2 + it.leg] = LD;
         reinterpret_cast<double*>(scr + sl.cand_energy)[it.slot] = H;
@@ -510,10 +547,22 @@ static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, 
         case 12: return go_leg_res<T, 12>(e, te, i0, istep, npc, blocks, prev, st);
         case 14: return go_leg_res<T, 14>(e, te, i0, istep, npc, blocks, prev, st);
         case 16: return go_leg_res<T, 16>(e, te, i0, istep, npc, blocks, prev, st);
-        default:
-            if (prev) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_coolheat_leg<T>, dim3(blocks), dim3(kChThreads), 0, st, e, te, i0, istep, npc);
+        default: {
+            // one pair per chain: 1024 threads in binary32, 512 in binary64 (as above)
+            constexpr int NTG = sizeof(T) == 4 ? 1024 : 512;
+            if (npc == 1 && prev)
+                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, true>), dim3(blocks), dim3(NTG), 0, st, e, te, i0, istep,
+                                   npc);
+            else if (npc == 1)
+                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, false>), dim3(blocks), dim3(NTG), 0, st, e, te, i0, istep,
+                                   npc);
+            else if (prev)
+                return hipErrorInvalidValue;
+            else
+                hipLaunchKernelGGL((k_coolheat_leg<T, kChThreads, false>), dim3(blocks), dim3(kChThreads), 0, st, e,
+                                   te, i0, istep, npc);
             return hipGetLastError();
+        }
     }
 }
 
@@ -554,19 +603,13 @@ hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipSt
     if (e.n_samples * e.n_chains <= 0 || R < 2) return hipSuccess;
     if (pairing == 0) {
         // ascending order: each pair sees the states the previous pair left
-        if (e.L >= 4 && e.L <= 16) {  // LDS-resident legs: pair i - 1 decided inside pair i's launch
-            for (int i = 0; i < R - 1; ++i) {
-                hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i, 1, 1, i > 0, st)
-                                                         : go_legs<float>(e, eps, i, 1, 1, i > 0, st);
-                if (err != hipSuccess) return err;
-            }
-            return launch_decide_copy(e, R - 2, 1, st);
-        }
+        // (pair i - 1 decided inside pair i's launch, the last pair by its own)
         for (int i = 0; i < R - 1; ++i) {
-            hipError_t err = coolheat_round(e, eps, i, 1, 1, i == R - 2, st);
+            hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i, 1, 1, i > 0, st)
+                                                     : go_legs<float>(e, eps, i, 1, 1, i > 0, st);
             if (err != hipSuccess) return err;
         }
-        return hipSuccess;
+        return launch_decide_copy(e, R - 2, 1, st);
     }
     const int first = pairing == 1 ? 0 : 1;
     const int npc = (R - first) / 2;

@@ -97,9 +97,11 @@ __device__ __forceinline__ double reinsert_site(T* __restrict__ s, const T* __re
     return fma(dz, static_cast<double>(Sz), fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pairing) {
-    __shared__ double red[kDecThreads / 64];
+// NT threads: 256 for one pair per workgroup (even / odd pairs), more for one chain
+// per workgroup (ascending pairs, each waiting for the last one).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_decimate(hsg_ensemble e, int pairing) {
+    __shared__ double red[NT / 64];
     __shared__ int s_acc;
     const int L = e.L, N = L * L * L, NH = N / 2, NQ = N / 4;
     const int R = e.n_temps, C = e.n_chains;
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
         const float fr0 = static_cast<float>(b2 / b1);
 
         double acc = 0.0;
-        for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+        for (int h = threadIdx.x; h < NH; h += NT) {
             const Nbr nb = neighbours<0>(h, d, L);
             T ax, ay, az, cx, cy, cz;
             field<T>(sx, J, NH, h, d, nb, ax, ay, az);
@@ -150,7 +152,7 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
             else
                 acc += (log_sinhc(b2 * a) - log_sinhc(b1 * a)) + (log_sinhc(b1 * c) - log_sinhc(b2 * c));
         }
-        const double lnA = block_sum<kDecThreads>(acc, red);
+        const double lnA = block_sum<NT>(acc, red);
         if (threadIdx.x == 0) {
             if (e.work) {
                 e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
             const T tb2 = static_cast<T>(b2), tb1 = static_cast<T>(b1);
             double ex = 0.0, ey = 0.0;
             if (sizeof(T) == 4) {
-                for (int q = threadIdx.x; q < NQ; q += kDecThreads) {
+                for (int q = threadIdx.x; q < NQ; q += NT) {
                     const Words wx = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
                     const Words wy = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
 #pragma unroll
@@ -192,7 +194,7 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
                     }
                 }
             } else {
-                for (int h = threadIdx.x; h < NH; h += kDecThreads) {
+                for (int h = threadIdx.x; h < NH; h += NT) {
                     const Nbr nb = neighbours<0>(h, d, L);
                     const Words wx = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
                     const Words wy = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
@@ -202,8 +204,8 @@ __global__ void __launch_bounds__(kDecThreads) k_decimate(hsg_ensemble e, int pa
                                            static_cast<T>(u01_52(wy.w2, wy.w3)));
                 }
             }
-            const double Hx = -block_sum<kDecThreads>(ex, red);
-            const double Hy = -block_sum<kDecThreads>(ey, red);
+            const double Hx = -block_sum<NT>(ex, red);
+            const double Hy = -block_sum<NT>(ey, red);
             if (threadIdx.x == 0) {
                 e.energy[gx] = Hx;
                 e.energy[gy] = Hy;
@@ -442,7 +444,11 @@ static hipError_t go_decimate(const hsg_ensemble& e, int pairing, int blocks, hi
         case 14: return go_decimate_res<T, 14>(e, pairing, blocks, st);
         case 16: return go_decimate_res<T, 16>(e, pairing, blocks, st);
         default:
-            hipLaunchKernelGGL(k_decimate<T>, dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
+            if (pairing == 0)  // binary64 with 512 threads (register budget, as above)
+                hipLaunchKernelGGL((k_decimate<T, sizeof(T) == 4 ? 1024 : 512>), dim3(blocks),
+                                   dim3(sizeof(T) == 4 ? 1024 : 512), 0, st, e, pairing);
+            else
+                hipLaunchKernelGGL((k_decimate<T, kDecThreads>), dim3(blocks), dim3(kDecThreads), 0, st, e, pairing);
             return hipGetLastError();
     }
 }

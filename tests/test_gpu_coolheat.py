@@ -109,7 +109,7 @@ def test_coolheat_parity_fp32(L, pairing):
     gpu.check()
 
 
-@pytest.mark.parametrize("L", [8, 16])
+@pytest.mark.parametrize("L", [8, 16, 18])
 def test_coolheat_ascending_fp32(L):
     """All pairs in ascending order (one round of legs per pair), FP32.  A
     configuration can be mapped by several consecutive accepted pairs, so the
