@@ -274,17 +274,22 @@ PAPER_T_MIN, PAPER_T_MAX = 0.12, 0.19
 PAPER_LADDERS = {16: dict(n_temps=15, n_or=20), 24: dict(n_temps=27, n_or=30), 32: dict(n_temps=43, n_or=40)}
 
 
-def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
-    """Standard, decimated and cooling / heating tempering on the paper's ladder for L
-    (Sec. IV), all pairs in ascending order every cycle, on the same S coupling sets
-    (fresh Gaussian sets; the paper's ten are unpublished) with 2 chains: per coupling
-    set the acceptance, the round-trip time t_R = cycles x configurations / trips
-    (Sec. IV.B) and tau_int of the overlap susceptibility at T_min (window c = 4), and
-    the per-set speed-ups over standard tempering averaged over the sets (Table II)."""
+STUDY_METHODS = ("standard", "decimation", "coolheat")
+
+
+def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_METHODS, n_temps=0):
+    """Standard, decimated and cooling / heating tempering (or a subset, `methods`) on
+    the paper's ladder for L (Sec. IV; n_temps > 0 replaces its N_T, as in the paper's
+    N_T = 22 runs at L = 24), all pairs in ascending order every cycle, on the same S
+    coupling sets (fresh Gaussian sets; the paper's ten are unpublished) with 2 chains:
+    per coupling set the acceptance, the round-trip time t_R = cycles x configurations /
+    trips (Sec. IV.B) and tau_int of the overlap susceptibility at T_min (window c = 4),
+    and, with standard tempering among the methods, the per-set speed-ups over it
+    averaged over the sets (Table II)."""
     from paper_1006_4247_amd import analysis, runtime
 
     cfg = PAPER_LADDERS[L]
-    R, n_or = cfg["n_temps"], cfg["n_or"]
+    R, n_or = (n_temps or cfg["n_temps"]), cfg["n_or"]
     i = np.arange(1, R + 1)
     temps = PAPER_T_MAX * (PAPER_T_MIN / PAPER_T_MAX) ** ((i - 1) / (R - 1))
     betas = 1.0 / temps
@@ -302,6 +307,8 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
             print("[paper-ladder L=%d] %s %d/%d" % (L, what, done, n), file=sys.stderr, flush=True)
 
     for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat")):
+        if method not in methods:
+            continue
         e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
         e.init_couplings()
         e.init_spins()
@@ -341,7 +348,7 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
     out = {"study": "paper-ladder", "L": L, "coupling_sets": S, "chains": C, "temperatures": R,
            "T": [PAPER_T_MIN, PAPER_T_MAX], "sweep": "1 HB + %d OR" % n_or, "exchange": "all pairs ascending",
            "cycles": cycles, "equilibration_cycles": equil, "data": "synthetic Gaussian coupling sets from Philox"}
-    std = res["standard"]
+    std = res.get("standard")
     for m, r in res.items():
         d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
              "t_R_per_set": q(r["t_R"]), "round_trips": int(r["trips"].sum()),
@@ -351,7 +358,7 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010):
             d["eps"] = r["eps"]
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
             d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
-        if m != "standard":
+        if m != "standard" and std is not None:
             cost = (r["gpu_s"] / cycles) / (std["gpu_s"] / cycles)  # GPU time per cycle vs standard
             d["speedup_vs_standard"] = {
                 "acceptance": round(float(np.mean(r["acc_set"] / np.maximum(std["acc_set"], 1e-12))), 3),
@@ -450,6 +457,10 @@ def main():
     ap.add_argument("--study-sets", type=int, default=64, help="coupling sets of the paper-ladder study")
     ap.add_argument("--study-cycles", type=int, nargs=2, default=[10000, 20000], metavar=("EQUIL", "MEASURE"),
                     help="equilibration and measurement cycles of the paper-ladder study")
+    ap.add_argument("--study-methods", nargs="+", choices=STUDY_METHODS, default=list(STUDY_METHODS),
+                    help="tempering methods of the paper-ladder study")
+    ap.add_argument("--study-temps", type=int, default=0, metavar="N_T",
+                    help="number of temperatures of the paper-ladder study (default: the paper's for L)")
     ap.add_argument("--uneven", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps of the uneven batch (five size classes, 424 MB of "
                          "spins) and print its JSON line")
@@ -477,7 +488,9 @@ def main():
             print("--paper-ladder takes L = 16, 24 or 32", file=sys.stderr)
             sys.exit(2)
         print(json.dumps(paper_ladder_study(torch, hsg, args.paper_ladder, args.study_sets,
-                                            args.study_cycles[1], args.study_cycles[0])), flush=True)
+                                            args.study_cycles[1], args.study_cycles[0],
+                                            methods=tuple(args.study_methods), n_temps=args.study_temps)),
+              flush=True)
         return
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
