@@ -383,13 +383,185 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 && NT <= 256 ? 3 : 1) k_dec
     }
 }
 
+// ---------------------------------------------------------------- split ascending pass
+// With few chains, one workgroup per chain (k_decimate) leaves most CUs idle through
+// the R - 1 sequential pairs.  Here pair i of every chain is spread over G workgroups,
+// each owning a slice of the decimated sublattice, in two launches:
+// k_dec_split_terms sums the site terms of each slice into a partial sum;
+// k_dec_split_apply adds the G partial sums up in slice order (every workgroup of a
+// chain alike, so all take the same decision), lets slice 0 record the decision, and
+// on acceptance re-inserts its slice in both configurations, leaving per-slice energy
+// sums that the next pair's first launch (or the finishing pass) adds up.  Per chain,
+// in the scratch's partial area: G partial sums, 2 G energy sums, and a record of the
+// pair's slots and decision.
+struct DecSplit {
+    double* part;  // [G]
+    double* epart; // [G][2]
+    int* rec;      // x, y, accepted
+};
+
+__device__ __forceinline__ DecSplit dec_split(const hsg_ensemble& e, int ch, int G) {
+    const ScratchLayout sl = scratch_layout(e);
+    double* base = reinterpret_cast<double*>(static_cast<unsigned char*>(e.scratch) + sl.partial) +
+                   static_cast<size_t>(ch) * (3 * G + 2);
+    DecSplit d;
+    d.part = base;
+    d.epart = base + G;
+    d.rec = reinterpret_cast<int*>(base + 3 * G);
+    return d;
+}
+
+// Energies of the configurations the previous pair re-inserted (if it was accepted).
+__device__ __forceinline__ void dec_split_energies(const hsg_ensemble& e, int ch, int G, const DecSplit& d) {
+    if (!d.rec[2]) return;
+    double hx = 0.0, hy = 0.0;
+    for (int g = 0; g < G; ++g) {
+        hx += d.epart[2 * g];
+        hy += d.epart[2 * g + 1];
+    }
+    const size_t base = static_cast<size_t>(ch) * e.n_temps;
+    e.energy[base + d.rec[0]] = -hx;
+    e.energy[base + d.rec[1]] = -hy;
+    if (!isfinite(hx) || !isfinite(hy)) atomicOr(e.guard, 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kDecThreads) k_dec_split_terms(hsg_ensemble e, int i, int G) {
+    __shared__ double red[kDecThreads / 64];
+    const int L = e.L, N = L * L * L, NH = N / 2;
+    const int R = e.n_temps, C = e.n_chains;
+    const int ch = static_cast<int>(blockIdx.x) / G, g = static_cast<int>(blockIdx.x) % G;
+    const DecSplit ds = dec_split(e, ch, G);
+    const int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int d = (static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u) + i) & 1;
+    const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(ch / C) * 3 * N;
+    const T* sx = static_cast<const T*>(e.spins) + (static_cast<size_t>(ch) * R + x) * 3 * N;
+    const T* sy = static_cast<const T*>(e.spins) + (static_cast<size_t>(ch) * R + y) * 3 * N;
+    const double b1 = e.betas[i], b2 = e.betas[i + 1];
+    const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
+    const float fr0 = static_cast<float>(b2 / b1);
+    const int h0 = static_cast<int>(static_cast<long long>(NH) * g / G);
+    const int h1 = static_cast<int>(static_cast<long long>(NH) * (g + 1) / G);
+    double acc = 0.0;
+    for (int h = h0 + static_cast<int>(threadIdx.x); h < h1; h += kDecThreads) {
+        const Nbr nb = neighbours<0>(h, d, L);
+        T ax, ay, az, cx, cy, cz;
+        field<T>(sx, J, NH, h, d, nb, ax, ay, az);
+        field<T>(sy, J, NH, h, d, nb, cx, cy, cz);
+        const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
+        if constexpr (sizeof(T) == 4)
+            acc += fma(b2 - b1, a - c,
+                       static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0)));
+        else
+            acc += (log_sinhc(b2 * a) - log_sinhc(b1 * a)) + (log_sinhc(b1 * c) - log_sinhc(b2 * c));
+    }
+    const double part = block_sum<kDecThreads>(acc, red);
+    if (threadIdx.x == 0) {
+        ds.part[g] = part;
+        if (g == 0) {
+            if (i > 0) dec_split_energies(e, ch, G, ds);  // pair i - 1, before its record is replaced
+            ds.rec[0] = x;
+            ds.rec[1] = y;
+            ds.rec[2] = 0;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kDecThreads) k_dec_split_apply(hsg_ensemble e, int i, int G) {
+    __shared__ double red[kDecThreads / 64];
+    const int L = e.L, N = L * L * L, NH = N / 2, NQ = N / 4;
+    const int R = e.n_temps, C = e.n_chains;
+    const int ch = static_cast<int>(blockIdx.x) / G, g = static_cast<int>(blockIdx.x) % G;
+    const DecSplit ds = dec_split(e, ch, G);
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int d = (static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u) + i) & 1;
+    const int x = ds.rec[0], y = ds.rec[1];
+    double lnA = 0.0;
+    for (int k = 0; k < G; ++k) lnA += ds.part[k];
+    const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, k0, k1);
+    const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
+    if (g == 0 && threadIdx.x == 0) {
+        long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+        if (e.work) {
+            e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
+            e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = static_cast<double>(d);
+        }
+        if (!isfinite(lnA)) atomicOr(e.guard, 1);
+        st[2 * i] += 1;
+        if (ok) {
+            int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+            int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+            sot[i] = y;
+            sot[i + 1] = x;
+            tos[x] = i + 1;
+            tos[y] = i;
+            st[2 * i + 1] += 1;
+            ds.rec[2] = 1;
+        }
+    }
+    if (!ok) return;  // uniform over the chain's workgroups
+    // x goes to beta_2, y to beta_1; this workgroup's slice of D is drawn anew
+    const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
+    T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
+    T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(ch / C) * 3 * N;
+    const uint32_t c3 = (kTagDecimate << 24) | (static_cast<uint32_t>(i) & 0xFFFFu);
+    const T tb2 = static_cast<T>(e.betas[i + 1]), tb1 = static_cast<T>(e.betas[i]);
+    double ex = 0.0, ey = 0.0;
+    if (sizeof(T) == 4) {  // one Philox block per site pair (q, q + N/4)
+        const int q0 = static_cast<int>(static_cast<long long>(NQ) * g / G);
+        const int q1 = static_cast<int>(static_cast<long long>(NQ) * (g + 1) / G);
+        for (int q = q0 + static_cast<int>(threadIdx.x); q < q1; q += kDecThreads) {
+            const Words wx = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
+            const Words wy = philox(static_cast<uint32_t>(q), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int h = q + half * NQ;
+                const Nbr nb = neighbours<0>(h, d, L);
+                ex += reinsert_site<T>(sx, J, NH, h, d, nb, tb2, static_cast<T>(u01_23(half ? wx.w2 : wx.w0)),
+                                       static_cast<T>(u01_23(half ? wx.w3 : wx.w1)));
+                ey += reinsert_site<T>(sy, J, NH, h, d, nb, tb1, static_cast<T>(u01_23(half ? wy.w2 : wy.w0)),
+                                       static_cast<T>(u01_23(half ? wy.w3 : wy.w1)));
+            }
+        }
+    } else {
+        const int h0 = static_cast<int>(static_cast<long long>(NH) * g / G);
+        const int h1 = static_cast<int>(static_cast<long long>(NH) * (g + 1) / G);
+        for (int h = h0 + static_cast<int>(threadIdx.x); h < h1; h += kDecThreads) {
+            const Nbr nb = neighbours<0>(h, d, L);
+            const Words wx = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gx), c3, k0, k1);
+            const Words wy = philox(static_cast<uint32_t>(h), n, e.slot_base + static_cast<uint32_t>(gy), c3, k0, k1);
+            ex += reinsert_site<T>(sx, J, NH, h, d, nb, tb2, static_cast<T>(u01_52(wx.w0, wx.w1)),
+                                   static_cast<T>(u01_52(wx.w2, wx.w3)));
+            ey += reinsert_site<T>(sy, J, NH, h, d, nb, tb1, static_cast<T>(u01_52(wy.w0, wy.w1)),
+                                   static_cast<T>(u01_52(wy.w2, wy.w3)));
+        }
+    }
+    const double Ex = block_sum<kDecThreads>(ex, red);
+    const double Ey = block_sum<kDecThreads>(ey, red);
+    if (threadIdx.x == 0) {
+        ds.epart[2 * g] = Ex;
+        ds.epart[2 * g + 1] = Ey;
+    }
+}
+
 // Per chain, after every pair: advance the exchange counter, update round trips
 // and clear the diagnostics of the pairs not attempted.
-__global__ void k_decimate_finish(hsg_ensemble e, int pairing) {
+// split_G > 0: the pass ran split over split_G workgroups per chain; the last pair's
+// energies are added up here.
+__global__ void k_decimate_finish(hsg_ensemble e, int pairing, int split_G) {
     const int n_chains = e.n_samples * e.n_chains;
     const int ch = blockIdx.x * blockDim.x + threadIdx.x;
     if (ch >= n_chains) return;
     const int R = e.n_temps;
+    if (split_G > 0) dec_split_energies(e, ch, split_G, dec_split(e, ch, split_G));
     if (e.work) {
         for (int i = 0; i < R - 1; ++i) {
             const bool sel = pairing == 0 || (pairing == 1 ? (i % 2) == 0 : (i % 2) == 1);
@@ -453,10 +625,41 @@ static hipError_t go_decimate(const hsg_ensemble& e, int pairing, int blocks, hi
     }
 }
 
+// Workgroups per chain for the split ascending pass (L > 16, scratch given): enough
+// to give the whole launch about 512 workgroups, at least 512 sites of D per
+// workgroup, within the scratch's partial area; 1 = use k_decimate.
+static int split_groups(const hsg_ensemble& e) {
+    if (e.L <= 16 || e.scratch == nullptr) return 1;
+    const int chains = e.n_samples * e.n_chains;
+    const long long NH = static_cast<long long>(e.L) * e.L * e.L / 2;
+    const ScratchLayout sl = scratch_layout(e);
+    const long long per_chain = static_cast<long long>(e.n_temps) * sl.max_tiles;  // doubles
+    long long G = (512 + chains - 1) / chains;
+    G = G < NH / 512 ? G : NH / 512;
+    G = G < (per_chain - 2) / 3 ? G : (per_chain - 2) / 3;
+    return G < 2 ? 1 : static_cast<int>(G);
+}
+
 hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
     const int chains = e.n_samples * e.n_chains;
     const int R = e.n_temps;
     if (chains <= 0 || R < 2) return hipSuccess;
+    const int G = pairing == 0 ? split_groups(e) : 1;
+    if (G > 1) {
+        for (int i = 0; i < R - 1; ++i) {
+            if (e.precision == HSG_FP64) {
+                hipLaunchKernelGGL(k_dec_split_terms<double>, dim3(chains * G), dim3(kDecThreads), 0, st, e, i, G);
+                hipLaunchKernelGGL(k_dec_split_apply<double>, dim3(chains * G), dim3(kDecThreads), 0, st, e, i, G);
+            } else {
+                hipLaunchKernelGGL(k_dec_split_terms<float>, dim3(chains * G), dim3(kDecThreads), 0, st, e, i, G);
+                hipLaunchKernelGGL(k_dec_split_apply<float>, dim3(chains * G), dim3(kDecThreads), 0, st, e, i, G);
+            }
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
+        hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing, G);
+        return hipGetLastError();
+    }
     int blocks = chains;
     if (pairing != 0) {
         const int first = pairing == 1 ? 0 : 1;
@@ -468,7 +671,7 @@ hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
                                                  : go_decimate<float>(e, pairing, blocks, st);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing);
+    hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing, 0);
     return hipGetLastError();
 }
 

@@ -119,9 +119,10 @@ def test_decimate_parity_fp32(L, pairing):
     gpu.check()
 
 
-@pytest.mark.parametrize("L", [8, 16])
+@pytest.mark.parametrize("L", [8, 16, 20, 24])
 def test_decimate_ascending_fp32(L):
-    """All pairs in ascending order (one workgroup per chain), FP32: along each chain
+    """All pairs in ascending order (one workgroup per chain up to L = 16, the pass split
+    over several workgroups per chain above), FP32: along each chain
     the pairs are compared in order until the first decision binary32 cannot settle
     (|ln A - ln u| within the bound); later pairs of that chain see states that may
     legitimately differ and are skipped."""
