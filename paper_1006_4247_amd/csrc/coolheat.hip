@@ -598,11 +598,301 @@ static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- split ascending pass
+// For L > 16 with few chains, each leg of pair i is spread over G workgroups, each
+// owning a slice of both sublattices, in two launches: k_ch_split_a maps the slice of
+// the leg's first sublattice (neighbours and own spins from the source configuration,
+// result into the slot's candidate buffer) and copies the slice of the other
+// sublattice; k_ch_split_b maps the second sublattice in the candidate buffer.  Each
+// leaves per-slice sums (log Jacobian, energy).  The decision of pair i is taken by
+// the cooling workgroups of pair i + 1 (every one alike, from the sums) before they
+// start, as only that leg depends on it; one of them updates the labels, counters and
+// energies, and each copies its slice of the accepted candidates over their spins.
+// The last pair is decided by k_ch_split_decide, and k_ch_split_finish advances the
+// exchange counter and the round trips.  Per chain and pair parity (pair i's sums are
+// written while pair i - 1's are read), in the scratch's partial area: ld[2][G],
+// h[2][G] and a record of both legs' slots and energies before the pair.  A slice is
+// the same range of sites h in every sublattice and component, for the maps and the
+// copies alike, so each site is copied and mapped by the workgroup that owns it.
+struct ChSplit {
+    double* ld;   // [leg][G] log Jacobian per slice (both half-steps)
+    double* hs;   // [leg][G] energy sum per slice (second half-step)
+    double* en;   // [leg] energy of the leg's configuration before the pair
+    int* slot;    // [leg] the leg's slot
+};
+
+__device__ __forceinline__ ChSplit ch_split(const hsg_ensemble& e, int ch, int G, int i) {
+    const ScratchLayout sl = scratch_layout(e);
+    double* base = reinterpret_cast<double*>(static_cast<unsigned char*>(e.scratch) + sl.partial) +
+                   (static_cast<size_t>(ch) * 2 + (i & 1)) * (4 * G + 3);
+    ChSplit c;
+    c.ld = base;
+    c.hs = base + 2 * G;
+    c.en = base + 4 * G;
+    c.slot = reinterpret_cast<int*>(base + 4 * G + 2);
+    return c;
+}
+
+// Pair i's acceptance from the records and sums (read-only while it is evaluated):
+// ln A = b1 H(x) + b2 H(y) - b1 H(C^-1 y) - b2 H(C x) + ln det J(x) - ln det J(C^-1 y).
+struct ChDecision {
+    bool ok;
+    int x, y;
+    double ld0, ld1, hx, hy;
+};
+
+__device__ __forceinline__ ChDecision ch_split_decision(const hsg_ensemble& e, int ch, int i, int G,
+                                                        const ChSplit& c) {
+    ChDecision d;
+    d.x = c.slot[0];
+    d.y = c.slot[1];
+    d.ld0 = d.ld1 = d.hx = d.hy = 0.0;
+    for (int g = 0; g < G; ++g) {
+        d.ld0 += c.ld[g];
+        d.ld1 += c.ld[G + g];
+        d.hx += c.hs[g];
+        d.hy += c.hs[G + g];
+    }
+    d.hx = -d.hx;  // H(C x) and H(C^-1 y)
+    d.hy = -d.hy;
+    const double b1 = e.betas[i], b2 = e.betas[i + 1];
+    const double lnA = b1 * c.en[0] + b2 * c.en[1] - b1 * d.hy - b2 * d.hx + d.ld0 - d.ld1;
+    const Words w = philox(static_cast<uint32_t>(i), e.swap_ctr[ch], e.chain_base + static_cast<uint32_t>(ch),
+                           kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
+    d.ok = log(u01_52(w.w0, w.w1)) < lnA;
+    return d;
+}
+
+// Labels, counters, energies and diagnostics of pair i after its decision (one thread).
+__device__ __forceinline__ void ch_split_commit(const hsg_ensemble& e, int ch, int i, const ChDecision& d) {
+    const int R = e.n_temps;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
+    W[2 * i] = d.ld0;
+    W[2 * i + 1] = d.ld1;
+    if (isnan(d.ld0) || isnan(d.ld1)) atomicOr(e.guard, 8);
+    st[2 * i] += 1;
+    if (d.ok) {
+        int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+        int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+        double* en = e.energy + static_cast<size_t>(ch) * R;
+        en[d.x] = d.hx;
+        en[d.y] = d.hy;
+        sot[i] = d.y;
+        sot[i + 1] = d.x;
+        tos[d.x] = i + 1;
+        tos[d.y] = i;
+        st[2 * i + 1] += 1;
+    }
+}
+
+// Slice [h0, h1) of every sublattice and component of candidate `slot` over its spins.
+template <typename T>
+__device__ __forceinline__ void ch_split_copy(const hsg_ensemble& e, size_t slot, int N, int h0, int h1) {
+    const ScratchLayout sl = scratch_layout(e);
+    const int NH = N / 2;
+    const T* src = reinterpret_cast<const T*>(static_cast<unsigned char*>(e.scratch) + sl.cand) + slot * 3 * N;
+    T* dst = static_cast<T*>(e.spins) + slot * 3 * N;
+    for (int plane = 0; plane < 6; ++plane)
+        for (int h = h0 + static_cast<int>(threadIdx.x); h < h1; h += kChThreads)
+            dst[plane * NH + h] = src[plane * NH + h];
+}
+
+// One half-step of a leg over sites [h0, h1) of sublattice p: fields from `nbr`, own
+// spins from `own`, results into `out` (may equal `own`); returns the log Jacobians'
+// sum and adds s'.S to *en if `want`.
+template <typename T, bool HEAT>
+__device__ __forceinline__ double ch_split_half(const T* nbr, const T* own, T* out, const T* __restrict__ J, int L,
+                                                int p, int h0, int h1, T eps, bool want, double* en) {
+    const int NH = L * L * L / 2;
+    const T* o0 = nbr + (0 * 2 + (1 - p)) * NH;
+    const T* o1 = nbr + (1 * 2 + (1 - p)) * NH;
+    const T* o2 = nbr + (2 * 2 + (1 - p)) * NH;
+    double ld = 0.0;
+    for (int h = h0 + static_cast<int>(threadIdx.x); h < h1; h += kChThreads) {
+        const Nbr nb = neighbours<0>(h, p, L);
+        T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int mu = d >> 1;
+            const T jj = (d & 1) ? J[(mu * 2 + (1 - p)) * NH + nb.n[d]] : J[(mu * 2 + p) * NH + h];
+            const int idx = nb.n[d];
+            Sx = fma(jj, o0[idx], Sx);
+            Sy = fma(jj, o1[idx], Sy);
+            Sz = fma(jj, o2[idx], Sz);
+        }
+        T sx = own[(0 * 2 + p) * NH + h], sy = own[(1 * 2 + p) * NH + h], sz = own[(2 * 2 + p) * NH + h];
+        ld += coolheat_site<T, HEAT>(sx, sy, sz, Sx, Sy, Sz, eps);
+        out[(0 * 2 + p) * NH + h] = sx;
+        out[(1 * 2 + p) * NH + h] = sy;
+        out[(2 * 2 + p) * NH + h] = sz;
+        if (want) {
+            const double dx = sx, dy = sy, dz = sz;
+            *en += fma(dz, static_cast<double>(Sz), fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+        }
+    }
+    return ld;
+}
+
+// Workgroup (chain, leg, slice g) of pair i's first launch.
+template <typename T>
+__global__ void __launch_bounds__(kChThreads) k_ch_split_a(hsg_ensemble e, T eps, int i, int G) {
+    __shared__ double red[kChThreads / 64];
+    const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
+    const int b = static_cast<int>(blockIdx.x);
+    const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
+    const ChSplit c = ch_split(e, ch, G, i);
+    const ScratchLayout sl = scratch_layout(e);
+    T* cand = reinterpret_cast<T*>(static_cast<unsigned char*>(e.scratch) + sl.cand);
+    T* spins = static_cast<T*>(e.spins);
+    const int h0 = static_cast<int>(static_cast<long long>(NH) * g / G);
+    const int h1 = static_cast<int>(static_cast<long long>(NH) * (g + 1) / G);
+    int slot;
+    double en_before;
+    bool from_cand = false;
+    if (leg == 0 && i > 0) {  // decide pair i - 1 first (uniform over the workgroup)
+        const ChSplit cp = ch_split(e, ch, G, i - 1);
+        const ChDecision d = ch_split_decision(e, ch, i - 1, G, cp);
+        if (d.ok) {  // its candidates become the spins of their slots, this slice here
+            ch_split_copy<T>(e, static_cast<size_t>(ch) * R + d.x, N, h0, h1);
+            ch_split_copy<T>(e, static_cast<size_t>(ch) * R + d.y, N, h0, h1);
+            __syncthreads();  // C x of this slice is saved before the map overwrites it
+        }
+        slot = d.ok ? d.x : cp.slot[1];
+        en_before = d.ok ? d.hx : cp.en[1];
+        from_cand = d.ok;
+        if (g == 0 && threadIdx.x == 0) ch_split_commit(e, ch, i - 1, d);
+    } else {
+        slot = label(e.slot_of_temp[ch * R + i + leg], R, e.guard);
+        en_before = e.energy[static_cast<size_t>(ch) * R + slot];
+    }
+    const size_t gs = static_cast<size_t>(ch) * R + slot;
+    const T* src = (from_cand ? cand : spins) + gs * 3 * N;
+    T* dst = cand + gs * 3 * N;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(ch / e.n_chains) * 3 * N;
+    const int p = leg;  // cooling maps sublattice 0 first, heating sublattice 1
+    double unused = 0.0;
+    const double ld = leg ? ch_split_half<T, true>(src, src, dst, J, L, p, h0, h1, eps, false, &unused)
+                          : ch_split_half<T, false>(src, src, dst, J, L, p, h0, h1, eps, false, &unused);
+    if (!from_cand) {  // the slice of the other sublattice into the candidate buffer
+        const int q = 1 - p;
+        for (int mu = 0; mu < 3; ++mu)
+            for (int h = h0 + static_cast<int>(threadIdx.x); h < h1; h += kChThreads)
+                dst[(mu * 2 + q) * NH + h] = src[(mu * 2 + q) * NH + h];
+    }
+    const double LD = block_sum<kChThreads>(ld, red);
+    if (threadIdx.x == 0) {
+        c.ld[leg * G + g] = LD;
+        if (g == 0) {
+            c.slot[leg] = slot;
+            c.en[leg] = en_before;
+        }
+    }
+}
+
+// Workgroup (chain, leg, slice g) of pair i's second launch.
+template <typename T>
+__global__ void __launch_bounds__(kChThreads) k_ch_split_b(hsg_ensemble e, T eps, int i, int G) {
+    __shared__ double red[kChThreads / 64];
+    const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
+    const int b = static_cast<int>(blockIdx.x);
+    const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
+    const ChSplit c = ch_split(e, ch, G, i);
+    const ScratchLayout sl = scratch_layout(e);
+    T* dst = reinterpret_cast<T*>(static_cast<unsigned char*>(e.scratch) + sl.cand) +
+             (static_cast<size_t>(ch) * R + c.slot[leg]) * 3 * N;
+    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(ch / e.n_chains) * 3 * N;
+    const int p = 1 - leg;
+    const int h0 = static_cast<int>(static_cast<long long>(NH) * g / G);
+    const int h1 = static_cast<int>(static_cast<long long>(NH) * (g + 1) / G);
+    double en = 0.0;
+    const double ld = leg ? ch_split_half<T, true>(dst, dst, dst, J, L, p, h0, h1, eps, true, &en)
+                          : ch_split_half<T, false>(dst, dst, dst, J, L, p, h0, h1, eps, true, &en);
+    const double LD = block_sum<kChThreads>(ld, red);
+    const double EN = block_sum<kChThreads>(en, red);
+    if (threadIdx.x == 0) {
+        c.ld[leg * G + g] += LD;
+        c.hs[leg * G + g] = EN;
+    }
+}
+
+// The last pair: decision, slice-wise copy of accepted candidates, commit.
+template <typename T>
+__global__ void __launch_bounds__(kChThreads) k_ch_split_decide(hsg_ensemble e, int i, int G) {
+    const int N = e.L * e.L * e.L, R = e.n_temps;
+    const int b = static_cast<int>(blockIdx.x);
+    const int g = b % G, ch = b / G;
+    const ChSplit c = ch_split(e, ch, G, i);
+    const ChDecision d = ch_split_decision(e, ch, i, G, c);
+    if (d.ok) {
+        const int NH = N / 2;
+        const int h0 = static_cast<int>(static_cast<long long>(NH) * g / G);
+        const int h1 = static_cast<int>(static_cast<long long>(NH) * (g + 1) / G);
+        ch_split_copy<T>(e, static_cast<size_t>(ch) * R + d.x, N, h0, h1);
+        ch_split_copy<T>(e, static_cast<size_t>(ch) * R + d.y, N, h0, h1);
+    }
+    if (g == 0 && threadIdx.x == 0) ch_split_commit(e, ch, i, d);
+}
+
+// Per chain, after the pass: exchange counter and round trips.
+__global__ void k_ch_split_finish(hsg_ensemble e) {
+    const int n_chains = e.n_samples * e.n_chains;
+    const int ch = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (ch >= n_chains) return;
+    const int R = e.n_temps;
+    e.swap_ctr[ch] += 1u;
+    const int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
+    for (int r = 0; r < R; ++r) {
+        const int Tr = tos[r];
+        if (Tr == 0) {
+            if (rs[r] == 2) rtt[r] += 1;
+            rs[r] = 1;
+        } else if (Tr == R - 1) {
+            if (rs[r] == 1) rs[r] = 2;
+        }
+    }
+}
+
+// Workgroups per leg for the split pass (L > 16): about 512 workgroups per launch, at
+// least 512 sites per slice, within the scratch's partial area; 1 = not split.
+static int ch_split_groups(const hsg_ensemble& e) {
+    if (e.L <= 16) return 1;
+    const int chains = e.n_samples * e.n_chains;
+    const long long NH = static_cast<long long>(e.L) * e.L * e.L / 2;
+    const ScratchLayout sl = scratch_layout(e);
+    const long long per_chain = static_cast<long long>(e.n_temps) * sl.max_tiles;  // doubles
+    long long G = (256 + chains - 1) / chains;
+    G = G < NH / 512 ? G : NH / 512;
+    G = G < (per_chain / 2 - 3) / 4 ? G : (per_chain / 2 - 3) / 4;  // two pair parities
+    return G < 2 ? 1 : static_cast<int>(G);
+}
+
+template <typename T>
+static hipError_t coolheat_split_pass(const hsg_ensemble& e, double eps, int G, hipStream_t st) {
+    const int chains = e.n_samples * e.n_chains, R = e.n_temps;
+    const T te = static_cast<T>(eps);
+    for (int i = 0; i < R - 1; ++i) {
+        hipLaunchKernelGGL(k_ch_split_a<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, te, i, G);
+        hipLaunchKernelGGL(k_ch_split_b<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, te, i, G);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_ch_split_decide<T>, dim3(chains * G), dim3(kChThreads), 0, st, e, R - 2, G);
+    hipLaunchKernelGGL(k_ch_split_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e);
+    return hipGetLastError();
+}
+
 hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipStream_t st) {
     const int R = e.n_temps;
     if (e.n_samples * e.n_chains <= 0 || R < 2) return hipSuccess;
     if (pairing == 0) {
         // ascending order: each pair sees the states the previous pair left
+        const int G = ch_split_groups(e);
+        if (G > 1)
+            return e.precision == HSG_FP64 ? coolheat_split_pass<double>(e, eps, G, st)
+                                           : coolheat_split_pass<float>(e, eps, G, st);
         // (pair i - 1 decided inside pair i's launch, the last pair by its own)
         for (int i = 0; i < R - 1; ++i) {
             hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i, 1, 1, i > 0, st)
