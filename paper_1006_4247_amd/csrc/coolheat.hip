@@ -371,49 +371,50 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg(hsg_ensemble e, T eps, int 
     }
 }
 
-// Decisions of the pairs i0 + istep m (m < npc) of chain ch; `last` advances the
-// exchange counter and the round trips (once per call).  cp[2 m + leg] receives the
-// slot whose candidate replaces its spins, or -1.
-__device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int istep, int npc, int last,
-                                      int* cp) {
+// Decision of pair i of chain ch with exchange counter n: cp[leg] receives the slot
+// whose candidate replaces its spins, or -1.
+__device__ __forceinline__ void coolheat_decide_pair(const hsg_ensemble& e, int ch, int i, uint32_t n, int* cp) {
     const int R = e.n_temps;
     const ScratchLayout sl = scratch_layout(e);
-    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    const double* cen = reinterpret_cast<const double*>(scr + sl.cand_energy);
+    const double* cen = reinterpret_cast<const double*>(static_cast<unsigned char*>(e.scratch) + sl.cand_energy) +
+                        static_cast<size_t>(ch) * R;
     int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
     int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
     double* en = e.energy + static_cast<size_t>(ch) * R;
     long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
-    double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
-    const uint32_t n = e.swap_ctr[ch];
+    const double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
     const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
-    for (int m = 0; m < npc; ++m) {
-        const int i = i0 + istep * m;
-        const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
-        const double b1 = e.betas[i], b2 = e.betas[i + 1];
-        const double lnA = b1 * en[x] + b2 * en[y] - b1 * cen[ch * R + y] - b2 * cen[ch * R + x] + W[2 * i] - W[2 * i + 1];
-        const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
-        st[2 * i] += 1;
-        const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
-        cp[2 * m] = ok ? x : -1;
-        cp[2 * m + 1] = ok ? y : -1;
-        if (ok) {
-            en[x] = cen[ch * R + x];
-            en[y] = cen[ch * R + y];
-            sot[i] = y;
-            sot[i + 1] = x;
-            tos[x] = i + 1;
-            tos[y] = i;
-            st[2 * i + 1] += 1;
-        }
+    const int x = label(sot[i], R, e.guard), y = label(sot[i + 1], R, e.guard);
+    const double b1 = e.betas[i], b2 = e.betas[i + 1];
+    const double lnA = b1 * en[x] + b2 * en[y] - b1 * cen[y] - b2 * cen[x] + W[2 * i] - W[2 * i + 1];
+    const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
+    st[2 * i] += 1;
+    const bool ok = log(u01_52(w.w0, w.w1)) < lnA;
+    cp[0] = ok ? x : -1;
+    cp[1] = ok ? y : -1;
+    if (ok) {
+        en[x] = cen[x];
+        en[y] = cen[y];
+        sot[i] = y;
+        sot[i + 1] = x;
+        tos[x] = i + 1;
+        tos[y] = i;
+        st[2 * i + 1] += 1;
     }
-    if (!last) return;
-    if (istep == 2)  // even / odd pairs: clear the entries of the pairs not attempted
+}
+
+// After the last decision of a call: clear the diagnostics of the pairs not attempted
+// (even / odd pairs), advance the exchange counter and update the round trips.
+__device__ __forceinline__ void coolheat_finish_chain(const hsg_ensemble& e, int ch, int i0, int istep) {
+    const int R = e.n_temps;
+    double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
+    if (istep == 2)
         for (int i = 1 - (i0 & 1); i < R - 1; i += 2) {
             W[2 * i] = 0.0;
             W[2 * i + 1] = 0.0;
         }
-    e.swap_ctr[ch] = n + 1u;
+    e.swap_ctr[ch] += 1u;
+    const int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
     int* rs = e.rt_state + static_cast<size_t>(ch) * R;
     long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
     for (int r = 0; r < R; ++r) {
@@ -427,16 +428,25 @@ __device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int
     }
 }
 
-// Decisions of the pairs i0 + istep m (m < npc) of one chain per thread; entry
-// (chain, m, leg) of the flags array names the slot whose candidate replaces its
-// spins, or -1.
-__global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc, int last) {
-    const int n_chains = e.n_samples * e.n_chains;
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n_chains) return;
+// Decisions of the pairs i0 + istep m (m < npc) of chain ch, in order; `last` finishes
+// the call.  cp[2 m + leg] receives the slot whose candidate replaces its spins, or -1.
+__device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int istep, int npc, int last,
+                                      int* cp) {
+    const uint32_t n = e.swap_ctr[ch];
+    for (int m = 0; m < npc; ++m) coolheat_decide_pair(e, ch, i0 + istep * m, n, cp + 2 * m);
+    if (last) coolheat_finish_chain(e, ch, i0, istep);
+}
+
+// Even or odd pairs: one thread per (chain, pair), the pairs of a call being disjoint;
+// entry (chain, m, leg) of the flags array names the slot whose candidate replaces its
+// spins, or -1.  The copy-back launch finishes each chain.
+__global__ void k_coolheat_decide(hsg_ensemble e, int i0, int istep, int npc) {
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= e.n_samples * e.n_chains * npc) return;
+    const int ch = t / npc, m = t - ch * npc;
     const ScratchLayout sl = scratch_layout(e);
     int* flags = reinterpret_cast<int*>(static_cast<unsigned char*>(e.scratch) + sl.flags);
-    coolheat_decide_chain(e, ch, i0, istep, npc, last, flags + static_cast<size_t>(ch) * npc * 2);
+    coolheat_decide_pair(e, ch, i0 + istep * m, e.swap_ctr[ch], flags + static_cast<size_t>(t) * 2);
 }
 
 // Ascending rounds (pair i of every chain): one workgroup per chain decides its pair
@@ -447,7 +457,8 @@ constexpr int kDecideCopyThreads = 512;
 constexpr int kPre = 6;
 
 template <typename T>
-__global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg_ensemble e, int i, int last) {
+__global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg_ensemble e, int i, int istep,
+                                                                             int last) {
     __shared__ int s_slot[2];
     const int ch = static_cast<int>(blockIdx.x);
     const int R = e.n_temps;
@@ -470,7 +481,7 @@ __global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg
             pre[leg][k] = v < nv ? src[v] : make_uint4(0, 0, 0, 0);
         }
     }
-    if (threadIdx.x == 0) coolheat_decide_chain(e, ch, i, 1, 1, last, s_slot);
+    if (threadIdx.x == 0) coolheat_decide_chain(e, ch, i, istep, 1, last, s_slot);
     __syncthreads();
 #pragma unroll
     for (int leg = 0; leg < 2; ++leg) {
@@ -491,18 +502,25 @@ __global__ void __launch_bounds__(kDecideCopyThreads) k_coolheat_decide_copy(hsg
 // Workgroup b copies candidate b of the decided pairs ((chain, m, leg) order), if
 // accepted, over the spins of its slot.
 template <typename T>
-__global__ void k_coolheat_copyback(hsg_ensemble e, int npc) {
+__global__ void k_coolheat_copyback(hsg_ensemble e, int i0, int istep, int npc) {
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const int ch = static_cast<int>(blockIdx.x) / (2 * npc);
+    if (static_cast<int>(blockIdx.x) % (2 * npc) == 0 && threadIdx.x == 0) coolheat_finish_chain(e, ch, i0, istep);
     const int r = reinterpret_cast<const int*>(scr + sl.flags)[blockIdx.x];
     if (r < 0) return;
-    const int ch = static_cast<int>(blockIdx.x) / (2 * npc);
     const size_t slot = static_cast<size_t>(ch) * e.n_temps + r;
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
     const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(scr + sl.cand) + slot * 3 * N);
     uint4* dst = reinterpret_cast<uint4*>(static_cast<T*>(e.spins) + slot * 3 * N);
     const size_t nv = 3 * N * sizeof(T) / 16;
     for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+}
+
+// A call that selects no pair: only the per-chain finish.
+__global__ void k_coolheat_finish(hsg_ensemble e, int i0, int istep) {
+    const int ch = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (ch < e.n_samples * e.n_chains) coolheat_finish_chain(e, ch, i0, istep);
 }
 
 template <typename T, int L, int NT, bool PREV>
@@ -529,7 +547,11 @@ static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, in
         return go_leg_nt<T, L, NTS, false>(e, eps, i0, istep, npc, blocks, st);
     }
     if (prev) return hipErrorInvalidValue;
-    return go_leg_nt<T, L, kChThreads, false>(e, eps, i0, istep, npc, blocks, st);
+    // many pairs per launch: binary32 legs with 512 threads, so that the three
+    // workgroups one CU's LDS holds at L = 16 carry 24 waves rather than 12 (measured
+    // 14 % faster at L = 16; binary64 legs, at 151 registers, lose occupancy instead)
+    constexpr int NTM = (sizeof(T) == 4 && NH >= 512) ? 512 : kChThreads;
+    return go_leg_nt<T, L, NTM, false>(e, eps, i0, istep, npc, blocks, st);
 }
 
 // Legs of the pairs i0 + istep m; prev (ascending, one pair per chain, L <= 16): the
@@ -566,14 +588,15 @@ static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, 
     }
 }
 
-static hipError_t launch_decide_copy(const hsg_ensemble& e, int i, int last, hipStream_t st) {
+// istep: 1 for an ascending pass, 2 for an even / odd call with one pair per chain.
+static hipError_t launch_decide_copy(const hsg_ensemble& e, int i, int istep, int last, hipStream_t st) {
     const int n_chains = e.n_samples * e.n_chains;
     if (e.precision == HSG_FP64)
         hipLaunchKernelGGL(k_coolheat_decide_copy<double>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e, i,
-                           last);
+                           istep, last);
     else
         hipLaunchKernelGGL(k_coolheat_decide_copy<float>, dim3(n_chains), dim3(kDecideCopyThreads), 0, st, e, i,
-                           last);
+                           istep, last);
     return hipGetLastError();
 }
 
@@ -586,15 +609,20 @@ static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int 
                                       : go_legs<float>(e, eps, i0, istep, npc, false, st);
         if (err != hipSuccess) return err;
     }
-    if (npc == 1) return launch_decide_copy(e, i0, last, st);  // decision and copy-back in one launch
-    hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep, npc, last);
+    if (npc == 1) return launch_decide_copy(e, i0, istep, last, st);  // decision and copy-back in one launch
+    if (npc == 0) {  // no pair selected (R = 2, odd pairs): the counters alone
+        hipLaunchKernelGGL(k_coolheat_finish, dim3((n_chains + 63) / 64), dim3(64), 0, st, e, i0, istep);
+        return hipGetLastError();
+    }
+    (void)last;  // even / odd pairs: one call is one round
+    hipLaunchKernelGGL(k_coolheat_decide, dim3((n_chains * npc + 63) / 64), dim3(64), 0, st, e, i0, istep, npc);
     err = hipGetLastError();
-    if (err != hipSuccess || npc == 0) return err;
+    if (err != hipSuccess) return err;
     const int blocks = n_chains * npc * 2;
     if (e.precision == HSG_FP64)
-        hipLaunchKernelGGL(k_coolheat_copyback<double>, dim3(blocks), dim3(256), 0, st, e, npc);
+        hipLaunchKernelGGL(k_coolheat_copyback<double>, dim3(blocks), dim3(256), 0, st, e, i0, istep, npc);
     else
-        hipLaunchKernelGGL(k_coolheat_copyback<float>, dim3(blocks), dim3(256), 0, st, e, npc);
+        hipLaunchKernelGGL(k_coolheat_copyback<float>, dim3(blocks), dim3(256), 0, st, e, i0, istep, npc);
     return hipGetLastError();
 }
 
@@ -899,7 +927,7 @@ hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipSt
                                                      : go_legs<float>(e, eps, i, 1, 1, i > 0, st);
             if (err != hipSuccess) return err;
         }
-        return launch_decide_copy(e, R - 2, 1, st);
+        return launch_decide_copy(e, R - 2, 1, 1, st);
     }
     const int first = pairing == 1 ? 0 : 1;
     const int npc = (R - first) / 2;

@@ -51,6 +51,26 @@ def test_coolheat_parity_fp64(L, pairing):
     gpu.check()
 
 
+@pytest.mark.parametrize("R", [2, 3, 4])
+def test_coolheat_short_ladders_fp64(R):
+    """Ladders with at most one selected pair per chain and call (and, at R = 2 with odd
+    pairs, none): a sequence of pairings, each call's diagnostics (zeros where not
+    attempted, whatever an earlier call left there), labels, counters, spins and
+    energies against the oracle."""
+    L, S, C = 4, 2, 2
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 500 + R, prec="fp64")
+    for call, pairing in enumerate([1, 2, 0, 2, 1, 0]):
+        w = gpu.coolheat_swap(EPS, pairing)
+        _, ld = ref.coolheat_swap(EPS, pairing)
+        torch.cuda.synchronize()
+        what = "coolheat fp64 R=%d call %d pairing %d" % (R, call, pairing)
+        assert np.max(np.abs(w.cpu().numpy() - ld)) <= 1e-9 * max(1.0, np.abs(ld).max()), what
+        st = compare_ints(gpu, ref, what)
+        assert np.max(np.abs(st["spins"] - ref.spins)) <= 1e-12, what
+        assert np.max(np.abs(st["energy"] - ref.energy)) <= 1e-9, what
+    gpu.check()
+
+
 def _max_k(ref, eps):
     L = ref.L
     k = 0.0
