@@ -69,6 +69,11 @@ def test_abi_version_and_validation_without_gpu():
     assert lib.hsg_swap(ctypes.byref(d), 1, 7, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_anneal_swap(ctypes.byref(d), 1, 2, 1, 3, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_sweep(None, 0, 1, 1, 3, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_sweep_measure(ctypes.byref(d), 1, -1, 1, 3, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_sweep_measure(ctypes.byref(d), 1, 1, 0, 0, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_sweep_measure(ctypes.byref(d), 1, 1, 1, 3, None) == _abi.HSG_ERR_INVALID
+    assert b"NULL" in lib.hsg_last_error()
+    assert lib.hsg_sweep_measure(None, 0, 1, 1, 3, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_mlp_forward(None, 0, 64, 2, None, 1, None, None, None) == _abi.HSG_ERR_INVALID
 
 
