@@ -29,7 +29,9 @@ N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
 VALU_PEAK_TOPS = N_CU * LANES_PER_CU * CLOCK_GHZ / 1e3  # 39.3 T lane-instructions/s
 
 # Algorithmic VALU operations per site update (one add/mul/FMA/compare/select, one
-# transcendental or one integer op each = 1; derived in DESIGN.md, "Roofline").
+# transcendental or one integer op each = 1), counted from the update formulas: a
+# 1 HB + 3 OR sweep averages (18 + 45 + 80/2 + 3 (18 + 12)) / 4 = 48.25 per update in
+# binary32, where one Philox block serves two sites.
 OPS_LOCAL_FIELD = 18          # 6 neighbours x 3 components, one FMA each
 OPS_OVERRELAX = 12            # s.S, |S|^2, 2(s.S)/S^2, f S - s
 OPS_HEATBATH = 45             # field norm and direction, R, w, c, sin(theta), frame, sin/cos(phi), s'

@@ -1,7 +1,7 @@
 """Helpers that set up the same ensemble on the GPU (through the C ABI) and in the
 oracle, from oracle-generated initial state, and compare them.
 
-Tolerances (derived in DESIGN.md, "Parity bars"):
+Tolerances, each from the arithmetic of the step it bounds:
   * one lattice sweep of one kind (heat-bath or overrelaxation; the paper's unit of
     a sweep, Sec. III.C/IV): max |ds| <= 1e-5 (FP32) / 1e-12 (FP64) per component.
     The only admitted exceptions are sites within two lattice steps of a site whose
