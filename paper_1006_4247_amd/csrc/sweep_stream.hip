@@ -1,10 +1,13 @@
 // Streaming sweep kernels: one launch per half-sweep, for lattices whose
 // replica does not fit in one workgroup's LDS (L = 24, 32, ...).
 //
-// Grid x = tiles of NT site pairs (h, h + N/4) of the updated sublattice,
-// grid y = groups of RB replicas of one sample.  A thread loads its sites'
-// couplings once and reuses them for the RB replicas; neighbour spins of the
-// other sublattice come through L1/L2 (each is read by six sites).  The energy
+// Work item = (group of RB replicas of one sample, tile of NT site pairs (h, h + N/4)
+// of the updated sublattice), tiles fastest, in a one-dimensional grid whose blocks
+// take the work items XCD by XCD (xcd_order): a replica's tiles run on one XCD, so
+// the neighbouring z-planes a tile reads from its neighbours' ranges come from that
+// XCD's L2.  A thread loads its sites' couplings once and reuses them for the RB
+// replicas; neighbour spins of the other sublattice come through L1/L2 (each is read
+// by six sites).  The energy
 // of the last half-sweep of a sweep is reduced per tile into scratch and
 // summed over tiles in a fixed order by a finalize kernel (deterministic).
 #include "hsg_device.h"
@@ -56,15 +59,16 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
     const int C = e.n_chains, R = e.n_temps;
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    const int tile = blockIdx.x;
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int tile = item % a.n_tiles, group = item / a.n_tiles;
     const int q = tile * NT + static_cast<int>(threadIdx.x);
     const bool active = q < NQ;
 
     int slot0, leg = 0, K = 0, ipair = 0;
     if (!a.anneal) {
-        slot0 = blockIdx.y * RB;
+        slot0 = group * RB;
     } else {
-        const LegInfo li = leg_of_block(e, blockIdx.y, a.parity);
+        const LegInfo li = leg_of_block(e, group, a.parity);
         if (a.step >= li.K) return;  // uniform over the block
         slot0 = li.slot;
         leg = li.leg;
@@ -242,7 +246,7 @@ __global__ void k_stream_anneal_copy(hsg_ensemble e, int parity) {
 // ---------------------------------------------------------------- dispatch
 template <typename T, int LT, int NT, int RB>
 static hipError_t launch_half(const hsg_ensemble& e, const StreamArgs& a, int gy, hipStream_t st) {
-    hipLaunchKernelGGL((k_stream_half<T, LT, NT, RB>), dim3(a.n_tiles, gy), dim3(NT), 0, st, e, a);
+    hipLaunchKernelGGL((k_stream_half<T, LT, NT, RB>), dim3(a.n_tiles * gy), dim3(NT), 0, st, e, a);
     return hipGetLastError();
 }
 
