@@ -767,7 +767,7 @@ template <typename T>
 __global__ void __launch_bounds__(kChThreads) k_ch_split_a(hsg_ensemble e, T eps, int i, int G) {
     __shared__ double red[kChThreads / 64];
     const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
-    const int b = static_cast<int>(blockIdx.x);
+    const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));  // a chain's slices on one XCD
     const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
     const ChSplit c = ch_split(e, ch, G, i);
     const ScratchLayout sl = scratch_layout(e);
@@ -823,7 +823,7 @@ template <typename T>
 __global__ void __launch_bounds__(kChThreads) k_ch_split_b(hsg_ensemble e, T eps, int i, int G) {
     __shared__ double red[kChThreads / 64];
     const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
-    const int b = static_cast<int>(blockIdx.x);
+    const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));  // a chain's slices on one XCD
     const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
     const ChSplit c = ch_split(e, ch, G, i);
     const ScratchLayout sl = scratch_layout(e);
@@ -848,7 +848,7 @@ __global__ void __launch_bounds__(kChThreads) k_ch_split_b(hsg_ensemble e, T eps
 template <typename T>
 __global__ void __launch_bounds__(kChThreads) k_ch_split_decide(hsg_ensemble e, int i, int G) {
     const int N = e.L * e.L * e.L, R = e.n_temps;
-    const int b = static_cast<int>(blockIdx.x);
+    const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));  // a chain's slices on one XCD
     const int g = b % G, ch = b / G;
     const ChSplit c = ch_split(e, ch, G, i);
     const ChDecision d = ch_split_decision(e, ch, i, G, c);

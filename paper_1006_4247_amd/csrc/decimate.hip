@@ -430,7 +430,9 @@ __global__ void __launch_bounds__(kDecThreads) k_dec_split_terms(hsg_ensemble e,
     __shared__ double red[kDecThreads / 64];
     const int L = e.L, N = L * L * L, NH = N / 2;
     const int R = e.n_temps, C = e.n_chains;
-    const int ch = static_cast<int>(blockIdx.x) / G, g = static_cast<int>(blockIdx.x) % G;
+    // a chain's slices on one XCD (they read each other's neighbouring sites)
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int ch = item / G, g = item % G;
     const DecSplit ds = dec_split(e, ch, G);
     const int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
     const uint32_t n = e.swap_ctr[ch];
@@ -476,7 +478,9 @@ __global__ void __launch_bounds__(kDecThreads) k_dec_split_apply(hsg_ensemble e,
     __shared__ double red[kDecThreads / 64];
     const int L = e.L, N = L * L * L, NH = N / 2, NQ = N / 4;
     const int R = e.n_temps, C = e.n_chains;
-    const int ch = static_cast<int>(blockIdx.x) / G, g = static_cast<int>(blockIdx.x) % G;
+    // a chain's slices on one XCD (they read each other's neighbouring sites)
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int ch = item / G, g = item % G;
     const DecSplit ds = dec_split(e, ch, G);
     const uint32_t n = e.swap_ctr[ch];
     const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
