@@ -872,7 +872,8 @@ void hsgref_coolheat_batch(int L, int S, int C, int R, const double* J, double* 
                            const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
                            uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
                            int64_t* rt_trips, uint32_t chain_base, uint64_t seed, int pairing,
-                           double eps, double* log_ratio_out, double* logdet_out)
+                           double eps, double* log_ratio_out, double* logdet_out,
+                           const double* eps_pair)
 {
     int N = L * L * L;
     int ch, n_chain = S * C;
@@ -899,8 +900,13 @@ void hsgref_coolheat_batch(int L, int S, int C, int R, const double* J, double* 
             gy = (size_t)ch * R + (size_t)sot[i + 1];
             memcpy(cx, spins + gx * rep, rep * sizeof(double));
             memcpy(cy, spins + gy * rep, rep * sizeof(double));
-            ldx = hsgref_coolheat(L, Js, cx, eps, 0);
-            ldy = hsgref_coolheat(L, Js, cy, eps, 1);
+            /* the map's parameter: one for every pair, or pair i's own (Sec. IV suggests
+             * tuning it for each pair of temperatures) */
+            {
+                double e_i = eps_pair ? eps_pair[i] : eps;
+                ldx = hsgref_coolheat(L, Js, cx, e_i, 0);
+                ldy = hsgref_coolheat(L, Js, cy, e_i, 1);
+            }
             hx = hsgref_energy(L, Js, cx);
             hy = hsgref_energy(L, Js, cy);
             lnA = b1 * energy[gx] + b2 * energy[gy] - b1 * hy - b2 * hx + ldx - ldy;

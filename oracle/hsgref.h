@@ -91,7 +91,8 @@ void hsgref_coolheat_batch(int L, int S, int C, int R, const double* J, double* 
                            const double* betas, int32_t* temp_of_slot, int32_t* slot_of_temp,
                            uint32_t* swap_ctr, double* energy, int64_t* stats, int32_t* rt_state,
                            int64_t* rt_trips, uint32_t chain_base, uint64_t seed, int pairing,
-                           double eps, double* log_ratio_out, double* logdet_out);
+                           double eps, double* log_ratio_out, double* logdet_out,
+                           const double* eps_pair);
 void hsgref_measure_batch(int L, int S, int C, int R, const double* spins, const double* energy,
                           const int32_t* slot_of_temp, double* Q, double* chi, double* e);
 void hsgref_roundtrip_update(int R, const int32_t* temp_of_slot, int32_t* rt_state,

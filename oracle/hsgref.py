@@ -80,7 +80,7 @@ def lib():
             "hsgref_coolheat": (_c_dbl, [_c_int, _dp, _dp, _c_dbl, _c_int]),
             "hsgref_coolheat_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _dp, _i32p,
                                              _i32p, _u32p, _dp, _i64p, _i32p, _i64p, _c_u32,
-                                             _c_u64, _c_int, _c_dbl, _dp, _dp]),
+                                             _c_u64, _c_int, _c_dbl, _dp, _dp, _dp]),
             "hsgref_measure_batch": (None, [_c_int, _c_int, _c_int, _c_int, _dp, _dp, _i32p, _dp,
                                             _dp, _dp]),
             "hsgref_roundtrip_update": (None, [_c_int, _i32p, _i32p, _i64p]),
@@ -388,17 +388,25 @@ class RefEnsemble:
         return lnA, role
 
     def coolheat_swap(self, eps, pairing=0):
-        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs.  Returns
-        ln A [S][C][R-1] and the log Jacobians of cooling at x and at C^-1 y
-        [S][C][R-1][2] (zeros where not attempted)."""
+        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs; eps is one
+        map parameter for every pair or an array of R-1, one per pair of temperatures
+        (Sec. IV).  Returns ln A [S][C][R-1] and the log Jacobians of cooling at x and at
+        C^-1 y [S][C][R-1][2] (zeros where not attempted)."""
         lnA = np.zeros((self.S, self.C, self.R - 1))
         ld = np.zeros((self.S, self.C, self.R - 1, 2))
+        if np.ndim(eps) == 0:
+            eps0, eps_pair = float(eps), None
+        else:
+            eps_pair = np.ascontiguousarray(eps, dtype=np.float64)
+            if eps_pair.shape != (self.R - 1,):
+                raise ValueError("per-pair eps must have R - 1 = %d entries" % (self.R - 1))
+            eps0 = 0.0
         lib().hsgref_coolheat_batch(self.L, self.S, self.C, self.R, dp(self.J), dp(self.spins),
                                     dp(self.betas), i32p(self.temp_of_slot),
                                     i32p(self.slot_of_temp), u32p(self.swap_ctr), dp(self.energy),
                                     i64p(self.stats), i32p(self.rt_state), i64p(self.rt_trips),
-                                    self.chain_base, self.seed, int(pairing), float(eps), dp(lnA),
-                                    dp(ld))
+                                    self.chain_base, self.seed, int(pairing), eps0, dp(lnA),
+                                    dp(ld), dp(eps_pair) if eps_pair is not None else None)
         return lnA, ld
 
     def measure(self):

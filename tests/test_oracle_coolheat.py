@@ -209,3 +209,51 @@ def test_forest_law_is_stationary_under_coolheat_exchange():
         assert abs(z) < 4.0, (r, H.mean(), mean, z)
         zv = (H.var(ddof=1) - var) / (var * np.sqrt(2.0 / (C - 1)))
         assert abs(zv) < 4.5, (r, H.var(ddof=1), var, zv)
+
+
+def _fresh(L, S, C, betas, seed):
+    ref = hsgref.RefEnsemble(L, S, C, betas, seed)
+    ref.init_couplings()
+    ref.init_spins()
+    ref.sweep(2, 1, 3)
+    return ref
+
+
+@pytest.mark.parametrize("pairing", [0, 1, 2])
+def test_per_pair_eps_constant_equals_one_eps(pairing):
+    """One parameter per pair of temperatures (Sec. IV), all equal: the same exchange
+    as the single parameter, bit for bit."""
+    L, S, C = 4, 2, 2
+    betas = hsgref.geometric_betas(0.5, 2.0, 6)
+    a, b = _fresh(L, S, C, betas, 51), _fresh(L, S, C, betas, 51)
+    for _ in range(3):
+        la, da = a.coolheat_swap(0.03, pairing)
+        lb, db = b.coolheat_swap(np.full(5, 0.03), pairing)
+        assert np.array_equal(la, lb) and np.array_equal(da, db)
+    for k in ("spins", "temp_of_slot", "slot_of_temp", "swap_ctr", "stats", "rt_state", "rt_trips", "energy"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_per_pair_eps_zero_pairs_are_plain_exchanges():
+    """Disjoint (even) pairs with their own parameters: a pair with eps_i = 0 has the
+    plain acceptance ln A = (b2 - b1)(H(y) - H(x)) of Eq. (1) and zero Jacobians, a pair
+    with eps_i > 0 the cooling / heating one, which differs from it."""
+    L, S, C = 4, 2, 2
+    betas = hsgref.geometric_betas(0.5, 2.0, 6)
+    ref = _fresh(L, S, C, betas, 52)
+    eps = np.array([0.0, 0.0, 0.04, 0.0, 0.0])
+    H = ref.energy.copy()
+    sot = ref.slot_of_temp.copy()
+    lnA, ld = ref.coolheat_swap(eps, 1)
+    for s in range(S):
+        for c in range(C):
+            for i in (0, 4):
+                x, y = sot[s, c, i], sot[s, c, i + 1]
+                plain = (betas[i + 1] - betas[i]) * (H[s, c, y] - H[s, c, x])
+                assert abs(lnA[s, c, i] - plain) <= 1e-10 * max(1.0, abs(plain))
+                assert np.all(ld[s, c, i] == 0.0)
+            x, y = sot[s, c, 2], sot[s, c, 3]
+            plain = (betas[3] - betas[2]) * (H[s, c, y] - H[s, c, x])
+            assert abs(lnA[s, c, 2] - plain) > 1e-6 and np.all(ld[s, c, 2] != 0.0)
+    with pytest.raises(ValueError):
+        ref.coolheat_swap(np.zeros(3), 1)
