@@ -216,6 +216,16 @@ hsg_status hsg_decimate_swap(const hsg_ensemble* ens, int n_ens, int pairing, vo
 hsg_status hsg_coolheat_swap(const hsg_ensemble* ens, int n_ens, int pairing, double eps,
                              void* stream);
 
+/* hsg_coolheat_swap with one map parameter per pair of temperatures (paper Sec. IV
+ * suggests tuning eps for each pair of beta values separately): pair i of ensemble e
+ * uses eps[o_e + i], o_e = sum over the ensembles before e of (n_temps - 1).  eps:
+ * device array of doubles, 8-byte aligned, owned by the caller; values must be
+ * finite and >= 0 (a value with eps |S| >= 1 at some site rejects that pair and sets
+ * guard bit 8, as above; other values are not checked on the host).  Same needs and
+ * outputs as hsg_coolheat_swap; equal values give its results bit for bit. */
+hsg_status hsg_coolheat_swap_pairs(const hsg_ensemble* ens, int n_ens, int pairing, const double* eps,
+                                   void* stream);
+
 /* Overlap (paper Sec. II): Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between the
  * chain-0 and chain-1 configurations at each temperature, chi = Q:Q / N, and
  * e_temp = H/N by temperature (the paper's E is -e).  Q and chi need C >= 2. */

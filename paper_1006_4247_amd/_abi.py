@@ -54,6 +54,7 @@ SIGNATURES = {
     "hsg_anneal_swap": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_decimate_swap": (_i, [_E, _i, _i, _vp]),
     "hsg_coolheat_swap": (_i, [_E, _i, _i, ctypes.c_double, _vp]),
+    "hsg_coolheat_swap_pairs": (_i, [_E, _i, _i, _vp, _vp]),
     "hsg_measure": (_i, [_E, _i, _vp]),
     "hsg_sweep_measure": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_check": (_i, [_E, _i, _vp]),

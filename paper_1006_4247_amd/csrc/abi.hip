@@ -259,8 +259,27 @@ hsg_status hsg_coolheat_swap(const hsg_ensemble* ens, int n_ens, int pairing, do
         if (!ens[i].work || !aligned(ens[i].work, 8))
             return fail(HSG_ERR_INVALID, "ensemble %d: work ([S][C][R-1][2] doubles) is required", i);
     for (int i = 0; i < n_ens; ++i) {
-        hipError_t err = hsg::launch_coolheat(ens[i], pairing, eps, as_stream(stream));
+        hipError_t err = hsg::launch_coolheat(ens[i], pairing, eps, nullptr, as_stream(stream));
         if (err != hipSuccess) return device(err, "cooling/heating exchange");
+    }
+    return ok();
+}
+
+hsg_status hsg_coolheat_swap_pairs(const hsg_ensemble* ens, int n_ens, int pairing, const double* eps,
+                                   void* stream) {
+    if (pairing < 0 || pairing > 2) return fail(HSG_ERR_INVALID, "pairing must be 0, 1 or 2 (got %d)", pairing);
+    if (!eps || !aligned(eps, 8))
+        return fail(HSG_ERR_INVALID, "eps must be a device array of doubles, 8-byte aligned");
+    hsg_status s = check_all(ens, n_ens, kState | kScratch);
+    if (s != HSG_OK) return s;
+    for (int i = 0; i < n_ens; ++i)
+        if (!ens[i].work || !aligned(ens[i].work, 8))
+            return fail(HSG_ERR_INVALID, "ensemble %d: work ([S][C][R-1][2] doubles) is required", i);
+    size_t off = 0;
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err = hsg::launch_coolheat(ens[i], pairing, 0.0, eps + off, as_stream(stream));
+        if (err != hipSuccess) return device(err, "cooling/heating exchange");
+        off += static_cast<size_t>(ens[i].n_temps - 1);
     }
     return ok();
 }

@@ -163,6 +163,18 @@ __device__ __forceinline__ ChItem ch_item(const hsg_ensemble& e, int b, int i0, 
 __device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int istep, int npc, int last,
                                       int* cp);
 
+// The map parameter: one for every pair, or pair i's own from a device array
+// (pair != nullptr).
+struct ChEps {
+    double eps;
+    const double* pair;
+};
+
+template <typename T>
+__device__ __forceinline__ T ch_eps(const ChEps& c, int i) {
+    return static_cast<T>(c.pair ? c.pair[i] : c.eps);
+}
+
 // LDS-resident legs (L <= 16): the replica in LDS, couplings from global memory.
 // NT threads: 256 where a launch holds many pairs, more for the single pair per
 // chain of an ascending round, whose legs then finish sooner.
@@ -174,7 +186,7 @@ __device__ void coolheat_decide_chain(const hsg_ensemble& e, int ch, int i0, int
 // depends on pair i0 - 1; the heating leg takes the configuration at beta_{i0+1},
 // which pair i0 - 1 does not touch, and runs meanwhile.
 template <typename T, int L, int NT, bool PREV>
-__global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+__global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, ChEps ce, int i0, int istep, int npc) {
     constexpr int N = L * L * L, NH = N / 2;
     constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -212,6 +224,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, 
     } else {
         it = ch_item(e, blockIdx.x, i0, istep, npc);
     }
+    const T eps = ch_eps<T>(ce, it.i);
     const int smp = it.ch / e.n_chains;
     const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
     T* own = spins + static_cast<size_t>(it.slot) * 3 * N;
@@ -280,7 +293,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, T eps, 
 // sits in this slot's candidate buffer and is copied back over its spins before the
 // map overwrites it.
 template <typename T, int NT, bool PREV>
-__global__ void __launch_bounds__(NT) k_coolheat_leg(hsg_ensemble e, T eps, int i0, int istep, int npc) {
+__global__ void __launch_bounds__(NT) k_coolheat_leg(hsg_ensemble e, ChEps ce, int i0, int istep, int npc) {
     __shared__ double red[NT / 64];
     const int L = e.L, N = L * L * L, NH = N / 2;
     const int nv = 3 * N * static_cast<int>(sizeof(T)) / 16;
@@ -316,6 +329,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg(hsg_ensemble e, T eps, int 
     } else {
         it = ch_item(e, blockIdx.x, i0, istep, npc);
     }
+    const T eps = ch_eps<T>(ce, it.i);
     const int smp = it.ch / e.n_chains;
     const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
     T* c = cand + static_cast<size_t>(it.slot) * 3 * N;
@@ -524,17 +538,18 @@ __global__ void k_coolheat_finish(hsg_ensemble e, int i0, int istep) {
 }
 
 template <typename T, int L, int NT, bool PREV>
-static hipError_t go_leg_nt(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, hipStream_t st) {
+static hipError_t go_leg_nt(const hsg_ensemble& e, const ChEps& ce, int i0, int istep, int npc, int blocks,
+                            hipStream_t st) {
     constexpr size_t lds = 3 * L * L * L * sizeof(T);
     auto kern = k_coolheat_leg_res<T, L, NT, PREV>;
     const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
     if (a != hipSuccess) return a;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, eps, i0, istep, npc);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, ce, i0, istep, npc);
     return hipGetLastError();
 }
 
 template <typename T, int L>
-static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, int npc, int blocks, bool prev,
+static hipError_t go_leg_res(const hsg_ensemble& e, const ChEps& ce, int i0, int istep, int npc, int blocks, bool prev,
                              hipStream_t st) {
     // one pair per chain: binary32 legs with 1024 threads, binary64 with 512 (its site
     // maps need more than the 128 registers a thread of a 1024-thread workgroup gets)
@@ -543,46 +558,45 @@ static hipError_t go_leg_res(const hsg_ensemble& e, T eps, int i0, int istep, in
     constexpr int NT1 = NH >= NTMAX ? NTMAX : ((NH + 63) / 64) * 64;
     constexpr int NTS = NT1 > kChThreads ? NT1 : kChThreads;
     if (npc == 1) {
-        if (prev) return go_leg_nt<T, L, NTS, true>(e, eps, i0, istep, npc, blocks, st);
-        return go_leg_nt<T, L, NTS, false>(e, eps, i0, istep, npc, blocks, st);
+        if (prev) return go_leg_nt<T, L, NTS, true>(e, ce, i0, istep, npc, blocks, st);
+        return go_leg_nt<T, L, NTS, false>(e, ce, i0, istep, npc, blocks, st);
     }
     if (prev) return hipErrorInvalidValue;
     // many pairs per launch: binary32 legs with 512 threads, so that the three
     // workgroups one CU's LDS holds at L = 16 carry 24 waves rather than 12 (measured
     // 14 % faster at L = 16; binary64 legs, at 151 registers, lose occupancy instead)
     constexpr int NTM = (sizeof(T) == 4 && NH >= 512) ? 512 : kChThreads;
-    return go_leg_nt<T, L, NTM, false>(e, eps, i0, istep, npc, blocks, st);
+    return go_leg_nt<T, L, NTM, false>(e, ce, i0, istep, npc, blocks, st);
 }
 
 // Legs of the pairs i0 + istep m; prev (ascending, one pair per chain, L <= 16): the
 // cooling legs first decide and copy pair i0 - 1.
 template <typename T>
-static hipError_t go_legs(const hsg_ensemble& e, double eps, int i0, int istep, int npc, bool prev,
+static hipError_t go_legs(const hsg_ensemble& e, const ChEps& ce, int i0, int istep, int npc, bool prev,
                           hipStream_t st) {
     const int blocks = e.n_samples * e.n_chains * npc * 2;
-    const T te = static_cast<T>(eps);
     switch (e.L) {
-        case 4: return go_leg_res<T, 4>(e, te, i0, istep, npc, blocks, prev, st);
-        case 6: return go_leg_res<T, 6>(e, te, i0, istep, npc, blocks, prev, st);
-        case 8: return go_leg_res<T, 8>(e, te, i0, istep, npc, blocks, prev, st);
-        case 10: return go_leg_res<T, 10>(e, te, i0, istep, npc, blocks, prev, st);
-        case 12: return go_leg_res<T, 12>(e, te, i0, istep, npc, blocks, prev, st);
-        case 14: return go_leg_res<T, 14>(e, te, i0, istep, npc, blocks, prev, st);
-        case 16: return go_leg_res<T, 16>(e, te, i0, istep, npc, blocks, prev, st);
+        case 4: return go_leg_res<T, 4>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 6: return go_leg_res<T, 6>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 8: return go_leg_res<T, 8>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 10: return go_leg_res<T, 10>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 12: return go_leg_res<T, 12>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 14: return go_leg_res<T, 14>(e, ce, i0, istep, npc, blocks, prev, st);
+        case 16: return go_leg_res<T, 16>(e, ce, i0, istep, npc, blocks, prev, st);
         default: {
             // one pair per chain: 1024 threads in binary32, 512 in binary64 (as above)
             constexpr int NTG = sizeof(T) == 4 ? 1024 : 512;
             if (npc == 1 && prev)
-                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, true>), dim3(blocks), dim3(NTG), 0, st, e, te, i0, istep,
+                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, true>), dim3(blocks), dim3(NTG), 0, st, e, ce, i0, istep,
                                    npc);
             else if (npc == 1)
-                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, false>), dim3(blocks), dim3(NTG), 0, st, e, te, i0, istep,
+                hipLaunchKernelGGL((k_coolheat_leg<T, NTG, false>), dim3(blocks), dim3(NTG), 0, st, e, ce, i0, istep,
                                    npc);
             else if (prev)
                 return hipErrorInvalidValue;
             else
                 hipLaunchKernelGGL((k_coolheat_leg<T, kChThreads, false>), dim3(blocks), dim3(kChThreads), 0, st, e,
-                                   te, i0, istep, npc);
+                                   ce, i0, istep, npc);
             return hipGetLastError();
         }
     }
@@ -600,13 +614,13 @@ static hipError_t launch_decide_copy(const hsg_ensemble& e, int i, int istep, in
     return hipGetLastError();
 }
 
-static hipError_t coolheat_round(const hsg_ensemble& e, double eps, int i0, int istep, int npc, int last,
+static hipError_t coolheat_round(const hsg_ensemble& e, const ChEps& ce, int i0, int istep, int npc, int last,
                                  hipStream_t st) {
     const int n_chains = e.n_samples * e.n_chains;
     hipError_t err = hipSuccess;
     if (npc > 0) {
-        err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i0, istep, npc, false, st)
-                                      : go_legs<float>(e, eps, i0, istep, npc, false, st);
+        err = e.precision == HSG_FP64 ? go_legs<double>(e, ce, i0, istep, npc, false, st)
+                                      : go_legs<float>(e, ce, i0, istep, npc, false, st);
         if (err != hipSuccess) return err;
     }
     if (npc == 1) return launch_decide_copy(e, i0, istep, last, st);  // decision and copy-back in one launch
@@ -764,8 +778,9 @@ __device__ __forceinline__ double ch_split_half(const T* nbr, const T* own, T* o
 
 // Workgroup (chain, leg, slice g) of pair i's first launch.
 template <typename T>
-__global__ void __launch_bounds__(kChThreads) k_ch_split_a(hsg_ensemble e, T eps, int i, int G) {
+__global__ void __launch_bounds__(kChThreads) k_ch_split_a(hsg_ensemble e, ChEps ce, int i, int G) {
     __shared__ double red[kChThreads / 64];
+    const T eps = ch_eps<T>(ce, i);
     const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
     const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));  // a chain's slices on one XCD
     const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
@@ -820,8 +835,9 @@ __global__ void __launch_bounds__(kChThreads) k_ch_split_a(hsg_ensemble e, T eps
 
 // Workgroup (chain, leg, slice g) of pair i's second launch.
 template <typename T>
-__global__ void __launch_bounds__(kChThreads) k_ch_split_b(hsg_ensemble e, T eps, int i, int G) {
+__global__ void __launch_bounds__(kChThreads) k_ch_split_b(hsg_ensemble e, ChEps ce, int i, int G) {
     __shared__ double red[kChThreads / 64];
+    const T eps = ch_eps<T>(ce, i);
     const int L = e.L, N = L * L * L, NH = N / 2, R = e.n_temps;
     const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));  // a chain's slices on one XCD
     const int g = b % G, leg = (b / G) & 1, ch = b / (2 * G);
@@ -898,12 +914,11 @@ static int ch_split_groups(const hsg_ensemble& e) {
 }
 
 template <typename T>
-static hipError_t coolheat_split_pass(const hsg_ensemble& e, double eps, int G, hipStream_t st) {
+static hipError_t coolheat_split_pass(const hsg_ensemble& e, const ChEps& ce, int G, hipStream_t st) {
     const int chains = e.n_samples * e.n_chains, R = e.n_temps;
-    const T te = static_cast<T>(eps);
     for (int i = 0; i < R - 1; ++i) {
-        hipLaunchKernelGGL(k_ch_split_a<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, te, i, G);
-        hipLaunchKernelGGL(k_ch_split_b<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, te, i, G);
+        hipLaunchKernelGGL(k_ch_split_a<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, ce, i, G);
+        hipLaunchKernelGGL(k_ch_split_b<T>, dim3(chains * 2 * G), dim3(kChThreads), 0, st, e, ce, i, G);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -912,26 +927,27 @@ static hipError_t coolheat_split_pass(const hsg_ensemble& e, double eps, int G, 
     return hipGetLastError();
 }
 
-hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipStream_t st) {
+hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, const double* eps_pair, hipStream_t st) {
+    const ChEps ce{eps, eps_pair};
     const int R = e.n_temps;
     if (e.n_samples * e.n_chains <= 0 || R < 2) return hipSuccess;
     if (pairing == 0) {
         // ascending order: each pair sees the states the previous pair left
         const int G = ch_split_groups(e);
         if (G > 1)
-            return e.precision == HSG_FP64 ? coolheat_split_pass<double>(e, eps, G, st)
-                                           : coolheat_split_pass<float>(e, eps, G, st);
+            return e.precision == HSG_FP64 ? coolheat_split_pass<double>(e, ce, G, st)
+                                           : coolheat_split_pass<float>(e, ce, G, st);
         // (pair i - 1 decided inside pair i's launch, the last pair by its own)
         for (int i = 0; i < R - 1; ++i) {
-            hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, eps, i, 1, 1, i > 0, st)
-                                                     : go_legs<float>(e, eps, i, 1, 1, i > 0, st);
+            hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, ce, i, 1, 1, i > 0, st)
+                                                     : go_legs<float>(e, ce, i, 1, 1, i > 0, st);
             if (err != hipSuccess) return err;
         }
         return launch_decide_copy(e, R - 2, 1, 1, st);
     }
     const int first = pairing == 1 ? 0 : 1;
     const int npc = (R - first) / 2;
-    return coolheat_round(e, eps, first, 2, npc, 1, st);
+    return coolheat_round(e, ce, first, 2, npc, 1, st);
 }
 
 }  // namespace hsg

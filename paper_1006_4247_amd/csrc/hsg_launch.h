@@ -52,7 +52,8 @@ hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st);
 hipError_t launch_anneal_decide(const hsg_ensemble& e, int parity, hipStream_t st);
 hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st);
 hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st);
-hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, hipStream_t st);
+// eps_pair: nullptr (eps for every pair) or a device array of n_temps - 1 parameters.
+hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, const double* eps_pair, hipStream_t st);
 
 // MLP
 hipError_t launch_mlp_forward(const float* p, int I, int H, int O, const float* x, int B,

@@ -193,12 +193,35 @@ class Ensemble:
         return self.work
 
     def coolheat_swap(self, eps, pairing=0):
-        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs; afterwards
+        """Cooling / heating exchange (paper Sec. III.B) of the selected pairs; eps is one
+        map parameter for every pair, or R - 1 of them, one per pair of temperatures
+        (Sec. IV; a sequence or a float64 tensor on this device).  Afterwards
         work[..., i, 0] and work[..., i, 1] hold ln det J_C(x) and ln det J_C(C^-1 y) of
         pair i (zeros where not attempted)."""
-        _abi.check(_abi.lib().hsg_coolheat_swap(ctypes.byref(self.desc), 1, int(pairing),
-                                                float(eps), self._stream()))
+        if isinstance(eps, torch.Tensor) or np.ndim(eps) > 0:
+            t = self.eps_pairs_tensor(eps)
+            self._eps_pairs = t  # kept alive while the launch may still read it
+            _abi.check(_abi.lib().hsg_coolheat_swap_pairs(ctypes.byref(self.desc), 1, int(pairing),
+                                                          _ptr(t), self._stream()))
+        else:
+            _abi.check(_abi.lib().hsg_coolheat_swap(ctypes.byref(self.desc), 1, int(pairing),
+                                                    float(eps), self._stream()))
         return self.work
+
+    def eps_pairs_tensor(self, eps):
+        """Per-pair map parameters as the float64 device tensor the exchange reads: a
+        tensor already in that form is used as it is; anything else (a sequence, an
+        array, a tensor elsewhere) is copied once and the copy waited for."""
+        if (isinstance(eps, torch.Tensor) and eps.dtype == torch.float64 and eps.device == self.device
+                and eps.is_contiguous()):
+            t = eps
+        else:
+            a = eps.detach().cpu().numpy() if isinstance(eps, torch.Tensor) else np.asarray(eps)
+            t = torch.tensor(a.astype(np.float64), device=self.device)
+            torch.cuda.synchronize(self.device)
+        if tuple(t.shape) != (self.R - 1,):
+            raise ValueError("per-pair eps must have R - 1 = %d entries" % (self.R - 1))
+        return t
 
     def measure(self):
         _abi.check(_abi.lib().hsg_measure(ctypes.byref(self.desc), 1, self._stream()))

@@ -27,12 +27,24 @@ class PTRun:
                  series_len=0, tunings=None, anneal_sweep=None, eps=0.0):
         if mode not in ("plain", "anneal", "decimate", "coolheat"):
             raise ValueError("mode must be 'plain', 'anneal', 'decimate' or 'coolheat'")
-        self.eps = float(eps)
+        # cooling / heating parameter: one number, R - 1 per-pair values shared by the
+        # ensembles, or one such sequence per ensemble (prepared on the device here, so
+        # that steps and graph captures copy nothing)
+        scalar = not isinstance(eps, (list, tuple, torch.Tensor)) and np.ndim(eps) == 0
+        self.eps = eps if scalar else None
         if pairing is None:
             pairing = 0 if mode == "plain" else -1
         if isinstance(ensembles, Ensemble):
             ensembles = [ensembles]
         self.ens = list(ensembles)
+        if self.eps is not None:
+            self.eps = float(self.eps)
+            self.eps_of = [self.eps] * len(self.ens)
+        else:
+            nested = (isinstance(eps, (list, tuple)) and len(eps) == len(self.ens)
+                      and (isinstance(eps[0], torch.Tensor) or np.ndim(eps[0]) > 0))
+            per = list(eps) if nested else [eps] * len(self.ens)
+            self.eps_of = [e.eps_pairs_tensor(x) for e, x in zip(self.ens, per)]
         self.n_hb, self.n_or = n_hb, n_or
         self.mode = mode
         self.pairing = pairing
@@ -73,7 +85,7 @@ class PTRun:
         elif self.mode == "decimate":
             e.decimate_swap(self.pairing if self.pairing >= 0 else parity + 1)
         elif self.mode == "coolheat":
-            e.coolheat_swap(self.eps, self.pairing if self.pairing >= 0 else parity + 1)
+            e.coolheat_swap(self.eps_of[i], self.pairing if self.pairing >= 0 else parity + 1)
         else:
             e.anneal_swap(parity, *self.anneal_sweep)
 
@@ -149,7 +161,8 @@ class PTRun:
         with open(prefix + ".json", "w") as fh:
             json.dump({"parity": self.parity, "steps_done": self.steps_done, "n_classes": len(self.ens),
                        "mode": self.mode, "pairing": self.pairing, "n_hb": self.n_hb, "n_or": self.n_or,
-                       "eps": self.eps}, fh)
+                       "eps": self.eps if self.eps is not None
+                       else [t.cpu().numpy().tolist() for t in self.eps_of]}, fh)
 
     def restore(self, prefix):
         """Load the state written by save() into this run's ensembles (same shapes)."""

@@ -273,3 +273,71 @@ def test_forest_law_stationary_under_gpu_coolheat(prec):
         zv = (H.var(ddof=1) - var) / (var * np.sqrt(2.0 / (C - 1)))
         assert abs(zv) < 4.5, (r, H.var(ddof=1), var, zv)
     gpu.check()
+
+
+@pytest.mark.parametrize("L", [4, 16, 20])
+@pytest.mark.parametrize("pairing", [0, 1, 2])
+def test_coolheat_per_pair_eps_parity_fp64(L, pairing):
+    """One map parameter per pair of temperatures (Sec. IV), through
+    hsg_coolheat_swap_pairs: the LDS-resident legs (L = 4, 16; at 16 ascending pairs
+    decide inside the next pair's launch) and the split pass (L = 20) against the
+    oracle, two calls."""
+    S, C, R = 2, 2, 5
+    eps = np.array([0.005, 0.02, 0.0, 0.012])
+    gpu, ref = make_pair(L, S, C, _betas(R), SEED + 700 + 10 * L + pairing, prec="fp64")
+    for call in range(2):
+        w = gpu.coolheat_swap(eps, pairing)
+        _, ld = ref.coolheat_swap(eps, pairing)
+        torch.cuda.synchronize()
+        what = "per-pair eps fp64 L=%d pairing %d call %d" % (L, pairing, call)
+        assert np.max(np.abs(w.cpu().numpy() - ld)) <= 1e-9 * max(1.0, np.abs(ld).max()), what
+        st = compare_ints(gpu, ref, what)
+        assert np.max(np.abs(st["spins"] - ref.spins)) <= 1e-12, what
+        assert np.max(np.abs(st["energy"] - ref.energy)) <= 1e-9, what
+    gpu.check()
+
+
+@pytest.mark.parametrize("L", [16, 24])
+def test_coolheat_equal_per_pair_eps_equals_one_eps(L):
+    """Equal per-pair parameters give the single-parameter exchange bit for bit
+    (binary32; L = 16 LDS-resident, L = 24 split pass), ascending and even pairs."""
+    S, C, R = 4, 2, 9
+    a = hsg.Ensemble(L, S, C, _betas(R, 0.8, 2.0), SEED + 800 + L, precision="fp32")
+    b = hsg.Ensemble(L, S, C, _betas(R, 0.8, 2.0), SEED + 800 + L, precision="fp32")
+    for e in (a, b):
+        e.init_couplings()
+        e.init_spins()
+        e.sweep(2, 1, 3)
+    eps_t = torch.full((R - 1,), 0.01, dtype=torch.float64, device=b.device)
+    for pairing in (0, 1, 0):
+        a.coolheat_swap(0.01, pairing)
+        b.coolheat_swap(eps_t, pairing)
+    torch.cuda.synchronize()
+    for k in ("spins", "temp_of_slot", "slot_of_temp", "energy", "swap_stats", "work", "rt_trips"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    a.check()
+    b.check()
+
+
+def test_coolheat_per_pair_eps_in_graph_replay():
+    """PTRun with per-pair parameters prepared on the device: replays of a captured
+    step equal eager steps."""
+    from paper_1006_4247_amd import runtime
+    L, S, C, R = 8, 3, 2, 6
+    eps = [0.02, 0.015, 0.01, 0.008, 0.006]
+    ens = [hsg.Ensemble(L, S, C, _betas(R, 0.8, 3.0), SEED + 900, precision="fp32") for _ in range(2)]
+    for e in ens:
+        e.init_couplings()
+        e.init_spins()
+    ra = runtime.PTRun([ens[0]], 1, 3, mode="coolheat", eps=eps)
+    rb = runtime.PTRun([ens[1]], 1, 3, mode="coolheat", eps=eps)
+    rb.capture()
+    for _ in range(3):
+        ra.step(rb.graph_steps)
+        rb.replay()
+        ra.synchronize()
+        for k in ("spins", "slot_of_temp", "energy", "swap_stats"):
+            assert torch.equal(getattr(ens[0], k), getattr(ens[1], k)), k
+    assert ens[0].swap_stats[..., 1].sum() > 0
+    ra.check()
+    rb.check()
