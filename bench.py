@@ -49,6 +49,8 @@ DEFAULT = "plain-pt-L16-S64-C2-R24"
 # short tuning runs scan
 COOLHEAT_EPS_PAPER = {16: 0.017, 24: 0.01}
 COOLHEAT_EPS_GRID = (0.001, 0.002, 0.003, 0.004, 0.005, 0.006, 0.008)
+# the per-pair tuner's finer grid (each pair keeps its best)
+COOLHEAT_EPS_GRID_PAIRS = (0.001, 0.0015, 0.002, 0.0025, 0.003, 0.0035, 0.004, 0.005, 0.006)
 
 
 def algorithmic_ops_per_update(n_hb, n_or, prec):
@@ -276,11 +278,13 @@ PAPER_T_MIN, PAPER_T_MAX = 0.12, 0.19
 PAPER_LADDERS = {16: dict(n_temps=15, n_or=20), 24: dict(n_temps=27, n_or=30), 32: dict(n_temps=43, n_or=40)}
 
 
-STUDY_METHODS = ("standard", "decimation", "coolheat")
+STUDY_METHODS = ("standard", "decimation", "coolheat", "coolheat_pairs")
+STUDY_DEFAULT = ("standard", "decimation", "coolheat")
 
 
-def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_METHODS, n_temps=0):
-    """Standard, decimated and cooling / heating tempering (or a subset, `methods`) on
+def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_DEFAULT, n_temps=0):
+    """Standard, decimated and cooling / heating tempering (or a subset, `methods`; with
+    "coolheat_pairs", cooling / heating with its parameter tuned per pair) on
     the paper's ladder for L (Sec. IV; n_temps > 0 replaces its N_T, as in the paper's
     N_T = 22 runs at L = 24), all pairs in ascending order every cycle, on the same S
     coupling sets (fresh Gaussian sets; the paper's ten are unpublished) with 2 chains:
@@ -308,7 +312,8 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
             done += k
             print("[paper-ladder L=%d] %s %d/%d" % (L, what, done, n), file=sys.stderr, flush=True)
 
-    for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat")):
+    for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat"),
+                         ("coolheat_pairs", "coolheat")):
         if method not in methods:
             continue
         e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
@@ -318,8 +323,11 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         eps, table = 0.0, None
         steps(runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False), equil // 2,
               method + " equilibration (plain)")
-        if mode == "coolheat":
+        if method == "coolheat":
             eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID, steps=300, n_hb=1, n_or=n_or, pairing=0)
+        elif method == "coolheat_pairs":
+            eps, table = runtime.tune_coolheat_eps_pairs(e, COOLHEAT_EPS_GRID_PAIRS, steps=300, n_hb=1,
+                                                         n_or=n_or, pairing=0)
         steps(runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, measure=False), equil - equil // 2,
               method + " equilibration")
         torch.cuda.synchronize()
@@ -360,6 +368,9 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
             d["eps"] = r["eps"]
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
             d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
+        if m == "coolheat_pairs":
+            d["eps_per_pair"] = [float(x) for x in r["eps"]]
+            d["tuner_acceptance_per_pair"] = {("%g" % k): [round(x, 4) for x in v] for k, v in r["table"].items()}
         if m != "standard" and std is not None:
             cost = (r["gpu_s"] / cycles) / (std["gpu_s"] / cycles)  # GPU time per cycle vs standard
             d["speedup_vs_standard"] = {
@@ -459,7 +470,7 @@ def main():
     ap.add_argument("--study-sets", type=int, default=64, help="coupling sets of the paper-ladder study")
     ap.add_argument("--study-cycles", type=int, nargs=2, default=[10000, 20000], metavar=("EQUIL", "MEASURE"),
                     help="equilibration and measurement cycles of the paper-ladder study")
-    ap.add_argument("--study-methods", nargs="+", choices=STUDY_METHODS, default=list(STUDY_METHODS),
+    ap.add_argument("--study-methods", nargs="+", choices=STUDY_METHODS, default=list(STUDY_DEFAULT),
                     help="tempering methods of the paper-ladder study")
     ap.add_argument("--study-temps", type=int, default=0, metavar="N_T",
                     help="number of temperatures of the paper-ladder study (default: the paper's for L)")

@@ -258,3 +258,22 @@ def tune_coolheat_eps(ens, grid, steps=200, n_hb=1, n_or=3, pairing=-1):
         table[float(eps)] = float(acc.mean())
     best = max(table, key=table.get)
     return best, table
+
+
+def tune_coolheat_eps_pairs(ens, grid, steps=200, n_hb=1, n_or=3, pairing=-1):
+    """Per-pair tuning, as the paper suggests (Sec. IV): the same short runs at each
+    eps of `grid`, keeping for every pair of temperatures the eps with its highest
+    acceptance (a pair's acceptance depends on its own parameter).  Returns (eps per
+    pair [R-1], {eps: acceptance per pair})."""
+    table = {}
+    for eps in grid:
+        run = PTRun([ens], n_hb, n_or, mode="coolheat", eps=eps, measure=False, pairing=pairing)
+        st0 = ens.swap_stats.cpu().numpy().copy()
+        run.step(steps)
+        run.synchronize()
+        st = ens.swap_stats.cpu().numpy() - st0
+        table[float(eps)] = st[..., 1].sum(axis=(0, 1)) / np.maximum(st[..., 0].sum(axis=(0, 1)), 1)
+    keys = list(table)
+    acc = np.stack([table[k] for k in keys])  # [grid][R-1]
+    best = np.array([keys[j] for j in np.argmax(acc, axis=0)], dtype=np.float64)
+    return best, {k: v.tolist() for k, v in table.items()}
