@@ -74,6 +74,10 @@ def test_abi_version_and_validation_without_gpu():
     assert lib.hsg_sweep_measure(ctypes.byref(d), 1, 1, 1, 3, None) == _abi.HSG_ERR_INVALID
     assert b"NULL" in lib.hsg_last_error()
     assert lib.hsg_sweep_measure(None, 0, 1, 1, 3, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_coolheat_swap_pairs(ctypes.byref(d), 1, 0, None, None) == _abi.HSG_ERR_INVALID
+    assert b"eps" in lib.hsg_last_error()
+    assert lib.hsg_coolheat_swap_pairs(ctypes.byref(d), 1, 5, None, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_coolheat_swap(ctypes.byref(d), 1, 0, -1.0, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_mlp_forward(None, 0, 64, 2, None, 1, None, None, None) == _abi.HSG_ERR_INVALID
 
 
