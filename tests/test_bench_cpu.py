@@ -1,0 +1,35 @@
+"""The benchmark's host-side contract, without a GPU: the one-GPU rule, the
+algorithmic operation and byte counts its roofline divides by, and the HBM-traffic
+summary it reports (only while it was taken on the current kernel sources)."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_algorithmic_counts():
+    # per update: local field 18, heat-bath 45, Philox 80 per block (two sites per block
+    # in binary32), overrelaxation 12; 1 HB + 3 OR
+    assert bench.algorithmic_ops_per_update(1, 3, "fp32") == (18 + 45 + 40 + 3 * 30) / 4
+    assert bench.algorithmic_ops_per_update(1, 3, "fp64") == (18 + 45 + 80 + 3 * 30) / 4
+    w = bench.WORKLOADS[bench.DEFAULT]
+    N, slots = w["L"] ** 3, w["S"] * w["C"] * w["R"]
+    # parity-1 half read, all written, couplings once per sample (4-byte spins)
+    assert bench.hbm_bytes_per_launch(w) == slots * (3 * (N // 2) * 4 + 3 * N * 4) + w["S"] * 3 * N * 4
+    assert bench.resident_kernel_name(w) == "k_resident<float,16,512>"
+
+
+def test_traffic_summary_is_current_or_absent():
+    w = bench.WORKLOADS[bench.DEFAULT]
+    t = bench.measured_traffic(bench.DEFAULT)
+    assert t is None or abs(t / bench.hbm_bytes_per_launch(w) - 1.0) < 0.01
