@@ -21,7 +21,8 @@ class PTRun:
     set on the ensembles); mode 'decimate': decimated exchange (paper Sec. III.A),
     alternating even / odd pairs, or all pairs ascending every step if pairing == 0;
     mode 'coolheat': cooling / heating exchange (paper Sec. III.B) with parameter
-    `eps`, pairs as for 'decimate'."""
+    `eps` (one number, R - 1 per-pair values, or one such sequence per ensemble),
+    pairs as for 'decimate'."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
                  series_len=0, tunings=None, anneal_sweep=None, eps=0.0):
