@@ -363,7 +363,12 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
              "t_R_per_set": q(r["t_R"]), "round_trips": int(r["trips"].sum()),
              "tau_int_chi_Tmin_c4": q(r["tau"]), "gpu_s": round(r["gpu_s"], 2),
-             "ms_per_cycle": round(r["gpu_s"] / cycles * 1e3, 4)}
+             "ms_per_cycle": round(r["gpu_s"] / cycles * 1e3, 4),
+             # per coupling set, in set order, so that runs of one method each on the same
+             # sets (same seed) can be paired set by set
+             "sets": {"acceptance": [round(float(x), 5) for x in r["acc_set"]],
+                      "t_R": [round(float(x), 1) for x in r["t_R"]],
+                      "tau_int_chi_Tmin_c4": [round(float(x), 3) for x in r["tau"]]}}
         if m == "coolheat":
             d["eps"] = r["eps"]
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
