@@ -49,6 +49,9 @@ DEFAULT = "plain-pt-L16-S64-C2-R24"
 # short tuning runs scan
 COOLHEAT_EPS_PAPER = {16: 0.017, 24: 0.01}
 COOLHEAT_EPS_GRID = (0.001, 0.002, 0.003, 0.004, 0.005, 0.006, 0.008)
+# the best eps falls with L (0.003 at L = 16, 0.002 at L = 24, the grid's 0.001 at
+# L = 32), so the L = 32 study's grid reaches below 0.001; the others keep the grid above
+COOLHEAT_EPS_GRID_STUDY = {32: (0.0004, 0.0006, 0.0008, 0.001, 0.0015, 0.002, 0.003)}
 # the per-pair tuner's finer grid (each pair keeps its best)
 COOLHEAT_EPS_GRID_PAIRS = (0.001, 0.0015, 0.002, 0.0025, 0.003, 0.0035, 0.004, 0.005, 0.006)
 
@@ -324,7 +327,8 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         steps(runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False), equil // 2,
               method + " equilibration (plain)")
         if method == "coolheat":
-            eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID, steps=300, n_hb=1, n_or=n_or, pairing=0)
+            eps, table = runtime.tune_coolheat_eps(e, COOLHEAT_EPS_GRID_STUDY.get(L, COOLHEAT_EPS_GRID), steps=300,
+                                                   n_hb=1, n_or=n_or, pairing=0)
         elif method == "coolheat_pairs":
             eps, table = runtime.tune_coolheat_eps_pairs(e, COOLHEAT_EPS_GRID_PAIRS, steps=300, n_hb=1,
                                                          n_or=n_or, pairing=0)
