@@ -351,8 +351,11 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         trips = rt.sum(axis=(1, 2)).astype(np.float64)
         t_R = cycles * C * R / np.maximum(trips, 1.0)
         tau = np.array([analysis.tau_int(chi[:, s, R - 1], c=4.0)[0] for s in range(S)])
-        res[method] = dict(acc_set=acc_set, acc_pair=acc_pair, t_R=t_R, tau=tau, trips=trips, gpu_s=dt,
-                           eq_s=eq_s, eps=eps, table=table)
+        # the paper's other two windows (Sec. IV.B), for how the speed-up depends on c
+        tau_c = {c: np.array([analysis.tau_int(chi[:, s, R - 1], c=float(c))[0] for s in range(S)])
+                 for c in (6, 10)}
+        res[method] = dict(acc_set=acc_set, acc_pair=acc_pair, t_R=t_R, tau=tau, tau_c=tau_c, trips=trips,
+                           gpu_s=dt, eq_s=eq_s, eps=eps, table=table)
 
     def q(a):
         a = np.asarray(a, dtype=np.float64)
@@ -366,13 +369,16 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
     for m, r in res.items():
         d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
              "t_R_per_set": q(r["t_R"]), "round_trips": int(r["trips"].sum()),
-             "tau_int_chi_Tmin_c4": q(r["tau"]), "gpu_s": round(r["gpu_s"], 2),
+             "tau_int_chi_Tmin_c4": q(r["tau"]), "tau_int_chi_Tmin_c6": q(r["tau_c"][6]),
+             "tau_int_chi_Tmin_c10": q(r["tau_c"][10]), "gpu_s": round(r["gpu_s"], 2),
              "ms_per_cycle": round(r["gpu_s"] / cycles * 1e3, 4),
              # per coupling set, in set order, so that runs of one method each on the same
              # sets (same seed) can be paired set by set
              "sets": {"acceptance": [round(float(x), 5) for x in r["acc_set"]],
                       "t_R": [round(float(x), 1) for x in r["t_R"]],
-                      "tau_int_chi_Tmin_c4": [round(float(x), 3) for x in r["tau"]]}}
+                      "tau_int_chi_Tmin_c4": [round(float(x), 3) for x in r["tau"]],
+                      "tau_int_chi_Tmin_c6": [round(float(x), 3) for x in r["tau_c"][6]],
+                      "tau_int_chi_Tmin_c10": [round(float(x), 3) for x in r["tau_c"][10]]}}
         if m == "coolheat":
             d["eps"] = r["eps"]
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
@@ -386,6 +392,8 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
                 "acceptance": round(float(np.mean(r["acc_set"] / np.maximum(std["acc_set"], 1e-12))), 3),
                 "round_trip": round(float(np.mean(std["t_R"] / r["t_R"])), 3),
                 "tau_int_chi": round(float(np.mean(std["tau"] / r["tau"])), 3),
+                "tau_int_chi_c6": round(float(np.mean(std["tau_c"][6] / r["tau_c"][6])), 3),
+                "tau_int_chi_c10": round(float(np.mean(std["tau_c"][10] / r["tau_c"][10])), 3),
                 # the same per GPU-second: per-cycle speed-ups over the relative cost of a cycle
                 "round_trip_per_gpu_s": round(float(np.mean(std["t_R"] / r["t_R"])) / cost, 3),
                 "tau_int_chi_per_gpu_s": round(float(np.mean(std["tau"] / r["tau"])) / cost, 3)}
