@@ -294,6 +294,52 @@ void hsgref_hb_uniforms(int L, int rng32, uint64_t seed, uint32_t slot_global, u
     }
 }
 
+/* Batch forms of the single-site pieces above, for tests that ask how an update
+ * responds when its field is moved: plain loops over the same functions, no new
+ * arithmetic.  fields: S_out[x] = S_x for the sites of `parity` (zeros elsewhere);
+ * uniforms: r1[x], r2[x] of the heat-bath at those sites; the `_many` forms apply
+ * one update per row of their [n][3] inputs. */
+void hsgref_fields(int L, const double* J, const double* s, int parity, double* S_out)
+{
+    int N = L * L * L, x;
+    for (x = 0; x < N; ++x) {
+        double* S = S_out + (size_t)x * 3;
+        if (hsgref_parity(L, x) == parity) {
+            hsgref_local_field(L, J, s, x, S);
+        } else {
+            S[0] = S[1] = S[2] = 0.0;
+        }
+    }
+}
+
+void hsgref_hb_uniforms_all(int L, int rng32, uint64_t seed, uint32_t slot_global, uint32_t t,
+                            uint32_t hs, int parity, double* r1, double* r2)
+{
+    int N = L * L * L, x;
+    for (x = 0; x < N; ++x) {
+        if (hsgref_parity(L, x) == parity) {
+            hsgref_hb_uniforms(L, rng32, seed, slot_global, t, hs, x, r1 + x, r2 + x);
+        } else {
+            r1[x] = r2[x] = 0.0;
+        }
+    }
+}
+
+void hsgref_heatbath_many(int n, const double* S, const double* beta, const double* r1,
+                          const double* r2, double* out)
+{
+    int i;
+    for (i = 0; i < n; ++i)
+        hsgref_heatbath_spin(S + (size_t)i * 3, beta[i], r1[i], r2[i], out + (size_t)i * 3);
+}
+
+void hsgref_overrelax_many(int n, const double* s, const double* S, double* out)
+{
+    int i;
+    for (i = 0; i < n; ++i)
+        hsgref_overrelax_spin(s + (size_t)i * 3, S + (size_t)i * 3, out + (size_t)i * 3);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Energies                                                                   */
 /* ------------------------------------------------------------------------- */

@@ -42,6 +42,12 @@ void hsgref_init_spins(int L, int n_slots, uint32_t slot_base, uint64_t seed,
 void   hsgref_local_field(int L, const double* J, const double* s, int x, double S[3]);
 void   hsgref_heatbath_spin(const double S[3], double beta, double r1, double r2, double out[3]);
 void   hsgref_overrelax_spin(const double s[3], const double S[3], double out[3]);
+void   hsgref_fields(int L, const double* J, const double* s, int parity, double* S_out);
+void   hsgref_hb_uniforms_all(int L, int rng32, uint64_t seed, uint32_t slot_global, uint32_t t,
+                              uint32_t hs, int parity, double* r1, double* r2);
+void   hsgref_heatbath_many(int n, const double* S, const double* beta, const double* r1,
+                            const double* r2, double* out);
+void   hsgref_overrelax_many(int n, const double* s, const double* S, double* out);
 void   hsgref_hb_uniforms(int L, int rng32, uint64_t seed, uint32_t slot_global, uint32_t t,
                           uint32_t hs, int x, double* r1, double* r2);
 

@@ -52,6 +52,11 @@ def lib():
             "hsgref_overrelax_spin": (None, [_dp, _dp, _dp]),
             "hsgref_hb_uniforms": (None, [_c_int, _c_int, _c_u64, _c_u32, _c_u32, _c_u32, _c_int,
                                           _dp, _dp]),
+            "hsgref_fields": (None, [_c_int, _dp, _dp, _c_int, _dp]),
+            "hsgref_hb_uniforms_all": (None, [_c_int, _c_int, _c_u64, _c_u32, _c_u32, _c_u32,
+                                              _c_int, _dp, _dp]),
+            "hsgref_heatbath_many": (None, [_c_int, _dp, _dp, _dp, _dp, _dp]),
+            "hsgref_overrelax_many": (None, [_c_int, _dp, _dp, _dp]),
             "hsgref_energy": (_c_dbl, [_c_int, _dp, _dp]),
             "hsgref_sublattice_energy": (_c_dbl, [_c_int, _dp, _dp, _c_int]),
             "hsgref_halfsweep": (None, [_c_int, _dp, _dp, _c_int, _c_int, _c_dbl, _c_u64, _c_u32,
@@ -206,6 +211,44 @@ def hb_uniforms(L, rng32, seed, slot_global, t, hs, x):
     lib().hsgref_hb_uniforms(L, int(rng32), seed, slot_global, t, hs, int(x),
                              ctypes.byref(r1), ctypes.byref(r2))
     return r1.value, r2.value
+
+
+def fields(L, J, s, par):
+    """Local fields [N][3] of the sites of parity `par` (zeros at the other sites)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros((L ** 3, 3))
+    lib().hsgref_fields(L, dp(J), dp(s), int(par), dp(out))
+    return out
+
+
+def hb_uniforms_all(L, rng32, seed, slot_global, t, hs, par):
+    """Heat-bath uniforms (r1 [N], r2 [N]) of the sites of parity `par` (zeros elsewhere)."""
+    r1 = np.zeros(L ** 3)
+    r2 = np.zeros(L ** 3)
+    lib().hsgref_hb_uniforms_all(L, int(rng32), seed, slot_global, t, hs, int(par), dp(r1), dp(r2))
+    return r1, r2
+
+
+def heatbath_many(S, beta, r1, r2):
+    """Heat-bath updates, one per row of S [n][3] with beta, r1, r2 [n]."""
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    n = S.shape[0]
+    b = np.ascontiguousarray(np.broadcast_to(beta, (n,)), dtype=np.float64)
+    r1 = np.ascontiguousarray(r1, dtype=np.float64)
+    r2 = np.ascontiguousarray(r2, dtype=np.float64)
+    out = np.zeros((n, 3))
+    lib().hsgref_heatbath_many(n, dp(S), dp(b), dp(r1), dp(r2), dp(out))
+    return out
+
+
+def overrelax_many(s, S):
+    """Overrelaxation updates, one per row of s, S [n][3]."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.zeros(S.shape)
+    lib().hsgref_overrelax_many(S.shape[0], dp(s), dp(S), dp(out))
+    return out
 
 
 def halfsweep(L, J, s, par, kind, beta, seed, slot_global, t, hs, rng32=False, order=None):

@@ -252,6 +252,19 @@ __device__ __forceinline__ void overrelax(T sx, T sy, T sz, T Sx, T Sy, T Sz, T&
     }
 }
 
+// Binary32 spins leave the unit sphere slowly under reflections alone (each one rounds;
+// a heat-bath update writes a fresh unit vector), so sweeps without a heat-bath lattice
+// sweep renormalise every spin once per sweep, in their last overrelaxation lattice
+// sweep: s <- s / |s| with the hardware reciprocal square root (1 ulp).  Binary64 keeps
+// |s| to ~1e-15 per thousand reflections and is left as it is.
+__device__ __forceinline__ void renormalize(float& x, float& y, float& z) {
+    const float r = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
+    x *= r;
+    y *= r;
+    z *= r;
+}
+__device__ __forceinline__ void renormalize(double&, double&, double&) {}
+
 template <typename T>
 struct NormTol;
 template <>

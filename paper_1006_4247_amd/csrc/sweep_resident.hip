@@ -117,7 +117,7 @@ __device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restric
 // One half-sweep over the sites of parity P (compile-time), HB or OR.
 template <typename T, int L, int NT, int MQ, int P>
 __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T, MQ>& own,
-                                              const FirstNbr& fn, bool hb, int hs, T beta,
+                                              const FirstNbr& fn, bool hb, bool rn, int hs, T beta,
                                               uint32_t tsw, uint32_t g, uint32_t k0, uint32_t k1,
                                               bool want, double& acc, bool& bad, int t) {
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
@@ -167,6 +167,7 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
                 heatbath<T>(Sx, Sy, Sz, beta, r1, r2, ox, oy, oz);
             } else {
                 overrelax<T>(w0[h], w1[h], w2[h], Sx, Sy, Sz, ox, oy, oz);
+                if (rn) renormalize(ox, oy, oz);
             }
             w0[h] = ox;
             w1[h] = oy;
@@ -329,12 +330,13 @@ __global__ void __launch_bounds__(NT)
         for (int step = 0; step < nhalf; ++step) {
             const int pos = adj ? nhalf - 1 - step : step;  // position in the forward order
             const bool hb = pos < 2 * n_hb;
+            const bool rn = n_hb == 0 && pos >= nhalf - 2;  // renormalised once per sweep
             const int p = pos & 1;
             const bool want = need_e && (step == nhalf - 1);
             if (p == 0)
-                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
+                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
             else
-                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
+                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
             __syncthreads();
         }
         if (need_e) {
@@ -461,11 +463,12 @@ __global__ void __launch_bounds__(2 * NT)
         double acc = 0.0;
         for (int step = 0; step < nhalf; ++step) {
             const bool hb = step < 2 * n_hb;
+            const bool rn = n_hb == 0 && step >= nhalf - 2;
             const bool want = need_e && (step == nhalf - 1);
             if ((step & 1) == 0)
-                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, step, beta, tsw, g, k0, k1, want, acc, bad, t);
+                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, step, beta, tsw, g, k0, k1, want, acc, bad, t);
             else
-                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, step, beta, tsw, g, k0, k1, want, acc, bad, t);
+                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, step, beta, tsw, g, k0, k1, want, acc, bad, t);
             __syncthreads();
         }
         if (need_e) {  // each half sums its own waves, in wave order
@@ -588,10 +591,11 @@ __global__ void __launch_bounds__(NT)
             const int stop = last ? n_pre : nhalf;
             for (int pos = 0; pos < stop; ++pos) {
                 const bool hb = pos < 2 * n_hb;
+                const bool rn = n_hb == 0 && pos >= nhalf - 2;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
                 lds_barrier();
             }
         }
@@ -606,11 +610,12 @@ __global__ void __launch_bounds__(NT)
             const uint32_t tsw = t0 + static_cast<uint32_t>(n_sweeps - 1);
             for (int pos = n_pre; pos < nhalf; ++pos) {
                 const bool hb = pos < 2 * n_hb;
+                const bool rn = n_hb == 0 && pos >= nhalf - 2;
                 const bool want = pos == nhalf - 1;
                 if ((pos & 1) == 0)
-                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
                 else
-                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
                 lds_barrier();
             }
         }

@@ -17,6 +17,7 @@ namespace hsg {
 
 struct StreamArgs {
     int hb[2], par[2], hs[2];  // per leg (regular sweeps use index 0)
+    int rn[2];                 // renormalise the updated spins (sweeps without heat-bath)
     int step;                  // sweep index within the call / annealing step k
     int want;                  // 1: last half-sweep of a sweep, reduce energy
     int anneal, parity;        // annealing legs of pairs with i mod 2 == parity
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
         K = li.K;
         ipair = li.ipair;
     }
-    const int hb = a.hb[leg], P = a.par[leg], hs = a.hs[leg];
+    const int hb = a.hb[leg], P = a.par[leg], hs = a.hs[leg], rn = a.rn[leg];
     const int smp = slot0 / (C * R);
     const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
     T* base = a.anneal ? reinterpret_cast<T*>(scr + sl.cand) : static_cast<T*>(e.spins);
@@ -147,6 +148,7 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
                     heatbath<T>(Sx, Sy, Sz, beta, r1, r2, ox, oy, oz);
                 } else {
                     overrelax<T>(w0[h], w1[h], w2[h], Sx, Sy, Sz, ox, oy, oz);
+                    if (rn) renormalize(ox, oy, oz);
                 }
                 w0[h] = ox;
                 w1[h] = oy;
@@ -295,6 +297,7 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
             a.hb[0] = a.hb[1] = pos < 2 * n_hb;
             a.par[0] = a.par[1] = pos & 1;
             a.hs[0] = a.hs[1] = pos;
+            a.rn[0] = a.rn[1] = n_hb == 0 && pos >= nhalf - 2;
             a.step = k;
             a.want = (pos == nhalf - 1);
             hipError_t err = half_prec(e, a, gy, nt, rb, st);
@@ -341,6 +344,8 @@ hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int
             a.hb[1] = dn < 2 * n_hb;
             a.par[1] = dn & 1;
             a.hs[1] = dn;
+            a.rn[0] = n_hb == 0 && up >= nhalf - 2;
+            a.rn[1] = n_hb == 0 && dn >= nhalf - 2;
             a.step = k;
             a.want = (s == nhalf - 1);
             err = half_prec(e, a, n_legs, nt, 1, st);

@@ -125,7 +125,7 @@ __device__ __forceinline__ void bonds_fetch(WaveBonds<T, L, NT>& b, const T* __r
 template <typename T, int L, int NT, bool HB>
 __device__ __forceinline__ void wave_update(T* __restrict__ lds, const WaveBonds<T, L, NT>& b, int P, int k,
                                             int hs, T beta, uint32_t tsw, uint32_t g, uint32_t k0,
-                                            uint32_t k1, bool want, double& acc, bool& bad) {
+                                            uint32_t k1, bool want, bool rn, double& acc, bool& bad) {
     constexpr int HL = L / 2, PL = HL * L, NH = PL * L, NQ = NH / 2;
     const int km = k == 0 ? L - 1 : k - 1, kp = k == L - 1 ? 0 : k + 1;
     const int O = 1 - P;
@@ -168,6 +168,7 @@ __device__ __forceinline__ void wave_update(T* __restrict__ lds, const WaveBonds
             heatbath<T>(Sx, Sy, Sz, beta, r1, r2, ox, oy, oz);
         } else {
             overrelax<T>(w0[q], w1[q], w2[q], Sx, Sy, Sz, ox, oy, oz);
+            if (rn) renormalize(ox, oy, oz);
         }
         w0[q] = ox;
         w1[q] = oy;
@@ -184,11 +185,11 @@ __device__ __forceinline__ void wave_update(T* __restrict__ lds, const WaveBonds
 template <typename T, int L, int NT>
 __device__ __forceinline__ void wave_update_any(bool hb, T* lds, const WaveBonds<T, L, NT>& b, int P, int k,
                                                 int hs, T beta, uint32_t tsw, uint32_t g, uint32_t k0,
-                                                uint32_t k1, bool want, double& acc, bool& bad) {
+                                                uint32_t k1, bool want, bool rn, double& acc, bool& bad) {
     if (hb)
-        wave_update<T, L, NT, true>(lds, b, P, k, hs, beta, tsw, g, k0, k1, want, acc, bad);
+        wave_update<T, L, NT, true>(lds, b, P, k, hs, beta, tsw, g, k0, k1, want, false, acc, bad);
     else
-        wave_update<T, L, NT, false>(lds, b, P, k, hs, beta, tsw, g, k0, k1, want, acc, bad);
+        wave_update<T, L, NT, false>(lds, b, P, k, hs, beta, tsw, g, k0, k1, want, rn, acc, bad);
 }
 
 // n_sweeps sweeps (n_hb heat-bath then n_or overrelaxation lattice sweeps each) of
@@ -221,6 +222,7 @@ __global__ void __launch_bounds__(NT) k_wave(hsg_ensemble e, int n_sweeps, int n
         const uint32_t tsw = t0 + static_cast<uint32_t>(s);
         for (int l = 0; l < nlat; ++l) {
             const bool hb = l < n_hb;
+            const bool rn = n_hb == 0 && l == nlat - 1;  // renormalised once per sweep
             const bool want = (s == n_sweeps - 1) && (l == nlat - 1);
             const int hs0 = 2 * l, hs1 = 2 * l + 1;
             // planes L-1, 0, 1 and 2, and the couplings of the first two steps
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(NT) k_wave(hsg_ensemble e, int n_sweeps, int n
             bonds_fetch<T, L, NT>(bw, J, 0, 0);
             bonds_fetch<T, L, NT>(bw_n, J, 0, 1);
             __syncthreads();
-            wave_update_any<T, L, NT>(hb, lds, bw, 0, 0, hs0, beta, tsw, g, k0, k1, false, acc, bad);
+            wave_update_any<T, L, NT>(hb, lds, bw, 0, 0, hs0, beta, tsw, g, k0, k1, false, rn, acc, bad);
             lds_barrier();
             bw = bw_n;
             for (int k = 1; k < L; ++k) {
@@ -246,10 +248,10 @@ __global__ void __launch_bounds__(NT) k_wave(hsg_ensemble e, int n_sweeps, int n
                     bonds_fetch<T, L, NT>(bb_n, J, 1, k);
                 }
                 lds_barrier();
-                wave_update_any<T, L, NT>(hb, lds, bw, 0, k, hs0, beta, tsw, g, k0, k1, false, acc, bad);
+                wave_update_any<T, L, NT>(hb, lds, bw, 0, k, hs0, beta, tsw, g, k0, k1, false, rn, acc, bad);
                 lds_barrier();
                 if (k - 1 >= 1) {
-                    wave_update_any<T, L, NT>(hb, lds, bb, 1, k - 1, hs1, beta, tsw, g, k0, k1, want, acc, bad);
+                    wave_update_any<T, L, NT>(hb, lds, bb, 1, k - 1, hs1, beta, tsw, g, k0, k1, want, rn, acc, bad);
                     lds_barrier();
                     wave_copy<T, L, NT, true>(lds, gs, k - 1);
                     bb = bb_n;
@@ -258,8 +260,8 @@ __global__ void __launch_bounds__(NT) k_wave(hsg_ensemble e, int n_sweeps, int n
             }
             // B sites of planes L-1 (couplings fetched at step L-1) and 0
             bonds_fetch<T, L, NT>(bw_n, J, 1, 0);
-            wave_update_any<T, L, NT>(hb, lds, bb, 1, L - 1, hs1, beta, tsw, g, k0, k1, want, acc, bad);
-            wave_update_any<T, L, NT>(hb, lds, bw_n, 1, 0, hs1, beta, tsw, g, k0, k1, want, acc, bad);
+            wave_update_any<T, L, NT>(hb, lds, bb, 1, L - 1, hs1, beta, tsw, g, k0, k1, want, rn, acc, bad);
+            wave_update_any<T, L, NT>(hb, lds, bw_n, 1, 0, hs1, beta, tsw, g, k0, k1, want, rn, acc, bad);
             lds_barrier();
             wave_copy<T, L, NT, true>(lds, gs, L - 1);
             wave_copy<T, L, NT, true>(lds, gs, 0);

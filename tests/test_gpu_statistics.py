@@ -7,6 +7,8 @@
   beta geometric 1..6, 1 HB + 3 OR + exchange every step): per-temperature energy
   density and overlap susceptibility of the GPU agree with the oracle's (different
   random streams, same couplings) within 3 sigma of the block-jackknife errors.
+* The same comparison for binary32 spins at L = 8 (beta geometric 0.5..3, where
+  these runs equilibrate): the GPU's FP32 chains against the FP64 oracle's.
 """
 import numpy as np
 import pytest
@@ -59,23 +61,21 @@ def test_forest_closed_forms_on_gpu(prec, mode):
     assert np.all(acc[:, 1] > 0)
 
 
-def test_long_run_matches_oracle():
-    L, C, R = 4, 2, 8
-    betas = hsgref.geometric_betas(1.0, 6.0, R)
-    ref0 = hsgref.RefEnsemble(L, 1, C, betas, 0x1006, prec="fp64")
+def _long_run_compare(L, R, betas, prec, n, burn, S_gpu, S_ref, seeds):
+    ref0 = hsgref.RefEnsemble(L, 1, 2, betas, seeds[0], prec="fp64")
     ref0.init_couplings()
     J = ref0.J[0].copy()
-    n, burn = 1500, 300
-    # GPU: 32 replicas of the same coupling set (independent streams)
-    S_gpu = 32
-    g = _replicated(L, S_gpu, C, betas, 0x2006, "fp64", J)
+    if prec == "fp32":
+        J = J.astype(np.float32).astype(np.float64)
+    C = 2
+    # GPU: S_gpu replicas of the same coupling set (independent streams)
+    g = _replicated(L, S_gpu, C, betas, seeds[1], prec, J)
     run = runtime.PTRun([g], n_hb=1, n_or=3, series_len=n)
     run.step(n)
     chi_g, e_g = run.series(0)
     run.check()
-    # oracle: 8 replicas of the same coupling set, other seed
-    S_ref = 8
-    ref = hsgref.RefEnsemble(L, S_ref, C, betas, 0x3006, prec="fp64")
+    # oracle (FP64): S_ref replicas of the same coupling set, other seed
+    ref = hsgref.RefEnsemble(L, S_ref, C, betas, seeds[2], prec="fp64")
     ref.init_spins()
     ref.set_state(J=np.broadcast_to(J, (S_ref,) + J.shape))
     chi_r = np.zeros((n, S_ref, R))
@@ -91,9 +91,23 @@ def test_long_run_matches_oracle():
             mg, sg = su.jackknife_mean_err(xg)
             mr, sr = su.jackknife_mean_err(xr)
             zz = (mg - mr) / np.sqrt(sg ** 2 + sr ** 2)
-            print("%s beta_%d gpu %.6f +- %.6f oracle %.6f +- %.6f z %+.2f" % (name, b, mg, sg, mr, sr, zz))
+            print("L=%d %s %s beta_%d gpu %.6f +- %.6f oracle %.6f +- %.6f z %+.2f" % (
+                L, prec, name, b, mg, sg, mr, sr, zz), flush=True)
             assert abs(zz) < 3.0, (name, b, mg, sg, mr, sr)
             z.append(zz)
     z = np.array(z)
     # the combined chi-square of the 2R comparisons stays plausible
     assert np.sum(z ** 2) < 2 * R + 6 * np.sqrt(4 * R), np.sum(z ** 2)
+
+
+def test_long_run_matches_oracle():
+    R = 8
+    _long_run_compare(4, R, hsgref.geometric_betas(1.0, 6.0, R), "fp64", 1500, 300, 32, 8,
+                      (0x1006, 0x2006, 0x3006))
+
+
+def test_long_run_fp32_l8_matches_oracle():
+    """FP32 spins (FP64 energies and observables) at L = 8 against the FP64 oracle."""
+    R = 8
+    _long_run_compare(8, R, hsgref.geometric_betas(0.5, 3.0, R), "fp32", 2000, 400, 32, 8,
+                      (0x1008, 0x2008, 0x3008))

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_pair import compare_states, make_pair, snapshot
+from gpu_pair import make_pair, sweep_and_check
 from oracle import hsgref
 
 import paper_1006_4247_amd as hsg
@@ -65,12 +65,18 @@ def test_sweep_measure_parity(prec, L, kind):
     gpu, ref = make_pair(L, S, C, _betas(R), SEED + L, prec=prec)
     _scramble_labels(gpu, ref, np.random.default_rng(L))
     _set_counters(gpu, ref, 300 + L)
-    before = snapshot(ref)
-    Q, chi, e = gpu.sweep_measure(1, n_hb, n_or)
-    ref.sweep(1, n_hb, n_or)
-    torch.cuda.synchronize()
-    compare_states(gpu, ref, prec, mode="composite" if kind == "hb+3or" else "lattice",
-                   before=before, n_hb=n_hb, n_or=n_or, what="L=%d %s %s" % (L, prec, kind))
+    out = {}
+
+    def launch():
+        out["m"] = gpu.sweep_measure(1, n_hb, n_or)
+        out["m"] = tuple(t.clone() for t in out["m"])
+
+    what = "sweep_measure L=%d %s %s" % (L, prec, kind)
+    rep = sweep_and_check(gpu, n_hb, n_or, launch=launch, what=what)
+    print("[parity] %s: %s" % (what, rep.summary()), flush=True)
+    Q, chi, e = out["m"]
+    # the measurement of the launch's own final configurations (the replay of a
+    # composite step leaves the same spins and energies)
     rQ, rchi, re = _oracle_measure_of(gpu)
     assert np.max(np.abs(Q.cpu().numpy() - rQ)) <= 1e-10
     assert np.max(np.abs(chi.cpu().numpy() - rchi)) <= 1e-10 * max(1.0, float(np.max(rchi)))
