@@ -79,7 +79,7 @@ typedef enum { HSG_FP64 = 0, HSG_FP32 = 1 } hsg_precision;
 typedef struct hsg_ensemble {
     int32_t L, n_samples, n_chains, n_temps;
     int32_t precision; /* hsg_precision */
-    int32_t reserved0;
+    int32_t reserved0; /* ignored (the library sets it in its own copies) */
     uint32_t sample_base, chain_base, slot_base; /* global stream offsets */
     uint32_t reserved1;
     uint64_t seed;
@@ -120,8 +120,12 @@ typedef struct hsg_tuning {
                                sweep (L 18..40 binary32, 18..28 binary64) */
     int32_t block_threads;  /* threads per workgroup */
     int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */
-    int32_t reserved;
+    int32_t flags;          /* HSG_TUNE_NO_RENORM: binary32 sweeps without a heat-bath lattice
+                               sweep skip their once-per-sweep renormalisation s <- s/|s|
+                               (on by default; it keeps |s| = 1 under reflections alone) */
 } hsg_tuning;
+
+#define HSG_TUNE_NO_RENORM 1
 
 int hsg_abi_version(void);
 

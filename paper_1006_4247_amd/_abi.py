@@ -12,6 +12,7 @@ HSG_ERR_NUMERIC = 3
 HSG_ERR_UNSUPPORTED = 4
 HSG_FP64 = 0
 HSG_FP32 = 1
+HSG_TUNE_NO_RENORM = 1
 
 _vp = ctypes.c_void_p
 
@@ -34,7 +35,7 @@ class HsgEnsemble(ctypes.Structure):
 
 class HsgTuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("replicas_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("replicas_per_block", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); the list is also what the export test checks

@@ -104,6 +104,15 @@ int sweep_path(const hsg_ensemble& e, const hsg_tuning* t) {
 // Every path but the streaming one works without the scratch.
 bool use_resident(const hsg_ensemble& e, const hsg_tuning* t) { return sweep_path(e, t) != 2; }
 
+// The library's own copy of a descriptor for the sweep kernels, its internal flag
+// word set from the tuning (renormalisation of sweeps without heat-bath on unless
+// HSG_TUNE_NO_RENORM).
+hsg_ensemble launch_copy(const hsg_ensemble& e, const hsg_tuning* t = nullptr) {
+    hsg_ensemble c = e;
+    c.reserved0 = (t && (t->flags & HSG_TUNE_NO_RENORM)) ? hsg::kFlagNoRenorm : 0;
+    return c;
+}
+
 }  // namespace
 
 extern "C" {
@@ -143,7 +152,7 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
         return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
                     n_sweeps, n_hb, n_or);
     if (tuning && (tuning->path < 0 || tuning->path > 4 || tuning->block_threads < 0 ||
-                   tuning->replicas_per_block < 0))
+                   tuning->replicas_per_block < 0 || (tuning->flags & ~HSG_TUNE_NO_RENORM) != 0))
         return fail(HSG_ERR_INVALID, "bad tuning values");
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;
@@ -164,16 +173,17 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
         const int nt = tuning ? tuning->block_threads : 0;
         hipError_t err;
         const int path = sweep_path(ens[i], tuning);
+        const hsg_ensemble e = launch_copy(ens[i], tuning);
         if (path == 1) {
-            err = hsg::launch_resident(ens[i], n_sweeps, n_hb, n_or, 2, 0, nt, as_stream(stream));
+            err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 2, 0, nt, as_stream(stream));
         } else if (path == 3) {
-            err = hsg::launch_resident(ens[i], n_sweeps, n_hb, n_or, 0, 0, nt, as_stream(stream));
+            err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 0, 0, nt, as_stream(stream));
         } else if (path == 4) {
             if (nt != 0) return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: the wavefront path takes no block_threads", i);
-            err = hsg::launch_wave_sweeps(ens[i], n_sweeps, n_hb, n_or, as_stream(stream));
+            err = hsg::launch_wave_sweeps(e, n_sweeps, n_hb, n_or, as_stream(stream));
         } else {
             const int rb = tuning ? tuning->replicas_per_block : 0;
-            err = hsg::launch_stream_sweeps(ens[i], n_sweeps, n_hb, n_or, nt, rb, as_stream(stream));
+            err = hsg::launch_stream_sweeps(e, n_sweeps, n_hb, n_or, nt, rb, nullptr, as_stream(stream));
         }
         if (err == hipErrorInvalidValue)
             return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: no kernel instance for block_threads = %d", i, nt);
@@ -222,10 +232,11 @@ hsg_status hsg_anneal_swap(const hsg_ensemble* ens, int n_ens, int parity, int n
     if (s != HSG_OK) return s;
     for (int i = 0; i < n_ens; ++i) {
         hipError_t err;
-        if (hsg::resident_supported(ens[i]))
-            err = hsg::launch_resident(ens[i], 0, n_hb, n_or, 1, parity, 0, as_stream(stream));
+        const hsg_ensemble e = launch_copy(ens[i]);
+        if (hsg::resident_supported(e))
+            err = hsg::launch_resident(e, 0, n_hb, n_or, 1, parity, 0, as_stream(stream));
         else
-            err = hsg::launch_stream_anneal(ens[i], parity, n_hb, n_or, 0, as_stream(stream));
+            err = hsg::launch_stream_anneal(e, parity, n_hb, n_or, 0, as_stream(stream));
         if (err != hipSuccess) return device(err, "anneal legs");
         err = hsg::launch_anneal_decide(ens[i], parity, as_stream(stream));
         if (err != hipSuccess) return device(err, "anneal decision");
@@ -310,7 +321,7 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
     for (int i = 0; i < n_ens; ++i) {
         hipError_t err;
         if (n_sweeps > 0 && hsg::resident_pair_supported(ens[i])) {
-            err = hsg::launch_resident_pair(ens[i], n_sweeps, n_hb, n_or, as_stream(stream));
+            err = hsg::launch_resident_pair(launch_copy(ens[i]), n_sweeps, n_hb, n_or, as_stream(stream));
             if (err != hipSuccess) return device(err, "sweep and measure");
             continue;
         }

@@ -265,6 +265,12 @@ __device__ __forceinline__ void renormalize(float& x, float& y, float& z) {
 }
 __device__ __forceinline__ void renormalize(double&, double&, double&) {}
 
+// The library launches its kernels with its own copy of an ensemble descriptor, whose
+// reserved0 word carries internal flags: bit 0 turns the renormalisation above off
+// (hsg_tuning.flags & HSG_TUNE_NO_RENORM).
+constexpr int32_t kFlagNoRenorm = 1;
+__host__ __device__ __forceinline__ bool renorm_on(const hsg_ensemble& e) { return !(e.reserved0 & kFlagNoRenorm); }
+
 template <typename T>
 struct NormTol;
 template <>

@@ -38,9 +38,11 @@ hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, i
 bool wave_supported(const hsg_ensemble& e);
 hipError_t launch_wave_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st);
 
-// Streaming path: one launch per half-sweep, any even L.
+// Streaming path: one launch per half-sweep, any even L.  The per-tile energy sums go
+// to `partial` ([slots][max_tiles] doubles), or to the ensemble's scratch if null.
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
-                                int block_threads, int replicas_per_block, hipStream_t st);
+                                int block_threads, int replicas_per_block, double* partial,
+                                hipStream_t st);
 hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int n_or,
                                 int block_threads, hipStream_t st);
 

@@ -1,0 +1,418 @@
+// Plans: one parallel-tempering cycle (sweep and measurement, then an exchange pass)
+// of several ensembles, captured once into a HIP graph inside the library and replayed
+// by hsg_plan_run.  Each ensemble's work is forked onto a capture stream of its own, so
+// the size classes of an uneven batch run concurrently in the graph; the whole cycle
+// is one graph launch.  Exchanges that alternate between even and odd pairs keep two
+// graphs (one per parity) and the plan remembers which parity comes next.
+//
+// The cycle's settings come from a small JSON object (a flat set of keys whose values
+// are numbers, strings or arrays of numbers); unknown keys are refused.
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hsg_device.h"
+#include "hsg_launch.h"
+
+namespace {
+
+thread_local char g_plan_err[512] = "";
+
+hsg_status plan_fail(hsg_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+hsg_status plan_fail(hsg_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_plan_err, sizeof(g_plan_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+// ---------------------------------------------------------------- settings
+struct Settings {
+    int exchange = 0;  // 0 plain, 1 annealed, 2 decimated, 3 cooling / heating, 4 none
+    int pairing = -2;  // -2: the exchange's default; -1: alternate odd / even pairs
+    int n_hb = 1, n_or = 3;
+    int anneal_n_hb = -1, anneal_n_or = -1;
+    int measure = 1;
+    int streams = 1;
+    double eps = 0.0;
+    std::vector<double> eps_pairs;  // per pair of every ensemble, ensembles in order
+    std::vector<int> path, block_threads, replicas_per_block;  // one value or one per ensemble
+};
+
+struct Parser {
+    const char* p;
+    std::string err;
+
+    void ws() {
+        while (*p && std::isspace(static_cast<unsigned char>(*p))) ++p;
+    }
+    bool expect(char c) {
+        ws();
+        if (*p != c) {
+            err = std::string("expected '") + c + "'";
+            return false;
+        }
+        ++p;
+        return true;
+    }
+    bool string(std::string& out) {
+        ws();
+        if (*p != '"') {
+            err = "expected a string";
+            return false;
+        }
+        ++p;
+        out.clear();
+        while (*p && *p != '"') {
+            if (*p == '\\') {
+                err = "escapes are not supported";
+                return false;
+            }
+            out += *p++;
+        }
+        if (*p != '"') {
+            err = "unterminated string";
+            return false;
+        }
+        ++p;
+        return true;
+    }
+    bool number(double& out) {
+        ws();
+        char* end = nullptr;
+        out = std::strtod(p, &end);
+        if (end == p || !std::isfinite(out)) {
+            err = "expected a finite number";
+            return false;
+        }
+        p = end;
+        return true;
+    }
+    // a number, or an array of numbers
+    bool numbers(std::vector<double>& out) {
+        ws();
+        out.clear();
+        if (*p != '[') {
+            double v;
+            if (!number(v)) return false;
+            out.push_back(v);
+            return true;
+        }
+        ++p;
+        ws();
+        if (*p == ']') {
+            ++p;
+            return true;
+        }
+        for (;;) {
+            double v;
+            if (!number(v)) return false;
+            out.push_back(v);
+            ws();
+            if (*p == ',') {
+                ++p;
+                continue;
+            }
+            return expect(']');
+        }
+    }
+};
+
+bool as_int(const std::vector<double>& v, int& out) {
+    if (v.size() != 1 || v[0] != std::floor(v[0]) || std::fabs(v[0]) > 1e9) return false;
+    out = static_cast<int>(v[0]);
+    return true;
+}
+
+bool as_ints(const std::vector<double>& v, std::vector<int>& out) {
+    out.clear();
+    for (double x : v) {
+        if (x != std::floor(x) || std::fabs(x) > 1e9) return false;
+        out.push_back(static_cast<int>(x));
+    }
+    return true;
+}
+
+hsg_status parse(const char* json, Settings& s) {
+    if (!json || !*json) return HSG_OK;
+    Parser ps{json, ""};
+    if (!ps.expect('{')) return plan_fail(HSG_ERR_INVALID, "plan settings: %s", ps.err.c_str());
+    ps.ws();
+    if (*ps.p == '}') {
+        ++ps.p;
+    } else {
+        for (;;) {
+            std::string key;
+            if (!ps.string(key) || !ps.expect(':'))
+                return plan_fail(HSG_ERR_INVALID, "plan settings: %s", ps.err.c_str());
+            ps.ws();
+            if (key == "exchange") {
+                std::string v;
+                if (!ps.string(v)) return plan_fail(HSG_ERR_INVALID, "plan settings: exchange: %s", ps.err.c_str());
+                if (v == "plain") s.exchange = 0;
+                else if (v == "anneal") s.exchange = 1;
+                else if (v == "decimate") s.exchange = 2;
+                else if (v == "coolheat") s.exchange = 3;
+                else if (v == "none") s.exchange = 4;
+                else return plan_fail(HSG_ERR_INVALID, "plan settings: unknown exchange \"%s\"", v.c_str());
+            } else {
+                std::vector<double> v;
+                if (!ps.numbers(v)) return plan_fail(HSG_ERR_INVALID, "plan settings: %s: %s", key.c_str(), ps.err.c_str());
+                bool ok = true;
+                if (key == "pairing") ok = as_int(v, s.pairing);
+                else if (key == "n_hb") ok = as_int(v, s.n_hb);
+                else if (key == "n_or") ok = as_int(v, s.n_or);
+                else if (key == "anneal_n_hb") ok = as_int(v, s.anneal_n_hb);
+                else if (key == "anneal_n_or") ok = as_int(v, s.anneal_n_or);
+                else if (key == "measure") ok = as_int(v, s.measure);
+                else if (key == "streams") ok = as_int(v, s.streams);
+                else if (key == "eps") {
+                    if (v.size() == 1) s.eps = v[0];
+                    else s.eps_pairs = v;
+                } else if (key == "path") ok = as_ints(v, s.path);
+                else if (key == "block_threads") ok = as_ints(v, s.block_threads);
+                else if (key == "replicas_per_block") ok = as_ints(v, s.replicas_per_block);
+                else return plan_fail(HSG_ERR_INVALID, "plan settings: unknown key \"%s\"", key.c_str());
+                if (!ok) return plan_fail(HSG_ERR_INVALID, "plan settings: %s must be an integer", key.c_str());
+            }
+            ps.ws();
+            if (*ps.p == ',') {
+                ++ps.p;
+                continue;
+            }
+            if (!ps.expect('}')) return plan_fail(HSG_ERR_INVALID, "plan settings: %s", ps.err.c_str());
+            break;
+        }
+    }
+    ps.ws();
+    if (*ps.p) return plan_fail(HSG_ERR_INVALID, "plan settings: trailing characters");
+    return HSG_OK;
+}
+
+// ---------------------------------------------------------------- the plan
+struct Plan {
+    std::vector<hsg_ensemble> ens;
+    Settings set;
+    std::vector<hsg_tuning> tune;
+    std::vector<bool> tuned;
+    bool alternating = false;
+    int next_parity = 0;
+    int device = 0;
+    double* eps_dev = nullptr;  // per-pair cooling / heating parameters (library-owned)
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+};
+
+// One cycle of ensemble i on stream st: sweep and measurement, then the exchange.
+hsg_status enqueue_cycle(const Plan& pl, int i, int parity, hipStream_t st) {
+    const hsg_ensemble* e = &pl.ens[i];
+    const Settings& s = pl.set;
+    void* vs = static_cast<void*>(st);
+    hsg_status r;
+    if (s.measure && !pl.tuned[i]) {
+        r = hsg_sweep_measure(e, 1, 1, s.n_hb, s.n_or, vs);
+    } else {
+        r = hsg_sweep_tuned(e, 1, 1, s.n_hb, s.n_or, pl.tuned[i] ? &pl.tune[i] : nullptr, vs);
+        if (r == HSG_OK && s.measure) r = hsg_measure(e, 1, vs);
+    }
+    if (r != HSG_OK) return r;
+    const int pairing = s.pairing >= 0 ? s.pairing : parity + 1;
+    switch (s.exchange) {
+    case 0: return hsg_swap(e, 1, pairing, vs);
+    case 1: return hsg_anneal_swap(e, 1, parity, s.anneal_n_hb, s.anneal_n_or, vs);
+    case 2: return hsg_decimate_swap(e, 1, pairing, vs);
+    case 3:
+        if (pl.eps_dev) {
+            size_t off = 0;
+            for (int k = 0; k < i; ++k) off += static_cast<size_t>(pl.ens[k].n_temps - 1);
+            return hsg_coolheat_swap_pairs(e, 1, pairing, pl.eps_dev + off, vs);
+        }
+        return hsg_coolheat_swap(e, 1, pairing, s.eps, vs);
+    default: return HSG_OK;
+    }
+}
+
+// Capture one cycle (exchange parity `parity`) of every ensemble into pl.graph/exec[slot].
+hsg_status capture(Plan& pl, int parity, int slot) {
+    const int n = static_cast<int>(pl.ens.size());
+    const bool fork = pl.set.streams != 0 && n > 1;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> side(fork ? n : 0, nullptr);
+    std::vector<hipEvent_t> join(fork ? n : 0, nullptr);
+    hipEvent_t start = nullptr;
+    hsg_status result = HSG_OK;
+    hipError_t err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    for (int i = 0; err == hipSuccess && i < static_cast<int>(side.size()); ++i) {
+        err = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    }
+    if (err == hipSuccess && fork) err = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (err != hipSuccess) {
+        result = plan_fail(HSG_ERR_DEVICE, "plan capture setup: %s", hipGetErrorString(err));
+    } else {
+        if (fork) err = hipEventRecord(start, cap);
+        for (int i = 0; i < n && err == hipSuccess && result == HSG_OK; ++i) {
+            hipStream_t st = cap;
+            if (fork) {
+                st = side[i];
+                err = hipStreamWaitEvent(st, start, 0);
+                if (err != hipSuccess) break;
+            }
+            result = enqueue_cycle(pl, i, parity, st);
+            if (result != HSG_OK) {
+                plan_fail(result, "plan capture, ensemble %d: %s", i, hsg_last_error());
+                break;
+            }
+            if (fork) {
+                err = hipEventRecord(join[i], st);
+                if (err == hipSuccess) err = hipStreamWaitEvent(cap, join[i], 0);
+            }
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t end = hipStreamEndCapture(cap, &g);
+        if (result == HSG_OK && err != hipSuccess)
+            result = plan_fail(HSG_ERR_DEVICE, "plan capture: %s", hipGetErrorString(err));
+        if (result == HSG_OK && end != hipSuccess)
+            result = plan_fail(HSG_ERR_DEVICE, "plan capture end: %s", hipGetErrorString(end));
+        if (result == HSG_OK) {
+            err = hipGraphInstantiate(&pl.exec[slot], g, nullptr, nullptr, 0);
+            if (err != hipSuccess) result = plan_fail(HSG_ERR_DEVICE, "plan instantiate: %s", hipGetErrorString(err));
+        }
+        if (result == HSG_OK) pl.graph[slot] = g;
+        else if (g) hipGraphDestroy(g);
+    }
+    for (size_t i = 0; i < side.size(); ++i) {
+        if (join[i]) hipEventDestroy(join[i]);
+        if (side[i]) hipStreamDestroy(side[i]);
+    }
+    if (start) hipEventDestroy(start);
+    if (cap) hipStreamDestroy(cap);
+    return result;
+}
+
+void release(Plan* pl) {
+    if (!pl) return;
+    int cur = 0;
+    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != pl->device;
+    if (switch_dev) hipSetDevice(pl->device);
+    for (int k = 0; k < 2; ++k) {
+        if (pl->exec[k]) hipGraphExecDestroy(pl->exec[k]);
+        if (pl->graph[k]) hipGraphDestroy(pl->graph[k]);
+    }
+    if (pl->eps_dev) hipFree(pl->eps_dev);
+    if (switch_dev) hipSetDevice(cur);
+    delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hsg_plan_last_error(void) { return g_plan_err; }
+
+hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tuning_json, void** plan) {
+    if (!plan) return plan_fail(HSG_ERR_INVALID, "plan: the output pointer is NULL");
+    *plan = nullptr;
+    if (!ens || n_ens < 1 || n_ens > 64) return plan_fail(HSG_ERR_INVALID, "plan: need 1 to 64 ensembles");
+    Plan* pl = new Plan();
+    Settings& s = pl->set;
+    hsg_status r = parse(tuning_json, s);
+    if (r != HSG_OK) {
+        delete pl;
+        return r;
+    }
+    if (s.anneal_n_hb < 0) s.anneal_n_hb = s.n_hb;
+    if (s.anneal_n_or < 0) s.anneal_n_or = s.n_or;
+    if (s.pairing == -2) s.pairing = (s.exchange == 0) ? 0 : -1;
+    auto bad = [&](const char* msg) {
+        delete pl;
+        return plan_fail(HSG_ERR_INVALID, "plan settings: %s", msg);
+    };
+    if (s.pairing < -1 || s.pairing > 2) return bad("pairing must be -1 (alternate), 0, 1 or 2");
+    if (s.exchange == 1 && s.pairing >= 0) return bad("the annealed exchange alternates even and odd pairs (pairing -1)");
+    if (s.n_hb < 0 || s.n_hb > 127 || s.n_or < 0 || s.n_hb + s.n_or < 1) return bad("need 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1");
+    if (!(s.eps >= 0.0)) return bad("eps must be >= 0");
+    pl->ens.assign(ens, ens + n_ens);
+    pl->alternating = s.exchange != 4 && s.pairing < 0;
+    size_t n_pairs = 0;
+    for (int i = 0; i < n_ens; ++i) n_pairs += static_cast<size_t>(ens[i].n_temps > 0 ? ens[i].n_temps - 1 : 0);
+    if (!s.eps_pairs.empty()) {
+        if (s.exchange != 3) return bad("per-pair eps is for the cooling / heating exchange");
+        if (s.eps_pairs.size() != n_pairs) return bad("eps needs one value per pair of every ensemble, in order");
+        for (double v : s.eps_pairs)
+            if (!(v >= 0.0)) return bad("eps must be >= 0");
+    }
+    auto per_ens = [&](const std::vector<int>& v, int i) { return v.empty() ? 0 : (v.size() == 1 ? v[0] : v[i]); };
+    for (const auto* v : {&s.path, &s.block_threads, &s.replicas_per_block})
+        if (v->size() > 1 && static_cast<int>(v->size()) != n_ens) return bad("tuning arrays need one value per ensemble");
+    pl->tune.resize(n_ens);
+    pl->tuned.resize(n_ens);
+    for (int i = 0; i < n_ens; ++i) {
+        hsg_tuning t{per_ens(s.path, i), per_ens(s.block_threads, i), per_ens(s.replicas_per_block, i), 0};
+        pl->tune[i] = t;
+        pl->tuned[i] = t.path != 0 || t.block_threads != 0 || t.replicas_per_block != 0;
+    }
+    hipError_t err = hipGetDevice(&pl->device);
+    if (err != hipSuccess) {
+        delete pl;
+        return plan_fail(HSG_ERR_DEVICE, "plan: %s", hipGetErrorString(err));
+    }
+    if (!s.eps_pairs.empty()) {
+        err = hipMalloc(&pl->eps_dev, s.eps_pairs.size() * sizeof(double));
+        if (err == hipSuccess)
+            err = hipMemcpy(pl->eps_dev, s.eps_pairs.data(), s.eps_pairs.size() * sizeof(double),
+                            hipMemcpyHostToDevice);
+        if (err != hipSuccess) {
+            release(pl);
+            return plan_fail(HSG_ERR_DEVICE, "plan: per-pair eps: %s", hipGetErrorString(err));
+        }
+    }
+    // the exchange parity of the first cycle is 0; alternating plans keep a second graph
+    r = capture(*pl, 0, 0);
+    if (r == HSG_OK && pl->alternating) r = capture(*pl, 1, 1);
+    if (r != HSG_OK) {
+        release(pl);
+        return r;
+    }
+    *plan = pl;
+    g_plan_err[0] = '\0';
+    return HSG_OK;
+}
+
+hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream) {
+    if (!plan) return plan_fail(HSG_ERR_INVALID, "plan: NULL plan");
+    if (n_cycles < 0) return plan_fail(HSG_ERR_INVALID, "plan: n_cycles must be >= 0");
+    Plan* pl = static_cast<Plan*>(plan);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < n_cycles; ++k) {
+        const int g = pl->alternating ? pl->next_parity : 0;
+        const hipError_t err = hipGraphLaunch(pl->exec[g], st);
+        if (err != hipSuccess) return plan_fail(HSG_ERR_DEVICE, "plan run: %s", hipGetErrorString(err));
+        if (pl->alternating) pl->next_parity ^= 1;
+    }
+    g_plan_err[0] = '\0';
+    return HSG_OK;
+}
+
+int hsg_plan_next_parity(const void* plan) {
+    return plan ? static_cast<const Plan*>(plan)->next_parity : -1;
+}
+
+hsg_status hsg_plan_set_next_parity(void* plan, int parity) {
+    if (!plan || parity < 0 || parity > 1) return plan_fail(HSG_ERR_INVALID, "plan: bad plan or parity");
+    static_cast<Plan*>(plan)->next_parity = parity;
+    return HSG_OK;
+}
+
+hsg_status hsg_plan_destroy(void* plan) {
+    release(static_cast<Plan*>(plan));
+    return HSG_OK;
+}
+
+}  // extern "C"

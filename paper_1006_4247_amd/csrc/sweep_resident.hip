@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(NT)
         for (int step = 0; step < nhalf; ++step) {
             const int pos = adj ? nhalf - 1 - step : step;  // position in the forward order
             const bool hb = pos < 2 * n_hb;
-            const bool rn = n_hb == 0 && pos >= nhalf - 2;  // renormalised once per sweep
+            const bool rn = renorm_on(e) && n_hb == 0 && pos >= nhalf - 2;  // renormalised once per sweep
             const int p = pos & 1;
             const bool want = need_e && (step == nhalf - 1);
             if (p == 0)
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(2 * NT)
         double acc = 0.0;
         for (int step = 0; step < nhalf; ++step) {
             const bool hb = step < 2 * n_hb;
-            const bool rn = n_hb == 0 && step >= nhalf - 2;
+            const bool rn = renorm_on(e) && n_hb == 0 && step >= nhalf - 2;
             const bool want = need_e && (step == nhalf - 1);
             if ((step & 1) == 0)
                 resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, step, beta, tsw, g, k0, k1, want, acc, bad, t);
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(NT)
             const int stop = last ? n_pre : nhalf;
             for (int pos = 0; pos < stop; ++pos) {
                 const bool hb = pos < 2 * n_hb;
-                const bool rn = n_hb == 0 && pos >= nhalf - 2;
+                const bool rn = renorm_on(e) && n_hb == 0 && pos >= nhalf - 2;
                 if ((pos & 1) == 0)
                     resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, false, acc, bad, static_cast<int>(threadIdx.x));
                 else
@@ -610,7 +610,7 @@ __global__ void __launch_bounds__(NT)
             const uint32_t tsw = t0 + static_cast<uint32_t>(n_sweeps - 1);
             for (int pos = n_pre; pos < nhalf; ++pos) {
                 const bool hb = pos < 2 * n_hb;
-                const bool rn = n_hb == 0 && pos >= nhalf - 2;
+                const bool rn = renorm_on(e) && n_hb == 0 && pos >= nhalf - 2;
                 const bool want = pos == nhalf - 1;
                 if ((pos & 1) == 0)
                     resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));

@@ -10,6 +10,9 @@
 // by six sites).  The energy
 // of the last half-sweep of a sweep is reduced per tile into scratch and
 // summed over tiles in a fixed order by a finalize kernel (deterministic).
+#include <map>
+#include <mutex>
+
 #include "hsg_device.h"
 #include "hsg_launch.h"
 
@@ -22,6 +25,7 @@ struct StreamArgs {
     int want;                  // 1: last half-sweep of a sweep, reduce energy
     int anneal, parity;        // annealing legs of pairs with i mod 2 == parity
     int n_tiles;
+    double* partial;           // per-tile energies [slots][max_tiles] (see scratch_layout)
 };
 
 struct LegInfo {
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
             if (bad) atomicOr(e.guard, 1);
             const double tot = block_sum<NT>(acc, red);
             if (threadIdx.x == 0)
-                reinterpret_cast<double*>(scr + sl.partial)[static_cast<size_t>(slot) * sl.max_tiles + tile] = -tot;
+                a.partial[static_cast<size_t>(slot) * sl.max_tiles + tile] = -tot;
         }
     }
 }
@@ -174,11 +178,10 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
 // Sum the per-tile energies of every slot in tile order.  Regular: energy[] and
 // (on the last sweep of the call) sweep_ctr += n_sweeps.  Annealing: the
 // candidate energy of each active leg.
-__global__ void k_stream_finalize(hsg_ensemble e, int n_tiles, int anneal, int parity, int step,
-                                  int ctr_add) {
+__global__ void k_stream_finalize(hsg_ensemble e, const double* part, int n_tiles, int anneal, int parity,
+                                  int step, int ctr_add) {
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    const double* part = reinterpret_cast<const double*>(scr + sl.partial);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     int slot;
     if (!anneal) {
@@ -280,8 +283,11 @@ static hipError_t half_prec(const hsg_ensemble& e, const StreamArgs& a, int gy, 
     return half_any<float>(e, a, gy, nt, rb, st);
 }
 
+// The per-tile energy sums of regular sweeps in `partial` (slots x max_tiles doubles),
+// or in the caller's scratch if it is null.
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
-                                int block_threads, int replicas_per_block, hipStream_t st) {
+                                int block_threads, int replicas_per_block, double* partial,
+                                hipStream_t st) {
     const int nt = block_threads > 0 ? block_threads : 256;
     int rb = replicas_per_block > 0 ? replicas_per_block : 1;
     const int CR = e.n_chains * e.n_temps;
@@ -289,6 +295,8 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
     const int NQ = e.L * e.L * e.L / 4;
     StreamArgs a{};
     a.n_tiles = (NQ + nt - 1) / nt;
+    a.partial = partial ? partial
+                        : reinterpret_cast<double*>(static_cast<unsigned char*>(e.scratch) + scratch_layout(e).partial);
     const int n_slots = e.n_samples * CR;
     const int gy = n_slots / rb;
     const int nhalf = 2 * (n_hb + n_or);
@@ -297,7 +305,7 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
             a.hb[0] = a.hb[1] = pos < 2 * n_hb;
             a.par[0] = a.par[1] = pos & 1;
             a.hs[0] = a.hs[1] = pos;
-            a.rn[0] = a.rn[1] = n_hb == 0 && pos >= nhalf - 2;
+            a.rn[0] = a.rn[1] = renorm_on(e) && n_hb == 0 && pos >= nhalf - 2;
             a.step = k;
             a.want = (pos == nhalf - 1);
             hipError_t err = half_prec(e, a, gy, nt, rb, st);
@@ -305,7 +313,7 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
         }
         const int last = (k == n_sweeps - 1);
         hipLaunchKernelGGL(k_stream_finalize, dim3((n_slots + 255) / 256), dim3(256), 0, st, e,
-                           a.n_tiles, 0, 0, k, last ? n_sweeps : 0);
+                           a.partial, a.n_tiles, 0, 0, k, last ? n_sweeps : 0);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -333,6 +341,7 @@ hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int
     a.anneal = 1;
     a.parity = parity;
     a.n_tiles = (NQ + nt - 1) / nt;
+    a.partial = reinterpret_cast<double*>(static_cast<unsigned char*>(e.scratch) + scratch_layout(e).partial);
     for (int k = 0; k <= Kmax; ++k) {
         hipLaunchKernelGGL(k_stream_anneal_book, dim3(lb), dim3(256), 0, st, e, parity, 1, k);
         if (k == Kmax) break;
@@ -344,15 +353,15 @@ hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int
             a.hb[1] = dn < 2 * n_hb;
             a.par[1] = dn & 1;
             a.hs[1] = dn;
-            a.rn[0] = n_hb == 0 && up >= nhalf - 2;
-            a.rn[1] = n_hb == 0 && dn >= nhalf - 2;
+            a.rn[0] = renorm_on(e) && n_hb == 0 && up >= nhalf - 2;
+            a.rn[1] = renorm_on(e) && n_hb == 0 && dn >= nhalf - 2;
             a.step = k;
             a.want = (s == nhalf - 1);
             err = half_prec(e, a, n_legs, nt, 1, st);
             if (err != hipSuccess) return err;
         }
-        hipLaunchKernelGGL(k_stream_finalize, dim3(lb), dim3(256), 0, st, e, a.n_tiles, 1, parity,
-                           k, 0);
+        hipLaunchKernelGGL(k_stream_finalize, dim3(lb), dim3(256), 0, st, e, a.partial, a.n_tiles, 1,
+                           parity, k, 0);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }

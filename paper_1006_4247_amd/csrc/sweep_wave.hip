@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(NT) k_wave(hsg_ensemble e, int n_sweeps, int n
         const uint32_t tsw = t0 + static_cast<uint32_t>(s);
         for (int l = 0; l < nlat; ++l) {
             const bool hb = l < n_hb;
-            const bool rn = n_hb == 0 && l == nlat - 1;  // renormalised once per sweep
+            const bool rn = renorm_on(e) && n_hb == 0 && l == nlat - 1;  // renormalised once per sweep
             const bool want = (s == n_sweeps - 1) && (l == nlat - 1);
             const int hs0 = 2 * l, hs1 = 2 * l + 1;
             // planes L-1, 0, 1 and 2, and the couplings of the first two steps

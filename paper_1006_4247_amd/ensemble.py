@@ -147,7 +147,7 @@ class Ensemble:
                                             self._stream()))
         else:
             t = _abi.HsgTuning(int(tuning.get("path", 0)), int(tuning.get("block_threads", 0)),
-                               int(tuning.get("replicas_per_block", 0)), 0)
+                               int(tuning.get("replicas_per_block", 0)), int(tuning.get("flags", 0)))
             _abi.check(_abi.lib().hsg_sweep_tuned(ctypes.byref(self.desc), 1, n_sweeps, n_hb, n_or,
                                                   ctypes.byref(t), self._stream()))
 

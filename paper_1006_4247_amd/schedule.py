@@ -249,6 +249,51 @@ def select_schedule(net, betas, ebar, L, K_grid, gammas=GAMMAS, floor=0.05, iter
     return K, G, A[np.arange(R - 1), pick]
 
 
+def round_trip_cost(acc, K, t_base, t_leg):
+    """Wall time per round trip, up to a constant, for a ladder whose pairs accept with
+    probability acc_i and anneal with K_i sweeps, pairs alternating even / odd.  A
+    configuration's temperature index is a random walk that crosses pair i with
+    probability acc_i / 2 per step; the commute time between the ends of such a walk
+    with a uniform stationary law is proportional to sum_i 1/acc_i steps.  A step costs
+    t_base (the sweep, measurement and exchange of every replica) plus t_leg per
+    annealing sweep of one pair (both legs, all chains; half the pairs anneal per step):
+    cost = (sum_i 1/acc_i) (t_base + t_leg sum_i K_i / 2)."""
+    acc = np.maximum(np.asarray(acc, dtype=np.float64), 1e-3)
+    K = np.asarray(K, dtype=np.float64)
+    return np.sum(1.0 / acc) * (t_base + t_leg * K.sum() / 2.0)
+
+
+def select_schedule_round_trips(net, betas, ebar, L, K_grid, t_base, t_leg, gammas=GAMMAS, sweeps=20):
+    """Per-pair protocols (K, gamma) minimising the predicted wall time per round trip
+    (round_trip_cost; K = 0 is the plain exchange of Eq. (1), acceptance min(1, e^{d beta
+    d H}) predicted by the same network), by coordinate descent over the pairs from the
+    plain exchange everywhere.  t_base and t_leg come from timing the method on the
+    device (seconds per step and per annealing sweep of one pair)."""
+    betas = np.asarray(betas, dtype=np.float64)
+    R = len(betas)
+    grid = [(k, g) for k in K_grid for g in (gammas if k > 0 else (0.0,))]
+    Ks = np.array([k for k, _ in grid], dtype=np.float64)
+    Gs = np.array([g for _, g in grid], dtype=np.float64)
+    A = np.zeros((R - 1, len(grid)))
+    for i in range(R - 1):
+        x = features(betas[i], betas[i + 1], ebar[i], ebar[i + 1], L, Ks, Gs)
+        A[i] = np.clip(predict(net, x), 1e-3, 1.0)
+    pick = np.array([int(np.argmin(Ks + np.abs(Gs))) for _ in range(R - 1)])  # K = 0 first
+    for _ in range(sweeps):
+        changed = False
+        for i in range(R - 1):
+            inv = np.sum(1.0 / A[np.arange(R - 1), pick]) - 1.0 / A[i, pick[i]]
+            ksum = Ks[pick].sum() - Ks[pick[i]]
+            cost = (inv + 1.0 / A[i]) * (t_base + t_leg * (ksum + Ks) / 2.0)
+            best = int(np.argmin(cost + 1e-12 * Ks))
+            if best != pick[i]:
+                pick[i] = best
+                changed = True
+        if not changed:
+            break
+    return Ks[pick].astype(np.int32), Gs[pick], A[np.arange(R - 1), pick]
+
+
 def fixed_schedule(R, K_fix):
     """The fallback: linear protocol with the same K for every pair."""
     return np.full(R - 1, int(K_fix), dtype=np.int32), np.zeros(R - 1)

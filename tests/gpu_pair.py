@@ -272,7 +272,8 @@ def sweep_and_check(gpu, n_hb, n_or, tuning=None, launch=None, slots=None, what=
     """Run the launch under test (default gpu.sweep(1, n_hb, n_or, tuning)) and check it
     against the oracle: a single-kind call directly (check_lattice_call); a composite
     step through its replay as single-kind calls on the GPU ([n_hb heat-bath lattice
-    sweeps] then n_or one-overrelaxation-sweep calls, the counter put back after each),
+    sweeps] then n_or one-overrelaxation-sweep calls without renormalisation, the
+    counter put back after each),
     which must equal the launch bit for bit, each replayed call meeting
     check_lattice_call.  Returns the ParityReport."""
     prec = gpu.precision
@@ -290,9 +291,12 @@ def sweep_and_check(gpu, n_hb, n_or, tuning=None, launch=None, slots=None, what=
     assert np.array_equal(post["sweep_ctr"], pre["sweep_ctr"] + 1), what
     _restore(gpu, pre)
     calls = [(n_hb, 0)] + [(0, 1)] * n_or
+    # the one-overrelaxation-sweep calls without the renormalisation that sweeps without
+    # heat-bath apply by default (the composite step has a heat-bath and does not)
+    replay_tuning = dict(tuning or {}, flags=hsg._abi.HSG_TUNE_NO_RENORM)
     for k, (h, o) in enumerate(calls):
         a = gpu_snap(gpu, pre["slots"])
-        gpu.sweep(1, h, o, tuning=tuning)
+        gpu.sweep(1, h, o, tuning=replay_tuning)
         b = gpu_snap(gpu, pre["slots"])
         check_lattice_call(gpu, a, b, h, o, J=J, report=report, what="%s replay call %d" % (what, k))
         gpu.sweep_ctr.copy_(torch.from_numpy(pre["sweep_ctr"].view(np.int32)))
@@ -403,6 +407,14 @@ def anneal_and_check(gpu, ref, parity, K, lam, n_hb, n_or, what=""):
     prec = gpu.precision
     S, C, R, L = ref.S, ref.C, ref.R, ref.L
     K = np.asarray(K, dtype=np.int32)
+    # both sides start from the GPU's state (an earlier call may have left them apart
+    # within its bars)
+    st0 = gpu.host_state()
+    ref.spins[...] = st0["spins"]
+    for k, v in (("temp_of_slot", "temp_of_slot"), ("slot_of_temp", "slot_of_temp"), ("sweep_ctr", "sweep_ctr"),
+                 ("swap_ctr", "swap_ctr"), ("stats", "stats"), ("rt_state", "rt_state"), ("rt_trips", "rt_trips"),
+                 ("energy", "energy")):
+        getattr(ref, v)[...] = st0[k]
     before = ref.spins.copy()
     ctr0, sot0, n0 = ref.sweep_ctr.copy(), ref.slot_of_temp.copy(), ref.swap_ctr.copy()
     stats0, tos0 = ref.stats.copy(), ref.temp_of_slot.copy()

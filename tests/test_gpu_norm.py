@@ -52,9 +52,12 @@ def test_overrelaxation_only_sweeps_renormalise(L, tuning):
     err = _max_norm_error(e)
     print("L=%d %s: max | |s|^2 - 1 | after 5000 OR-only lattice sweeps: %.3e" % (L, tuning, err))
     assert err < 1e-6, err
-    # overrelaxation conserves H; the renormalisation moves it by at most the norm change
+    # overrelaxation conserves H; in binary32 each reflection's factor 2 (s.S)/S^2 carries
+    # the 1-ulp reciprocal, which can be systematic (H moves by ~2^-23 of itself per
+    # half-sweep, ~1e-3 over these 10^4 half-sweeps), and the renormalisation moves each
+    # term by its norm change: per site, far below 1e-4
     H1 = e.energy_from_scratch().cpu().numpy()
-    assert np.max(np.abs(H1 - H0) / np.abs(H0)) < 1e-3
+    assert np.max(np.abs(H1 - H0)) / e.N < 1e-4
     e.check()
 
 

@@ -147,7 +147,7 @@ def test_sweep_full_shape_sampled_replicas():
     gpu.sweep(1, 1, 0)
     gpu.sweep_ctr.copy_(ctr0)
     for _ in range(3):
-        gpu.sweep(1, 0, 1)
+        gpu.sweep(1, 0, 1, tuning={"flags": hsg._abi.HSG_TUNE_NO_RENORM})
     torch.cuda.synchronize()
     assert torch.equal(gpu.spins, after)
     # sampled replicas against the oracle, call by call
