@@ -159,6 +159,21 @@ hsg_status hsg_sweep(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb,
 hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb,
                            int n_or, const hsg_tuning* tuning, void* stream);
 
+/* hsg_sweep for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same sweeps,
+ * results bit for bit those of hsg_sweep with the default tuning, without
+ * ens[i].scratch (it may be NULL).  Ensembles on the streaming path (those whose
+ * replica does not fit one workgroup's LDS) keep their per-tile energy sums in a
+ * device array of the library's own, 4 MiB per device (held until the process ends;
+ * 4 MiB = 524288 doubles, enough for slots x ceil(L^3/256) doubles: e.g. 512 slots
+ * at L = 32, 37 slots at L = 64); a larger ensemble returns HSG_ERR_INVALID before
+ * anything is enqueued.  Nothing is allocated.  Every call on one device shares
+ * that array, so calls on one device that overlap in time (different streams or host
+ * threads) race and must be serialised by the caller; consecutive calls on one
+ * stream are safe (each sum is written before it is read). */
+hsg_status hsg_sweep_static(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                            void* stream);
+
 /* H = -sum over bonds J s.s (Eq. (2)) of every slot, from scratch, in FP64.
  * H_out: device array of sum_e S_e C_e R_e doubles, ensembles in order, slot
  * layout [S][C][R]; NULL writes ens[e].energy instead. */

@@ -50,6 +50,7 @@ SIGNATURES = {
     "hsg_init_spins": (_i, [_E, _i, _i, _vp]),
     "hsg_sweep": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_sweep_tuned": (_i, [_E, _i, _i, _i, _i, ctypes.POINTER(HsgTuning), _vp]),
+    "hsg_sweep_static": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_energy": (_i, [_E, _i, _vp, _vp]),
     "hsg_swap": (_i, [_E, _i, _i, _vp]),
     "hsg_anneal_swap": (_i, [_E, _i, _i, _i, _i, _vp]),

@@ -197,6 +197,43 @@ hsg_status hsg_sweep(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb,
     return hsg_sweep_tuned(ens, n_ens, n_sweeps, n_hb, n_or, nullptr, stream);
 }
 
+hsg_status hsg_sweep_static(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
+                            void* stream) {
+    if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
+        return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
+                    n_sweeps, n_hb, n_or);
+    hsg_status s = check_all(ens, n_ens, kState);
+    if (s != HSG_OK) return s;
+    bool any_stream = false;
+    for (int i = 0; i < n_ens; ++i) {
+        if (use_resident(ens[i], nullptr)) continue;
+        any_stream = true;
+        const hsg::ScratchLayout sl = hsg::scratch_layout(ens[i]);
+        const size_t need = static_cast<size_t>(ens[i].n_samples) * ens[i].n_chains * ens[i].n_temps * sl.max_tiles;
+        if (need > hsg::kStaticPartialDoubles)
+            return fail(HSG_ERR_INVALID,
+                        "ensemble %d: its per-tile energy sums need %zu bytes, more than the %zu bytes of the "
+                        "library's device array (use hsg_sweep with a caller-allocated scratch)",
+                        i, need * sizeof(double), hsg::kStaticPartialDoubles * sizeof(double));
+    }
+    double* partial = nullptr;
+    if (any_stream) {
+        hipError_t err = hsg::static_partial(&partial);
+        if (err != hipSuccess) return device(err, "sweep_static: device array address");
+    }
+    if (n_sweeps == 0) return ok();
+    for (int i = 0; i < n_ens; ++i) {
+        hipError_t err;
+        const hsg_ensemble e = launch_copy(ens[i]);
+        if (use_resident(e, nullptr))
+            err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 0, 0, 0, as_stream(stream));
+        else
+            err = hsg::launch_stream_sweeps(e, n_sweeps, n_hb, n_or, 0, 0, partial, as_stream(stream));
+        if (err != hipSuccess) return device(err, "sweep_static");
+    }
+    return ok();
+}
+
 hsg_status hsg_energy(const hsg_ensemble* ens, int n_ens, double* H_out, void* stream) {
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;

@@ -43,6 +43,10 @@ hipError_t launch_wave_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
                                 int block_threads, int replicas_per_block, double* partial,
                                 hipStream_t st);
+// Capacity (doubles) of the library's own device array that serves as `partial` for
+// callers that cannot allocate, and its address on the current device.
+constexpr size_t kStaticPartialDoubles = size_t(1) << 19;  // 4 MiB
+hipError_t static_partial(double** out);
 hipError_t launch_stream_anneal(const hsg_ensemble& e, int parity, int n_hb, int n_or,
                                 int block_threads, hipStream_t st);
 

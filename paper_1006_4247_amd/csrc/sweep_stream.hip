@@ -248,6 +248,37 @@ __global__ void k_stream_anneal_copy(hsg_ensemble e, int parity) {
     for (size_t v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
 }
 
+// ---------------------------------------------------------------- allocation-free form
+// Device-resident storage for the per-tile energy sums of the streaming sweeps, for
+// callers that cannot allocate (hsg_sweep_static).  Each device holds its own copy
+// until the process ends; its address on the current device comes from
+// hipGetSymbolAddress (the name itself is only a host-side stand-in).  Every tile
+// writes its sum before the finalising pass reads it, so nothing needs clearing.
+static __device__ __align__(256) double scratch[kStaticPartialDoubles];
+
+namespace {
+std::mutex g_static_mu;
+std::map<int, double*> g_static_ptr;  // device -> address of `scratch` there
+}  // namespace
+
+hipError_t static_partial(double** out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    auto it = g_static_ptr.find(dev);
+    if (it != g_static_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return err;
+    g_static_ptr[dev] = static_cast<double*>(p);
+    *out = static_cast<double*>(p);
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- dispatch
 template <typename T, int LT, int NT, int RB>
 static hipError_t launch_half(const hsg_ensemble& e, const StreamArgs& a, int gy, hipStream_t st) {
