@@ -28,14 +28,13 @@ HBM_PEAK_GBS = 8000.0
 N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
 VALU_PEAK_TOPS = N_CU * LANES_PER_CU * CLOCK_GHZ / 1e3  # 39.3 T lane-instructions/s
 
-# Algorithmic VALU operations per site update (one add/mul/FMA/compare/select, one
-# transcendental or one integer op each = 1), counted from the update formulas: a
-# 1 HB + 3 OR sweep averages (18 + 45 + 80/2 + 3 (18 + 12)) / 4 = 48.25 per update in
-# binary32, where one Philox block serves two sites.
-OPS_LOCAL_FIELD = 18          # 6 neighbours x 3 components, one FMA each
-OPS_OVERRELAX = 12            # s.S, |S|^2, 2(s.S)/S^2, f S - s
-OPS_HEATBATH = 45             # field norm and direction, R, w, c, sin(theta), frame, sin/cos(phi), s'
-OPS_PHILOX_PER_BLOCK = 10 * 8  # 10 rounds x (2 mul-lo, 2 mul-hi, 3 xor, key add)
+# Algorithmic VALU operations per site update, the op model of the scope table's
+# measurement row (one add/mul/FMA/compare, one transcendental or one integer op = 1):
+# heat-bath ~150 (18 FMA for the field; norm, direction and R; the angles with their
+# exp/log/sqrt/reciprocals; the frame; sin/cos of the azimuth; the rotation; ~50 integer
+# ops of Philox per two uniforms), overrelaxation ~30 (field 18, reflection 12).
+OPS_HEATBATH_UPDATE = 150
+OPS_OVERRELAX_UPDATE = 30
 
 WORKLOADS = {
     "plain-pt-L16-S64-C2-R24": dict(L=16, S=64, C=2, R=24, bmin=1.0, bmax=8.0, prec="fp32",
@@ -56,10 +55,8 @@ COOLHEAT_EPS_GRID_STUDY = {32: (0.0004, 0.0006, 0.0008, 0.001, 0.0015, 0.002, 0.
 COOLHEAT_EPS_GRID_PAIRS = (0.001, 0.0015, 0.002, 0.0025, 0.003, 0.0035, 0.004, 0.005, 0.006)
 
 
-def algorithmic_ops_per_update(n_hb, n_or, prec):
-    per_hb = OPS_LOCAL_FIELD + OPS_HEATBATH + OPS_PHILOX_PER_BLOCK / (2 if prec == "fp32" else 1)
-    per_or = OPS_LOCAL_FIELD + OPS_OVERRELAX
-    return (n_hb * per_hb + n_or * per_or) / (n_hb + n_or)
+def algorithmic_ops_per_update(n_hb, n_or):
+    return (n_hb * OPS_HEATBATH_UPDATE + n_or * OPS_OVERRELAX_UPDATE) / (n_hb + n_or)
 
 
 def hbm_bytes_per_launch(w, n_sweeps=1):
@@ -113,6 +110,26 @@ def measured_traffic(workload):
                 kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
                 if kv.get("workload") == workload and kv.get("sources_sha256") == digest:
                     return int(kv["bytes_per_launch"])
+    return None
+
+
+def measured_valu_instructions(workload, kernel):
+    """VALU wave-instructions per launch of `kernel` from the rocprofv3 SQ_INSTS_VALU
+    summary in profiles/ (its 'valu:' line), or None if it was taken on other kernel
+    sources or for another workload."""
+    if workload is None:
+        return None
+    path = os.path.join(ROOT, "profiles", "valu_lds_counters_k_resident_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    digest = kernel_sources_sha256()
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("valu:"):
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if (kv.get("workload") == workload and kv.get("sources_sha256") == digest
+                        and kv.get("kernel") == kernel.replace(" ", "")):
+                    return int(kv["insts_valu_per_launch"])
     return None
 
 
@@ -281,21 +298,27 @@ PAPER_T_MIN, PAPER_T_MAX = 0.12, 0.19
 PAPER_LADDERS = {16: dict(n_temps=15, n_or=20), 24: dict(n_temps=27, n_or=30), 32: dict(n_temps=43, n_or=40)}
 
 
-STUDY_METHODS = ("standard", "decimation", "coolheat", "coolheat_pairs")
+STUDY_METHODS = ("standard", "decimation", "coolheat", "coolheat_pairs", "learned")
 STUDY_DEFAULT = ("standard", "decimation", "coolheat")
 
 
-def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_DEFAULT, n_temps=0):
+def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_DEFAULT, n_temps=0,
+                       compact=False):
     """Standard, decimated and cooling / heating tempering (or a subset, `methods`; with
-    "coolheat_pairs", cooling / heating with its parameter tuned per pair) on
-    the paper's ladder for L (Sec. IV; n_temps > 0 replaces its N_T, as in the paper's
-    N_T = 22 runs at L = 24), all pairs in ascending order every cycle, on the same S
-    coupling sets (fresh Gaussian sets; the paper's ten are unpublished) with 2 chains:
-    per coupling set the acceptance, the round-trip time t_R = cycles x configurations /
-    trips (Sec. IV.B) and tau_int of the overlap susceptibility at T_min (window c = 4),
-    and, with standard tempering among the methods, the per-set speed-ups over it
-    averaged over the sets (Table II)."""
+    "coolheat_pairs", cooling / heating with its parameter tuned per pair; with
+    "learned", annealed exchanges whose protocols the learned schedule picks to minimise
+    the predicted GPU time per round trip) on the paper's ladder for L (Sec. IV; n_temps
+    > 0 replaces its N_T, as in the paper's N_T = 22 runs at L = 24), all pairs in
+    ascending order every cycle (the annealed exchange alternates even and odd pairs),
+    on the same S coupling sets (fresh Gaussian sets; the paper's ten are unpublished)
+    with 2 chains: per coupling set the acceptance, the round-trip time t_R = cycles x
+    configurations / trips (Sec. IV.B) and tau_int of the overlap susceptibility at
+    T_min (window c = 4), and, with standard tempering among the methods, the per-set
+    speed-ups over it averaged over the sets (Table II), with their standard errors;
+    per GPU-second they are divided by the relative GPU time of a cycle, timed from the
+    library's captured cycle of each method."""
     from paper_1006_4247_amd import analysis, runtime
+    from paper_1006_4247_amd import schedule as sch
 
     cfg = PAPER_LADDERS[L]
     R, n_or = (n_temps or cfg["n_temps"]), cfg["n_or"]
@@ -315,15 +338,30 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
             done += k
             print("[paper-ladder L=%d] %s %d/%d" % (L, what, done, n), file=sys.stderr, flush=True)
 
+    def cycle_ms(e, mode, eps, n=300, **kw):
+        # GPU time per cycle from the library's captured cycle
+        run = runtime.PTRun([e], 1, n_or, mode=mode, eps=eps, **kw)
+        run.capture()
+        run.replay(20)
+        run.synchronize()
+        t0 = time.perf_counter()
+        run.replay(n)
+        run.synchronize()
+        dt = time.perf_counter() - t0
+        run.release()
+        return dt / n * 1e3
+
     for method, mode in (("standard", "plain"), ("decimation", "decimate"), ("coolheat", "coolheat"),
-                         ("coolheat_pairs", "coolheat")):
+                         ("coolheat_pairs", "coolheat"), ("learned", "anneal")):
         if method not in methods:
             continue
-        e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32")
+        K_grid = (0, 1, 2, 4, 8)
+        e = hsg.Ensemble(L, S, C, betas, seed, precision="fp32", K_max=max(K_grid) if method == "learned" else 0)
         e.init_couplings()
         e.init_spins()
         t0 = time.perf_counter()
-        eps, table = 0.0, None
+        eps, table, extra = 0.0, None, {}
+        kw = dict(pairing=0)
         steps(runtime.PTRun([e], 1, n_or, mode="plain", pairing=0, measure=False), equil // 2,
               method + " equilibration (plain)")
         if method == "coolheat":
@@ -332,13 +370,40 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         elif method == "coolheat_pairs":
             eps, table = runtime.tune_coolheat_eps_pairs(e, COOLHEAT_EPS_GRID_PAIRS, steps=300, n_hb=1,
                                                          n_or=n_or, pairing=0)
-        steps(runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, measure=False), equil - equil // 2,
+        elif method == "learned":
+            # legs of one heat-bath and one overrelaxation lattice sweep per annealing step
+            # (any composition keeps the exchange exact; these cost a tenth of the cycle's)
+            leg = (1, 1)
+            kw = dict(anneal_sweep=leg)
+            tl = time.perf_counter()
+            e.set_schedule(np.zeros(R - 1, dtype=np.int32))
+            t_base = cycle_ms(e, "anneal", 0.0, **kw)
+            K0 = 4
+            e.set_schedule(np.full(R - 1, K0, dtype=np.int32))
+            t_leg = (cycle_ms(e, "anneal", 0.0, **kw) - t_base) / (K0 * (R - 1) / 2.0)
+            rng = np.random.default_rng(7)
+            x, y, wt = sch.generate_data(e, 40, K_grid, rng, n_hb=1, n_or=n_or, leg=leg)
+            net, loss = sch.train(x, y, wt, steps=3000)
+            kcol = np.rint(x[:, 5] * 32).astype(int)
+            fit = sch.predict(net, x)
+            extra_fit = {str(k): [round(float(y[kcol == k].mean()), 4), round(float(fit[kcol == k].mean()), 4)]
+                         for k in K_grid if np.any(kcol == k)}
+            _, _, et = e.measure()
+            ebar = et.mean(dim=(0, 1)).cpu().numpy()
+            K, G, pred = sch.select_schedule_round_trips(net, betas, ebar, L, K_grid, t_base, t_leg)
+            e.set_schedule(K, sch.protocol(betas, K, G, e.K_max))
+            extra = {"K": [int(k) for k in K], "gamma": [float(g) for g in G],
+                     "predicted_acceptance": [round(float(a), 4) for a in pred], "leg_sweep": "1 HB + 1 OR",
+                     "t_base_ms": round(t_base, 4), "t_leg_ms": round(t_leg, 5), "train_mse": round(loss, 5),
+                     "data_vs_fit_acceptance_by_K": extra_fit,
+                     "learner_s": round(time.perf_counter() - tl, 2)}
+        steps(runtime.PTRun([e], 1, n_or, mode=mode, eps=eps, measure=False, **kw), equil - equil // 2,
               method + " equilibration")
         torch.cuda.synchronize()
         eq_s = time.perf_counter() - t0
         st0 = e.swap_stats.cpu().numpy().copy()
         rt0 = e.rt_trips.cpu().numpy().copy()
-        run = runtime.PTRun([e], 1, n_or, mode=mode, pairing=0, eps=eps, series_len=cycles)
+        run = runtime.PTRun([e], 1, n_or, mode=mode, eps=eps, series_len=cycles, **kw)
         t0 = time.perf_counter()
         steps(run, cycles, method)
         dt = time.perf_counter() - t0
@@ -354,13 +419,19 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
         # the paper's other two windows (Sec. IV.B), for how the speed-up depends on c
         tau_c = {c: np.array([analysis.tau_int(chi[:, s, R - 1], c=float(c))[0] for s in range(S)])
                  for c in (6, 10)}
+        ms = cycle_ms(e, mode, eps, **kw)
         res[method] = dict(acc_set=acc_set, acc_pair=acc_pair, t_R=t_R, tau=tau, tau_c=tau_c, trips=trips,
-                           gpu_s=dt, eq_s=eq_s, eps=eps, table=table)
+                           gpu_s=dt, eq_s=eq_s, eps=eps, table=table, ms=ms, extra=extra)
 
     def q(a):
         a = np.asarray(a, dtype=np.float64)
         return {"mean": round(float(a.mean()), 4), "min": round(float(a.min()), 4),
                 "max": round(float(a.max()), 4)}
+
+    def me(a):
+        # mean over the coupling sets and its standard error
+        a = np.asarray(a, dtype=np.float64)
+        return [round(float(a.mean()), 3), round(float(a.std(ddof=1) / np.sqrt(len(a))), 3)]
 
     out = {"study": "paper-ladder", "L": L, "coupling_sets": S, "chains": C, "temperatures": R,
            "T": [PAPER_T_MIN, PAPER_T_MAX], "sweep": "1 HB + %d OR" % n_or, "exchange": "all pairs ascending",
@@ -369,34 +440,40 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
     for m, r in res.items():
         d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
              "t_R_per_set": q(r["t_R"]), "round_trips": int(r["trips"].sum()),
-             "tau_int_chi_Tmin_c4": q(r["tau"]), "tau_int_chi_Tmin_c6": q(r["tau_c"][6]),
-             "tau_int_chi_Tmin_c10": q(r["tau_c"][10]), "gpu_s": round(r["gpu_s"], 2),
-             "ms_per_cycle": round(r["gpu_s"] / cycles * 1e3, 4),
-             # per coupling set, in set order, so that runs of one method each on the same
-             # sets (same seed) can be paired set by set
-             "sets": {"acceptance": [round(float(x), 5) for x in r["acc_set"]],
-                      "t_R": [round(float(x), 1) for x in r["t_R"]],
-                      "tau_int_chi_Tmin_c4": [round(float(x), 3) for x in r["tau"]],
-                      "tau_int_chi_Tmin_c6": [round(float(x), 3) for x in r["tau_c"][6]],
-                      "tau_int_chi_Tmin_c10": [round(float(x), 3) for x in r["tau_c"][10]]}}
-        if m == "coolheat":
-            d["eps"] = r["eps"]
+             "tau_int_chi_Tmin_c4": q(r["tau"]), "gpu_s": round(r["gpu_s"], 2),
+             "ms_per_cycle": round(r["ms"], 4)}
+        if not compact:
+            d["tau_int_chi_Tmin_c6"] = q(r["tau_c"][6])
+            d["tau_int_chi_Tmin_c10"] = q(r["tau_c"][10])
+            # per coupling set, in set order, so that runs of one method each on the same
+            # sets (same seed) can be paired set by set
+            d["sets"] = {"acceptance": [round(float(x), 5) for x in r["acc_set"]],
+                         "t_R": [round(float(x), 1) for x in r["t_R"]],
+                         "tau_int_chi_Tmin_c4": [round(float(x), 3) for x in r["tau"]],
+                         "tau_int_chi_Tmin_c6": [round(float(x), 3) for x in r["tau_c"][6]],
+                         "tau_int_chi_Tmin_c10": [round(float(x), 3) for x in r["tau_c"][10]]}
+        if m in ("coolheat", "coolheat_pairs"):
+            d["eps"] = r["eps"] if m == "coolheat" else [float(x) for x in r["eps"]]
             d["eps_paper"] = COOLHEAT_EPS_PAPER.get(L)
-            d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
-        if m == "coolheat_pairs":
-            d["eps_per_pair"] = [float(x) for x in r["eps"]]
-            d["tuner_acceptance_per_pair"] = {("%g" % k): [round(x, 4) for x in v] for k, v in r["table"].items()}
+            if m == "coolheat":
+                d["tuner_acceptance"] = {("%g" % k): round(v, 4) for k, v in r["table"].items()}
+            else:
+                d["tuner_acceptance_per_pair"] = {("%g" % k): [round(x, 4) for x in v] for k, v in r["table"].items()}
+        d.update(r["extra"])
         if m != "standard" and std is not None:
-            cost = (r["gpu_s"] / cycles) / (std["gpu_s"] / cycles)  # GPU time per cycle vs standard
+            cost = r["ms"] / std["ms"]  # GPU time per cycle vs standard
+            rt_ratio = std["t_R"] / r["t_R"]
+            tau_ratio = std["tau"] / r["tau"]
+            d["cost_per_cycle_vs_standard"] = round(cost, 3)
             d["speedup_vs_standard"] = {
-                "acceptance": round(float(np.mean(r["acc_set"] / np.maximum(std["acc_set"], 1e-12))), 3),
-                "round_trip": round(float(np.mean(std["t_R"] / r["t_R"])), 3),
-                "tau_int_chi": round(float(np.mean(std["tau"] / r["tau"])), 3),
-                "tau_int_chi_c6": round(float(np.mean(std["tau_c"][6] / r["tau_c"][6])), 3),
-                "tau_int_chi_c10": round(float(np.mean(std["tau_c"][10] / r["tau_c"][10])), 3),
+                "acceptance": me(r["acc_set"] / np.maximum(std["acc_set"], 1e-12)),
+                "round_trip": me(rt_ratio), "tau_int_chi": me(tau_ratio),
                 # the same per GPU-second: per-cycle speed-ups over the relative cost of a cycle
-                "round_trip_per_gpu_s": round(float(np.mean(std["t_R"] / r["t_R"])) / cost, 3),
-                "tau_int_chi_per_gpu_s": round(float(np.mean(std["tau"] / r["tau"])) / cost, 3)}
+                "round_trip_per_gpu_s": me(rt_ratio / cost), "tau_int_chi_per_gpu_s": me(tau_ratio / cost),
+                "form": "[mean over coupling sets, standard error]"}
+            if not compact:
+                d["speedup_vs_standard"]["tau_int_chi_c6"] = me(std["tau_c"][6] / r["tau_c"][6])
+                d["speedup_vs_standard"]["tau_int_chi_c10"] = me(std["tau_c"][10] / r["tau_c"][10])
         out[m] = d
     return out
 
@@ -407,48 +484,56 @@ UNEVEN = dict(Ls=[8, 12, 16, 24, 32], samples=[128, 64, 32, 16, 8], temps=[8, 12
               seed=0x100642470004)
 
 
-def uneven_study(torch, hsg, steps, warm=20):
+def uneven_study(torch, hsg, steps, warm=20, tunings=(None, "auto")):
     """Steps of the uneven batch (sweep 1 HB + 3 OR, plain exchange, measurement per
-    class, the classes on their own streams) replayed from a HIP graph: site updates per
-    ns over the batch, and the algorithmic HBM bytes of its sweeps per second (LDS-resident
-    classes: the parity-1 half of every replica read and all of it written once per
-    sweep, couplings once; streaming classes, one launch per half-sweep: per half-sweep
-    the updated half read and written and the other half read, couplings once per
-    sample)."""
+    class, the classes on their own streams) replayed from the library's captured cycle:
+    site updates per ns over the batch, and the algorithmic HBM bytes of its sweeps per
+    second (LDS-resident classes: the parity-1 half of every replica read and all of it
+    written once per sweep, couplings once; streaming classes, one launch per
+    half-sweep: per half-sweep the updated half read and written and the other half
+    read, couplings once per sample); with the library's default kernels and with the
+    autotuner's choice per class."""
     from paper_1006_4247_amd import runtime
     ens = runtime.uneven_batch(UNEVEN["Ls"], UNEVEN["samples"], UNEVEN["temps"], UNEVEN["seed"])
     for e in ens:
         e.init_couplings()
         e.init_spins()
-    run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0)
-    run.step(warm)
-    run.capture()
-    run.replay(warm)
-    run.synchronize()
-    t0 = time.perf_counter()
-    run.replay(steps)
-    run.synchronize()
-    dt = time.perf_counter() - t0
-    run.check()
-    upd = run.site_updates_per_step() * steps
-    nbytes = 0
-    classes = []
-    for e in ens:
-        N, slots = e.N, e.n_slots
-        resident = e.L <= 16
-        if resident:  # one launch per sweep
-            b = slots * (3 * (N // 2) * 4 + 3 * N * 4) + e.S * 3 * N * 4
-        else:  # 8 half-sweeps, each reading the whole replica and writing half of it
-            b = 8 * (slots * (3 * N * 4 + 3 * (N // 2) * 4) + e.S * 3 * N * 4)
-        nbytes += b * steps
-        classes.append({"L": e.L, "samples": e.S, "temperatures": e.R, "path": "resident" if resident else "streaming",
-                        "spin_MB": round(slots * 3 * N * 4 / 1e6, 1)})
-    gbs = nbytes / dt / 1e9
-    return {"study": "uneven-batch", "classes": classes, "chains": 2, "steps": steps,
-            "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
-            "site_updates_per_ns": round(upd / dt / 1e9, 2), "ms_per_step": round(dt / steps * 1e3, 4),
-            "sweep_algorithmic_hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % UNEVEN["seed"]}
+    out = {"study": "uneven-batch", "chains": 2, "steps": steps,
+           "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % UNEVEN["seed"]}
+    for tun in tunings:
+        run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0, tunings=tun)
+        run.step(warm)
+        run.capture()
+        run.replay(warm)
+        run.synchronize()
+        t0 = time.perf_counter()
+        run.replay(steps)
+        run.synchronize()
+        dt = time.perf_counter() - t0
+        run.check()
+        run.release()
+        upd = run.site_updates_per_step() * steps
+        nbytes = 0
+        classes = []
+        for e, t in zip(ens, run.tunings):
+            N, slots = e.N, e.n_slots
+            path = (t or {}).get("path", 0) or (3 if e.L <= 16 else 2)
+            resident = path in (1, 3)
+            if resident:  # one launch per sweep
+                b = slots * (3 * (N // 2) * 4 + 3 * N * 4) + e.S * 3 * N * 4
+            elif path == 4:  # one pass per lattice sweep: read all, write all
+                b = 4 * (slots * 2 * 3 * N * 4 + e.S * 3 * N * 4)
+            else:  # 8 half-sweeps, each reading the whole replica and writing half of it
+                b = 8 * (slots * (3 * N * 4 + 3 * (N // 2) * 4) + e.S * 3 * N * 4)
+            nbytes += b * steps
+            classes.append({"L": e.L, "samples": e.S, "temperatures": e.R, "tuning": t or "default",
+                            "spin_MB": round(slots * 3 * N * 4 / 1e6, 1)})
+        gbs = nbytes / dt / 1e9
+        key = "default_kernels" if tun is None else "autotuned"
+        out[key] = {"classes": classes, "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
+                    "site_updates_per_ns": round(upd / dt / 1e9, 2), "ms_per_step": round(dt / steps * 1e3, 4),
+                    "sweep_algorithmic_hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def copy_probe(torch, mib, reps=10):
@@ -470,6 +555,97 @@ def copy_probe(torch, mib, reps=10):
                       "GBs": 2 * n * 4 / (ms.mean() / 1e3) / 1e9}), flush=True)
 
 
+def phase(name):
+    """A progress line on stderr naming the phase that starts (so a log says where a
+    run stopped)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, name), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
+def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
+    """The workload's step (sweep of every replica, measurement, plain exchange of all
+    pairs ascending) as the library's captured cycle (a plan: one graph launch per step),
+    timed over exactly `steps` replays after `warmup` untimed ones; before those, the
+    cycle is replayed for about `clock_warmup_s` seconds so that the chip runs at its
+    steady clock.  The dominant kernel's average duration is then taken from HIP events
+    around a batch of back-to-back sweep launches on the same stream."""
+    from paper_1006_4247_amd import runtime
+    dev = torch.device("cuda:0")
+    betas = hsg.geometric_betas(w["bmin"], w["bmax"], w["R"])
+    ens = hsg.Ensemble(w["L"], w["S"], w["C"], betas, w["seed"], precision=w["prec"], device=dev)
+    ens.init_couplings()
+    ens.init_spins()
+    run = runtime.PTRun([ens], w["n_hb"], w["n_or"], mode="plain", pairing=0)
+    run.capture()
+    stream = torch.cuda.current_stream(dev)
+    # steady clocks: replay until clock_warmup_s has passed (not counted)
+    t_w = time.perf_counter()
+    n_clock = 0
+    while time.perf_counter() - t_w < clock_warmup_s:
+        run.replay(200)
+        run.synchronize()
+        n_clock += 200
+    run.replay(warmup)
+    run.synchronize()
+    stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.replay(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    run.check()
+    stats1 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
+    acc = (stats1[:, 1] - stats0[:, 1]).astype(np.float64)
+    att = (stats1[:, 0] - stats0[:, 0]).astype(np.float64)
+    run.release()
+    ens.stream = None  # eager calls below go to this stream (the run had given it its own)
+    # the dominant kernel: back-to-back sweep launches on this stream, events around them
+    n_k = max(50, min(400, int(0.05 / max(elapsed / max(steps, 1), 1e-5))))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ens.sweep(5, w["n_hb"], w["n_or"])
+    ev0.record(stream)
+    for _ in range(n_k):
+        ens.sweep(1, w["n_hb"], w["n_or"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    avg_launch_s = ev0.elapsed_time(ev1) / 1e3 / n_k
+    ens.check()
+
+    N = w["L"] ** 3
+    slots = w["S"] * w["C"] * w["R"]
+    upd_per_step = slots * N * (w["n_hb"] + w["n_or"])
+    ops = algorithmic_ops_per_update(w["n_hb"], w["n_or"]) * upd_per_step
+    alu_achieved = ops / avg_launch_s / 1e12
+    hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
+    name = resident_kernel_name(w)
+    workload = [k for k, v in WORKLOADS.items() if v == w]
+    valu = measured_valu_instructions(workload[0] if workload else None, name)
+    roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(workload[0]) if workload else None,
+                "kernel": "%s (one sweep of every replica per launch)" % name,
+                "avg_launch_ms": round(avg_launch_s * 1e3, 5),
+                "avg_launch_from": "HIP events around %d back-to-back sweep launches on the run's stream" % n_k,
+                "ops_per_site_update": algorithmic_ops_per_update(w["n_hb"], w["n_or"]),
+                "valu_issue_frac": (round(valu / (N_CU * CLOCK_GHZ * 1e9 * avg_launch_s), 4) if valu else None),
+                "valu_wave_instructions_per_launch": valu,
+                "hbm_algorithmic_GBs": round(hbm_achieved, 1),
+                "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
+                "sweep_site_updates_per_ns": round(upd_per_step / avg_launch_s / 1e9, 2)}
+    return {"value": round(steps * upd_per_step / (elapsed * 1e9), 3),
+            "ms_per_step": round(elapsed * 1e3 / steps, 5),
+            "timing": {"timed": "%d replays of the captured cycle (hsg_plan_run), one graph launch per step"
+                                % steps,
+                       "clock_warmup": "%d untimed replays (%.2f s) before the %d warm-up steps"
+                                       % (n_clock, clock_warmup_s, warmup)},
+            "roofline": roofline,
+            "acceptance": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
+            "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -479,6 +655,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exchange-comparison", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the binary64 line, the uneven batch and the paper-ladder study")
+    ap.add_argument("--clock-warmup", type=float, default=1.5, metavar="SECONDS",
+                    help="untimed replays of the step before the counted warm-up (steady clocks)")
+    ap.add_argument("--uneven-steps", type=int, default=200, help="steps of the uneven batch in the default run")
+    ap.add_argument("--study-sets-default", type=int, default=64,
+                    help="coupling sets of the default run's compact L = 16 paper-ladder study")
+    ap.add_argument("--study-cycles-default", type=int, nargs=2, default=[3000, 12000], metavar=("EQUIL", "MEASURE"))
     ap.add_argument("--compare-steps", type=int, nargs=2, default=[20000, 4000], metavar=("PLAIN", "ANNEAL"),
                     help="steps of the plain dense-ladder run and of each annealed run")
     ap.add_argument("--paper-ladder", type=int, default=0, metavar="L",
@@ -525,73 +709,44 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    betas = hsg.geometric_betas(w["bmin"], w["bmax"], w["R"])
-    ens = hsg.Ensemble(w["L"], w["S"], w["C"], betas, w["seed"], precision=w["prec"], device=dev)
-    ens.init_couplings()
-    ens.init_spins()
-    stream = torch.cuda.current_stream(dev)
-
-    def step(evs=None):
-        if evs is not None:
-            evs[0].record(stream)
-        ens.sweep(1, w["n_hb"], w["n_or"])
-        if evs is not None:
-            evs[1].record(stream)
-        ens.swap(0)
-        ens.measure()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ens.check()
-    elapsed = t1 - t0
-    sweep_ms = np.array([a.elapsed_time(b) for a, b in events])
-    stats1 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
-    acc = (stats1[:, 1] - stats0[:, 1]).astype(np.float64)
-    att = (stats1[:, 0] - stats0[:, 0]).astype(np.float64)
-
-    N = w["L"] ** 3
-    slots = w["S"] * w["C"] * w["R"]
-    upd_per_step = slots * N * (w["n_hb"] + w["n_or"])
-    value = args.steps * upd_per_step / (elapsed * 1e9)
-    avg_launch_s = float(sweep_ms.mean()) / 1e3
-    ops = algorithmic_ops_per_update(w["n_hb"], w["n_or"], w["prec"]) * upd_per_step
-    alu_achieved = ops / avg_launch_s / 1e12
-    hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
-    roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(args.workload),
-                "kernel": "%s (one sweep of every replica per launch)" % resident_kernel_name(w),
-                "avg_launch_ms": round(avg_launch_s * 1e3, 5),
-                "hbm_algorithmic_GBs": round(hbm_achieved, 1),
-                "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
-                "sweep_site_updates_per_ns": round(upd_per_step / avg_launch_s / 1e9, 2)}
+    phase("headline: %s" % args.workload)
+    head = headline(torch, hsg, w, args.steps, args.warmup, args.clock_warmup)
     line = {
         "metric": "site-updates/ns & HBM roofline %; accepted swaps per GPU-s vs plain PT",
-        "value": round(value, 3), "unit": "site-updates/ns", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "value": head["value"], "unit": "site-updates/ns", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": w["prec"].replace("fp", "f"),
         "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % w["seed"],
         "config": {"workload": args.workload, "L": w["L"], "samples": w["S"], "chains": w["C"],
                    "temperatures": w["R"], "beta": [w["bmin"], w["bmax"]], "sweep": "%d HB + %d OR" % (w["n_hb"], w["n_or"]),
                    "exchange": "all neighbour pairs, ascending, every step", "measure": "every step"},
-        "roofline": roofline,
-        "swap_acceptance_per_pair": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
-        "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1),  # this ladder (acceptance ~0)
+        "timing": head["timing"],
+        "roofline": head["roofline"],
+        "swap_acceptance_per_pair": head["acceptance"],
+        "accepted_swaps_per_gpu_s": head["accepted_swaps_per_gpu_s"],  # this ladder (acceptance ~0)
     }
+    if not args.no_extras:
+        if w["prec"] == "fp32":
+            phase("the same workload in binary64 (the paper's precision)")
+            w64 = dict(w, prec="fp64")
+            h64 = headline(torch, hsg, w64, max(args.steps, 200), args.warmup, 0.5)
+            line["fp64_same_shape"] = {"value": h64["value"], "unit": "site-updates/ns",
+                                       "ms_per_step": h64["ms_per_step"],
+                                       "sweep_kernel_avg_ms": h64["roofline"]["avg_launch_ms"],
+                                       "kernel": h64["roofline"]["kernel"], "steps": max(args.steps, 200)}
+        phase("uneven batch (five size classes, beyond the MALL)")
+        line["uneven_batch"] = uneven_study(torch, hsg, args.uneven_steps)
+        phase("paper-ladder study L=16 (round trips per GPU-second)")
+        line["paper_ladder_L16"] = paper_ladder_study(torch, hsg, 16, args.study_sets_default,
+                                                      args.study_cycles_default[1], args.study_cycles_default[0],
+                                                      methods=STUDY_DEFAULT + ("learned",), compact=True)
     if not args.no_exchange_comparison:
+        phase("exchange comparison (dense ladder, annealed, decimated, cooling/heating)")
         line["exchange_comparison"] = exchange_comparison(torch, hsg, w, *args.compare_steps)
     if not args.no_cpu_baseline:
+        phase("cpu baseline (the oracle on the host)")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    phase("done")
     print(json.dumps(line), flush=True)
 
 

@@ -260,6 +260,44 @@ hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream);
 hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
                              void* stream);
 
+/* --- plans: a captured cycle of several ensembles ----------------------------
+ * One cycle of the method (scope: the workloads' step) for every ensemble: n_hb
+ * heat-bath and n_or overrelaxation lattice sweeps with the measurement of the swept
+ * configurations (hsg_sweep_measure, or hsg_sweep_tuned + hsg_measure when a tuning is
+ * given), then one exchange pass (hsg_swap, hsg_anneal_swap, hsg_decimate_swap or
+ * hsg_coolheat_swap[_pairs]).  hsg_plan_create captures that cycle into HIP graphs
+ * inside the library, each ensemble on a capture stream of its own so that the size
+ * classes of an uneven batch run concurrently; hsg_plan_run launches it n_cycles
+ * times on `stream` (one graph launch per cycle), with the results of the same calls
+ * made eagerly, bit for bit.  Exchanges that alternate between even and odd pairs
+ * (pairing -1; the annealed exchange always does) start with the even pairs and the
+ * plan remembers the next parity across runs.
+ *
+ * tuning_json: NULL, "" or a flat JSON object; keys (all optional):
+ *   "exchange": "plain" (default) | "anneal" | "decimate" | "coolheat" | "none"
+ *   "pairing": -1 alternate even / odd pairs, 0 all ascending, 1 even, 2 odd
+ *              (default 0 for plain, -1 otherwise)
+ *   "n_hb", "n_or": sweep composition (default 1, 3); "measure": 0 | 1 (default 1)
+ *   "anneal_n_hb", "anneal_n_or": composition of the annealing legs' sweeps
+ *   "eps": one cooling / heating parameter, or an array of one per pair of every
+ *          ensemble, ensembles in order (the library keeps its own device copy)
+ *   "path", "block_threads", "replicas_per_block", "flags": hsg_tuning fields, one
+ *          value or an array with one per ensemble
+ *   "streams": 0 to capture all ensembles on one stream (default 1)
+ * Unknown keys and malformed values are refused (HSG_ERR_INVALID).  The plan copies the
+ * descriptors: the caller's device buffers must stay allocated, and the descriptors'
+ * pointers unchanged, until hsg_plan_destroy.  Creating a plan enqueues nothing on the
+ * caller's streams and changes no state; it allocates the graphs (and the per-pair eps
+ * copy).  A plan is used from one host thread at a time, on the device it was created
+ * on; runs on one plan must not overlap.  *plan receives an opaque handle. */
+hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tuning_json, void** plan);
+hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream);
+hsg_status hsg_plan_destroy(void* plan);
+/* Parity (0 even, 1 odd) of the next cycle's exchange (alternating plans; 0 otherwise),
+ * and setting it (e.g. to continue a run that started eagerly). */
+int hsg_plan_next_parity(const void* plan);
+hsg_status hsg_plan_set_next_parity(void* plan, int parity);
+
 /* Synchronise `stream`, then report the guards: HSG_ERR_NUMERIC if any is set. */
 hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream);
 

@@ -60,6 +60,11 @@ SIGNATURES = {
     "hsg_measure": (_i, [_E, _i, _vp]),
     "hsg_sweep_measure": (_i, [_E, _i, _i, _i, _i, _vp]),
     "hsg_check": (_i, [_E, _i, _vp]),
+    "hsg_plan_create": (_i, [_E, _i, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "hsg_plan_run": (_i, [_vp, _i, _vp]),
+    "hsg_plan_destroy": (_i, [_vp]),
+    "hsg_plan_next_parity": (_i, [_vp]),
+    "hsg_plan_set_next_parity": (_i, [_vp, _i]),
     "hsg_mlp_forward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp]),
     "hsg_mlp_backward": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp]),
     "hsg_mlp_mse_grad": (_i, [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),

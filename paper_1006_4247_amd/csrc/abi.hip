@@ -115,6 +115,10 @@ hsg_ensemble launch_copy(const hsg_ensemble& e, const hsg_tuning* t = nullptr) {
 
 }  // namespace
 
+namespace hsg {
+void set_last_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg ? msg : ""); }
+}  // namespace hsg
+
 extern "C" {
 
 int hsg_abi_version(void) { return HSG_ABI_VERSION; }

@@ -7,6 +7,9 @@
 
 namespace hsg {
 
+// The thread's message for hsg_last_error (entry points implemented outside abi.hip).
+void set_last_error(const char* msg);
+
 // Largest dynamic LDS a workgroup may use on this device (bytes).
 size_t max_block_lds();
 // Allows `kern` more than 64 KiB of dynamic LDS on the current device (once per

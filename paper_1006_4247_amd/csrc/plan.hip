@@ -9,6 +9,7 @@
 // are numbers, strings or arrays of numbers); unknown keys are refused.
 #include <cctype>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -20,14 +21,15 @@
 
 namespace {
 
-thread_local char g_plan_err[512] = "";
-
+// Failures are reported like every other entry point's (hsg_last_error).
 hsg_status plan_fail(hsg_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 hsg_status plan_fail(hsg_status code, const char* fmt, ...) {
+    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_plan_err, sizeof(g_plan_err), fmt, ap);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
+    hsg::set_last_error(buf);
     return code;
 }
 
@@ -41,7 +43,7 @@ struct Settings {
     int streams = 1;
     double eps = 0.0;
     std::vector<double> eps_pairs;  // per pair of every ensemble, ensembles in order
-    std::vector<int> path, block_threads, replicas_per_block;  // one value or one per ensemble
+    std::vector<int> path, block_threads, replicas_per_block, flags;  // one value or one per ensemble
 };
 
 struct Parser {
@@ -177,6 +179,7 @@ hsg_status parse(const char* json, Settings& s) {
                 } else if (key == "path") ok = as_ints(v, s.path);
                 else if (key == "block_threads") ok = as_ints(v, s.block_threads);
                 else if (key == "replicas_per_block") ok = as_ints(v, s.replicas_per_block);
+                else if (key == "flags") ok = as_ints(v, s.flags);
                 else return plan_fail(HSG_ERR_INVALID, "plan settings: unknown key \"%s\"", key.c_str());
                 if (!ok) return plan_fail(HSG_ERR_INVALID, "plan settings: %s must be an integer", key.c_str());
             }
@@ -266,7 +269,8 @@ hsg_status capture(Plan& pl, int parity, int slot) {
             }
             result = enqueue_cycle(pl, i, parity, st);
             if (result != HSG_OK) {
-                plan_fail(result, "plan capture, ensemble %d: %s", i, hsg_last_error());
+                const std::string why = hsg_last_error();
+                plan_fail(result, "plan capture, ensemble %d: %s", i, why.c_str());
                 break;
             }
             if (fork) {
@@ -285,14 +289,14 @@ hsg_status capture(Plan& pl, int parity, int slot) {
             if (err != hipSuccess) result = plan_fail(HSG_ERR_DEVICE, "plan instantiate: %s", hipGetErrorString(err));
         }
         if (result == HSG_OK) pl.graph[slot] = g;
-        else if (g) hipGraphDestroy(g);
+        else if (g) (void)hipGraphDestroy(g);
     }
     for (size_t i = 0; i < side.size(); ++i) {
-        if (join[i]) hipEventDestroy(join[i]);
-        if (side[i]) hipStreamDestroy(side[i]);
+        if (join[i]) (void)hipEventDestroy(join[i]);
+        if (side[i]) (void)hipStreamDestroy(side[i]);
     }
-    if (start) hipEventDestroy(start);
-    if (cap) hipStreamDestroy(cap);
+    if (start) (void)hipEventDestroy(start);
+    if (cap) (void)hipStreamDestroy(cap);
     return result;
 }
 
@@ -300,21 +304,19 @@ void release(Plan* pl) {
     if (!pl) return;
     int cur = 0;
     const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != pl->device;
-    if (switch_dev) hipSetDevice(pl->device);
+    if (switch_dev) (void)hipSetDevice(pl->device);
     for (int k = 0; k < 2; ++k) {
-        if (pl->exec[k]) hipGraphExecDestroy(pl->exec[k]);
-        if (pl->graph[k]) hipGraphDestroy(pl->graph[k]);
+        if (pl->exec[k]) (void)hipGraphExecDestroy(pl->exec[k]);
+        if (pl->graph[k]) (void)hipGraphDestroy(pl->graph[k]);
     }
-    if (pl->eps_dev) hipFree(pl->eps_dev);
-    if (switch_dev) hipSetDevice(cur);
+    if (pl->eps_dev) (void)hipFree(pl->eps_dev);
+    if (switch_dev) (void)hipSetDevice(cur);
     delete pl;
 }
 
 }  // namespace
 
 extern "C" {
-
-const char* hsg_plan_last_error(void) { return g_plan_err; }
 
 hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tuning_json, void** plan) {
     if (!plan) return plan_fail(HSG_ERR_INVALID, "plan: the output pointer is NULL");
@@ -349,14 +351,15 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
             if (!(v >= 0.0)) return bad("eps must be >= 0");
     }
     auto per_ens = [&](const std::vector<int>& v, int i) { return v.empty() ? 0 : (v.size() == 1 ? v[0] : v[i]); };
-    for (const auto* v : {&s.path, &s.block_threads, &s.replicas_per_block})
+    for (const auto* v : {&s.path, &s.block_threads, &s.replicas_per_block, &s.flags})
         if (v->size() > 1 && static_cast<int>(v->size()) != n_ens) return bad("tuning arrays need one value per ensemble");
     pl->tune.resize(n_ens);
     pl->tuned.resize(n_ens);
     for (int i = 0; i < n_ens; ++i) {
-        hsg_tuning t{per_ens(s.path, i), per_ens(s.block_threads, i), per_ens(s.replicas_per_block, i), 0};
+        hsg_tuning t{per_ens(s.path, i), per_ens(s.block_threads, i), per_ens(s.replicas_per_block, i),
+                     per_ens(s.flags, i)};
         pl->tune[i] = t;
-        pl->tuned[i] = t.path != 0 || t.block_threads != 0 || t.replicas_per_block != 0;
+        pl->tuned[i] = t.path != 0 || t.block_threads != 0 || t.replicas_per_block != 0 || t.flags != 0;
     }
     hipError_t err = hipGetDevice(&pl->device);
     if (err != hipSuccess) {
@@ -381,7 +384,7 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         return r;
     }
     *plan = pl;
-    g_plan_err[0] = '\0';
+    hsg::set_last_error("");
     return HSG_OK;
 }
 
@@ -396,7 +399,7 @@ hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream) {
         if (err != hipSuccess) return plan_fail(HSG_ERR_DEVICE, "plan run: %s", hipGetErrorString(err));
         if (pl->alternating) pl->next_parity ^= 1;
     }
-    g_plan_err[0] = '\0';
+    hsg::set_last_error("");
     return HSG_OK;
 }
 

@@ -188,21 +188,21 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 // mode 0: regular sweeps of slot (work item) at its own temperature.
 // mode 1: annealing legs of the pairs with i mod 2 == parity; block ->
 //         (chain, pair, leg); leg 0 = up (forward order), 1 = down (adjoint).
+// The work of one workgroup: work item `bid` (see above), the replica in the LDS at
+// smem_raw, `red` and `s_H` workgroup-shared scratch of >= NT/64 and 1 doubles.  Used
+// by k_resident and by the persistent batch kernel (sweep_batch.hip).
 template <typename T, int L, int NT>
-__global__ void __launch_bounds__(NT)
-    k_resident(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int anneal, int parity) {
+__device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, int n_sweeps, int n_hb, int n_or,
+                                              int anneal, int parity, unsigned char* smem_raw, double* red,
+                                              double& s_H) {
     constexpr int N = L * L * L, NQ = N / 4;
     constexpr int MQ = (NQ + NT - 1) / NT;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
-    __shared__ double red[(NT + 63) / 64];
-    __shared__ double s_H;
 
     const int C = e.n_chains, R = e.n_temps;
     int slot, leg = 0, ipair = 0, K = n_sweeps, ch = 0;
     double lam_a = 0.0, lam_b = 0.0;
     const double* lam_tab = nullptr;
-    const int bid = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
     if (!anneal) {
         slot = bid;
     } else {
@@ -366,6 +366,16 @@ __global__ void __launch_bounds__(NT)
             e.sweep_ctr[slot] = t0 + static_cast<uint32_t>(n_sweeps);
         }
     }
+}
+
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT)
+    k_resident(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int anneal, int parity) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[(NT + 63) / 64];
+    __shared__ double s_H;
+    resident_item<T, L, NT>(e, xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)), n_sweeps,
+                            n_hb, n_or, anneal, parity, smem_raw, red, s_H);
 }
 
 // Regular sweeps and the measurement of one (sample, temperature) in one launch, for

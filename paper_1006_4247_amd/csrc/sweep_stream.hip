@@ -56,16 +56,17 @@ __device__ __forceinline__ double proto(const hsg_ensemble& e, int ipair, int K,
     return a + static_cast<double>(k) * (b - a) / static_cast<double>(K + 1);
 }
 
+// One work item of a half-sweep: tile `tile` of the replica group `group` (`red`:
+// workgroup-shared scratch of >= NT/64 doubles).  Used by k_stream_half and by the
+// persistent batch kernel (sweep_batch.hip).
 template <typename T, int LT, int NT, int RB>
-__global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a) {
+__device__ __forceinline__ void stream_tile(const hsg_ensemble& e, const StreamArgs& a, int tile, int group,
+                                            double* red) {
     const int L = LT > 0 ? LT : e.L;
     const int N = L * L * L, NH = N / 2, NQ = N / 4;
-    __shared__ double red[(NT + 63) / 64];
     const int C = e.n_chains, R = e.n_temps;
     const ScratchLayout sl = scratch_layout(e);
     unsigned char* scr = static_cast<unsigned char*>(e.scratch);
-    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-    const int tile = item % a.n_tiles, group = item / a.n_tiles;
     const int q = tile * NT + static_cast<int>(threadIdx.x);
     const bool active = q < NQ;
 
@@ -173,6 +174,13 @@ __global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a
                 a.partial[static_cast<size_t>(slot) * sl.max_tiles + tile] = -tot;
         }
     }
+}
+
+template <typename T, int LT, int NT, int RB>
+__global__ void __launch_bounds__(NT) k_stream_half(hsg_ensemble e, StreamArgs a) {
+    __shared__ double red[(NT + 63) / 64];
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    stream_tile<T, LT, NT, RB>(e, a, item % a.n_tiles, item / a.n_tiles, red);
 }
 
 // Sum the per-tile energies of every slot in tile order.  Regular: energy[] and

@@ -5,13 +5,18 @@ sweep and measurement of the swept configurations (one launch where an ensemble'
 chains fit one workgroup per temperature) -> exchange (plain, Eq. (1), annealed,
 decimated or cooling / heating).  Each size class runs
 on its own HIP stream, so the kernels of an uneven batch (several L, sample counts and
-ladders) overlap on the chip; `capture()` records one or two steps of every class into
-a HIP graph (torch's graph API drives the capture; every kernel is ours) so that
-replays cost one launch.  Observables are copied into device-resident time series.
+ladders) overlap on the chip; `capture()` builds a plan of the library
+(hsg_plan_create: the library captures one cycle of every class into a HIP graph,
+each class on a capture stream of its own) and `replay()` runs it (hsg_plan_run, one
+graph launch per cycle).  Observables are copied into device-resident time series.
 """
+import ctypes
+import json
+
 import numpy as np
 import torch
 
+from . import _abi
 from .ensemble import Ensemble
 
 
@@ -22,7 +27,9 @@ class PTRun:
     alternating even / odd pairs, or all pairs ascending every step if pairing == 0;
     mode 'coolheat': cooling / heating exchange (paper Sec. III.B) with parameter
     `eps` (one number, R - 1 per-pair values, or one such sequence per ensemble),
-    pairs as for 'decimate'."""
+    pairs as for 'decimate'.  tunings: None (the library's default kernels), 'auto' (the
+    autotuner's fastest sweep variant per ensemble shape, cached per device), or one
+    tuning dict (or None) per ensemble."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
                  series_len=0, tunings=None, anneal_sweep=None, eps=0.0):
@@ -50,7 +57,12 @@ class PTRun:
         self.mode = mode
         self.pairing = pairing
         self.measure = measure
-        self.tunings = tunings or [None] * len(self.ens)
+        if isinstance(tunings, str):
+            if tunings != "auto":
+                raise ValueError("tunings must be None, 'auto' or one tuning dict (or None) per ensemble")
+            from .autotune import tune_ensemble
+            tunings = [tune_ensemble(e, n_hb, n_or)[0] for e in self.ens]
+        self.tunings = list(tunings) if tunings else [None] * len(self.ens)
         self.anneal_sweep = anneal_sweep or (n_hb, n_or)
         dev = self.ens[0].device
         self.device = dev
@@ -58,6 +70,7 @@ class PTRun:
         self.parity = 0
         self.steps_done = 0
         self.graph = None
+        self.plan = None
         self.graph_steps = 0
         self.series_len = int(series_len)
         self.series_pos = 0
@@ -121,35 +134,68 @@ class PTRun:
         return p
 
     # ------------------------------------------------------------ graphs
+    def plan_settings(self):
+        """The cycle as the library's plan settings (hsg_plan_create's JSON)."""
+        names = {"plain": "plain", "anneal": "anneal", "decimate": "decimate", "coolheat": "coolheat"}
+        st = {"exchange": names[self.mode], "n_hb": int(self.n_hb), "n_or": int(self.n_or),
+              "measure": int(bool(self.measure))}
+        if self.mode == "plain":
+            st["pairing"] = int(self.pairing)
+        elif self.mode in ("decimate", "coolheat"):
+            st["pairing"] = int(self.pairing) if self.pairing >= 0 else -1
+        if self.mode == "anneal":
+            st["anneal_n_hb"], st["anneal_n_or"] = int(self.anneal_sweep[0]), int(self.anneal_sweep[1])
+        if self.mode == "coolheat":
+            if self.eps is not None:
+                st["eps"] = float(self.eps)
+            else:
+                st["eps"] = [float(v) for t in self.eps_of for v in t.detach().cpu().numpy()]
+        if any(t is not None for t in self.tunings):
+            for k in ("path", "block_threads", "replicas_per_block"):
+                st[k] = [int((t or {}).get(k, 0)) for t in self.tunings]
+        return st
+
     def capture(self, n_steps=None):
-        """Record n_steps steps (default: 1, or 2 where the exchange alternates between
-        even and odd pairs, one per parity) of every size class into one HIP graph.  Time series are not recorded
-        inside graphs."""
+        """Build the library plan of one cycle of every size class (captured into HIP
+        graphs inside the library).  Time series are not recorded by plans.  The plan
+        reads the ensembles' descriptors as they are now (schedules included)."""
         if self.series_len:
-            raise RuntimeError("graph capture does not record time series (series_len must be 0)")
-        alternating = self.mode == "anneal" or (self.mode in ("decimate", "coolheat") and self.pairing < 0)
-        n_steps = n_steps or (2 if alternating else 1)
+            raise RuntimeError("plans do not record time series (series_len must be 0)")
+        self.release()
         torch.cuda.synchronize(self.device)
-        g = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream(device=self.device)
-        cap.wait_stream(torch.cuda.current_stream(self.device))
-        with torch.cuda.graph(g, stream=cap):
-            par = self.parity
-            for _ in range(n_steps):
-                self._fork(lambda i, p=par: self._step_one(i, p, None))
-                par ^= 1
-        torch.cuda.synchronize(self.device)
-        self.graph = g
-        self.graph_steps = n_steps
-        return g
+        for e in self.ens:
+            e._fill_desc()
+        descs = (_abi.HsgEnsemble * len(self.ens))(*[e.desc for e in self.ens])
+        plan = ctypes.c_void_p()
+        txt = json.dumps(self.plan_settings()).encode()
+        _abi.check(_abi.lib().hsg_plan_create(descs, len(self.ens), txt, ctypes.byref(plan)))
+        self.plan = plan
+        self._plan_descs = descs
+        _abi.check(_abi.lib().hsg_plan_set_next_parity(self.plan, int(self.parity)))
+        self.graph = plan
+        self.graph_steps = 1
+        return plan
 
     def replay(self, n=1):
-        """Replay the captured steps n times (on the current stream)."""
-        for _ in range(n):
-            self.graph.replay()
-            self.steps_done += self.graph_steps
-            if self.graph_steps % 2 == 1:
-                self.parity ^= 1
+        """Run n cycles of the plan (on the current stream)."""
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _abi.check(_abi.lib().hsg_plan_run(self.plan, int(n), st))
+        self.steps_done += int(n)
+        self.parity = int(_abi.lib().hsg_plan_next_parity(self.plan))
+
+    def release(self):
+        """Destroy the plan (if any); eager steps are possible again."""
+        if getattr(self, "plan", None) is not None:
+            torch.cuda.synchronize(self.device)
+            _abi.lib().hsg_plan_destroy(self.plan)
+        self.plan = None
+        self.graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:  # interpreter shutdown
+            pass
 
     # ------------------------------------------------------------ checkpoint / resume
     def save(self, prefix):
@@ -166,13 +212,26 @@ class PTRun:
                        else [t.cpu().numpy().tolist() for t in self.eps_of]}, fh)
 
     def restore(self, prefix):
-        """Load the state written by save() into this run's ensembles (same shapes)."""
+        """Load the state written by save() into this run's ensembles (same shapes).  The
+        run's own dynamics (exchange mode, pairing, sweep composition, cooling / heating
+        parameters) must be those of the saved run: a resumed run that silently changed
+        them would not continue the same Markov chain, so a mismatch raises."""
         import json
         from safetensors import safe_open
         with open(prefix + ".json") as fh:
             pos = json.load(fh)
         if pos["n_classes"] != len(self.ens):
             raise ValueError("checkpoint holds %d size classes, this run %d" % (pos["n_classes"], len(self.ens)))
+        mine = {"mode": self.mode, "pairing": self.pairing, "n_hb": self.n_hb, "n_or": self.n_or}
+        for k, v in mine.items():
+            if pos.get(k) != v:
+                raise ValueError("checkpoint %s = %r, this run %r" % (k, pos.get(k), v))
+        eps = (self.eps if self.eps is not None else [t.cpu().numpy().tolist() for t in self.eps_of])
+        if self.mode == "coolheat" and not np.allclose(np.asarray(pos.get("eps"), dtype=np.float64),
+                                                       np.asarray(eps, dtype=np.float64), rtol=0, atol=0):
+            raise ValueError("checkpoint eps = %r, this run %r" % (pos.get("eps"), eps))
+        # kernels of this run may still be in flight on the classes' streams
+        self.synchronize()
         for i, e in enumerate(self.ens):
             with safe_open("%s.%d.safetensors" % (prefix, i), framework="pt") as f:
                 m = json.loads(f.metadata()["hsg_meta"])

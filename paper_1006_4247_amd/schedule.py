@@ -158,10 +158,12 @@ def acceptance_from_work(work, parity):
 
 
 # ---------------------------------------------------------------- data and selection
-def generate_data(ens, n_rounds, K_choices, rng, gammas=GAMMAS, sweeps_between=2, n_hb=1, n_or=3):
+def generate_data(ens, n_rounds, K_choices, rng, gammas=GAMMAS, sweeps_between=2, n_hb=1, n_or=3, leg=None):
     """Annealed exchanges with random protocols (chosen independently of the states) on
-    `ens` (needs K_max >= max(K_choices)).  Returns (x [n][7] float32, target [n],
-    weight [n]) with one record per (pair, attempt)."""
+    `ens` (needs K_max >= max(K_choices)), sweeps of n_hb + n_or between them, legs of
+    `leg` = (n_hb, n_or) sweeps (default the same).  Returns (x [n][7] float32,
+    target [n], weight [n]) with one record per (pair, attempt)."""
+    leg = leg or (n_hb, n_or)
     X, Y, Wt = [], [], []
     R = ens.R
     betas = ens.betas_host
@@ -174,7 +176,7 @@ def generate_data(ens, n_rounds, K_choices, rng, gammas=GAMMAS, sweeps_between=2
             ens.sweep(sweeps_between, n_hb, n_or)
             _, _, e = ens.measure()
             ebar = e.mean(dim=(0, 1)).cpu().numpy()
-            ens.anneal_swap(parity, n_hb, n_or)
+            ens.anneal_swap(parity, *leg)
             acc, sel = acceptance_from_work(ens.work.cpu().numpy(), parity)
             idx = np.nonzero(sel)[0]
             X.append(features(betas[idx], betas[idx + 1], ebar[idx], ebar[idx + 1], ens.L, K[idx], G[idx]))

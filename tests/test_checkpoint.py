@@ -72,3 +72,24 @@ def test_resume_is_bitwise_identical(tmp_path, mode):
     for k in a._STATE:
         assert torch.equal(getattr(a, k), getattr(b, k)), k
     a.check()
+
+
+@pytest.mark.gpu
+def test_restore_refuses_other_dynamics(tmp_path):
+    """A checkpoint resumes only the run it came from: another exchange, pairing, sweep
+    composition or cooling / heating parameter raises instead of silently continuing a
+    different Markov chain."""
+    e = hsg.Ensemble(4, 1, 2, hsg.geometric_betas(0.8, 3.0, 4), 0x5A18, precision="fp32")
+    e.init_couplings()
+    e.init_spins()
+    run = runtime.PTRun([e], 1, 3, mode="coolheat", eps=0.01)
+    run.step(2)
+    prefix = str(tmp_path / "ckpt")
+    run.save(prefix)
+    for kw in (dict(mode="coolheat", eps=0.02), dict(mode="decimate"), dict(mode="coolheat", eps=0.01, pairing=0)):
+        other = runtime.PTRun([e], 1, 3, **kw)
+        with pytest.raises(ValueError):
+            other.restore(prefix)
+    with pytest.raises(ValueError):
+        runtime.PTRun([e], 1, 5, mode="coolheat", eps=0.01).restore(prefix)
+    runtime.PTRun([e], 1, 3, mode="coolheat", eps=0.01).restore(prefix)

@@ -93,3 +93,22 @@ def test_layout_conversion_matches_oracle_indexing(L):
     b = natural_to_device(a, L)
     assert b.shape == (2, 3, 3, 2, N // 2)
     assert np.array_equal(device_to_natural(b, L), a)
+
+
+def test_plan_settings_are_validated_without_gpu():
+    """hsg_plan_create parses and checks its JSON settings before touching the device:
+    malformed or unknown settings return HSG_ERR_INVALID with a message."""
+    _abi = _lib_or_skip()
+    lib = _abi.lib()
+    d = (_abi.HsgEnsemble * 1)()
+    plan = ctypes.c_void_p()
+    bad = [b'{"exchange": "bogus"}', b'{"nope": 1}', b'{"pairing": 1.5}',
+           b'{"exchange": "anneal", "pairing": 0}', b'[1]', b'{"eps": [0.1, 0.2]}',
+           b'{"n_hb": 0, "n_or": 0}', b'{"exchange": "coolheat", "eps": -1}', b'{"path": [1, 2]}',
+           b'{"exchange": "plain"} x']
+    for js in bad:
+        assert lib.hsg_plan_create(d, 1, js, ctypes.byref(plan)) == _abi.HSG_ERR_INVALID, js
+        assert lib.hsg_last_error(), js
+        assert not plan.value
+    assert lib.hsg_plan_create(d, 0, b"{}", ctypes.byref(plan)) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_plan_run(None, 1, None) == _abi.HSG_ERR_INVALID
