@@ -484,24 +484,29 @@ UNEVEN = dict(Ls=[8, 12, 16, 24, 32], samples=[128, 64, 32, 16, 8], temps=[8, 12
               seed=0x100642470004)
 
 
-def uneven_study(torch, hsg, steps, warm=20, tunings=(None, "auto")):
-    """Steps of the uneven batch (sweep 1 HB + 3 OR, plain exchange, measurement per
-    class, the classes on their own streams) replayed from the library's captured cycle:
-    site updates per ns over the batch, and the algorithmic HBM bytes of its sweeps per
-    second (LDS-resident classes: the parity-1 half of every replica read and all of it
-    written once per sweep, couplings once; streaming classes, one launch per
-    half-sweep: per half-sweep the updated half read and written and the other half
-    read, couplings once per sample); with the library's default kernels and with the
-    autotuner's choice per class."""
-    from paper_1006_4247_amd import runtime
+def uneven_study(torch, hsg, steps, warm=20):
+    """Steps of the uneven batch (sweep 1 HB + 3 OR, measurement, plain exchange of all
+    pairs ascending, per class) replayed from the library's captured cycle: site updates
+    per ns over the batch, and the algorithmic HBM bytes of its sweeps per second
+    (LDS-resident classes: the parity-1 half of every replica read and all of it written
+    once per sweep, couplings once; streaming classes, one launch per half-sweep: per
+    half-sweep the updated half read and written and the other half read, couplings once
+    per sample; wavefront: one read and one write per lattice sweep).  Three forms: the
+    library's default kernels with the classes one after another, the same with each
+    class on its own stream, and the autotuner's kernels and order; and, for the sweeps
+    alone, one persistent launch over all classes (tuning path 5) against the classes'
+    sweeps one after another."""
+    import ctypes
+    from paper_1006_4247_amd import _abi, runtime
     ens = runtime.uneven_batch(UNEVEN["Ls"], UNEVEN["samples"], UNEVEN["temps"], UNEVEN["seed"])
     for e in ens:
         e.init_couplings()
         e.init_spins()
     out = {"study": "uneven-batch", "chains": 2, "steps": steps,
            "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % UNEVEN["seed"]}
-    for tun in tunings:
-        run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0, tunings=tun)
+    for key, tun, conc in (("default_kernels_in_sequence", None, False), ("default_kernels_concurrent", None, True),
+                           ("autotuned", "auto", "auto")):
+        run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0, tunings=tun, concurrent=conc)
         run.step(warm)
         run.capture()
         run.replay(warm)
@@ -518,8 +523,7 @@ def uneven_study(torch, hsg, steps, warm=20, tunings=(None, "auto")):
         for e, t in zip(ens, run.tunings):
             N, slots = e.N, e.n_slots
             path = (t or {}).get("path", 0) or (3 if e.L <= 16 else 2)
-            resident = path in (1, 3)
-            if resident:  # one launch per sweep
+            if path in (1, 3):  # one launch per sweep
                 b = slots * (3 * (N // 2) * 4 + 3 * N * 4) + e.S * 3 * N * 4
             elif path == 4:  # one pass per lattice sweep: read all, write all
                 b = 4 * (slots * 2 * 3 * N * 4 + e.S * 3 * N * 4)
@@ -529,10 +533,40 @@ def uneven_study(torch, hsg, steps, warm=20, tunings=(None, "auto")):
             classes.append({"L": e.L, "samples": e.S, "temperatures": e.R, "tuning": t or "default",
                             "spin_MB": round(slots * 3 * N * 4 / 1e6, 1)})
         gbs = nbytes / dt / 1e9
-        key = "default_kernels" if tun is None else "autotuned"
-        out[key] = {"classes": classes, "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
+        out[key] = {"classes": classes, "concurrent": run.concurrent,
+                    "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
                     "site_updates_per_ns": round(upd / dt / 1e9, 2), "ms_per_step": round(dt / steps * 1e3, 4),
                     "sweep_algorithmic_hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # the sweeps alone: one persistent launch over the five classes against the classes'
+    # default sweep launches one after another
+    for e in ens:
+        e.stream = None
+    descs = (_abi.HsgEnsemble * len(ens))(*[e.desc for e in ens])
+    tb = _abi.HsgTuning(5, 0, 0, 0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def one_launch():
+        _abi.check(_abi.lib().hsg_sweep_tuned(descs, len(ens), 1, 1, 3, ctypes.byref(tb), stream))
+
+    def in_sequence():
+        for e in ens:
+            e.sweep(1, 1, 3)
+
+    res = {}
+    n = max(10, steps // 10)
+    for name, fn in (("classes_in_sequence", in_sequence), ("one_persistent_launch", one_launch)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        res[name] = {"ms_per_sweep": round(dt * 1e3, 4),
+                     "site_updates_per_ns": round(sum(e.n_slots * e.N * 4 for e in ens) / dt / 1e9, 2)}
+    for e in ens:
+        e.check()
+    out["sweeps_one_persistent_launch_vs_in_sequence"] = res
     return out
 
 

@@ -18,7 +18,8 @@
  *  - Numerical trouble seen by a kernel (a non-finite spin or energy, a spin
  *    whose norm left 1 by more than the precision's tolerance, a protocol
  *    length outside [0, anneal_K_max], a temperature label outside [0, R), a
- *    cooling map that is not a bijection) is latched in *guard (bits 1, 2, 4, 8)
+ *    cooling map that is not a bijection, a wait of the persistent batch launch that
+ *    ran out) is latched in *guard (bits 1, 2, 4, 8, 16)
  *    and reported by hsg_check as
  *    HSG_ERR_NUMERIC.  Out-of-range values are clamped before use, so a
  *    corrupted label or protocol length never addresses outside its ensemble.
@@ -117,8 +118,15 @@ typedef struct hsg_tuning {
                                workgroups; 2 streaming half-sweeps; 3 LDS-resident lattice,
                                one workgroup per replica; 4 wavefront: one workgroup per
                                replica walking its z-planes, one HBM pass per lattice
-                               sweep (L 18..40 binary32, 18..28 binary64) */
-    int32_t block_threads;  /* threads per workgroup */
+                               sweep (L 18..40 binary32, 18..28 binary64); 5 one persistent
+                               launch over all the ensembles of the call (at most 8, one
+                               precision, L >= 4): L = 12, 14, 16 swept in LDS, one
+                               replica per work item from a counter, the others in tiles
+                               half-sweep by half-sweep behind a barrier of their own
+                               part of the grid (they, and the first ensemble, need their
+                               scratch); spins as with the other paths, bit for bit */
+    int32_t block_threads;  /* threads per workgroup (path 5: workgroups of the tiled part,
+                               a multiple of 8; 0 = by its share of the work) */
     int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */
     int32_t flags;          /* HSG_TUNE_NO_RENORM: binary32 sweeps without a heat-bath lattice
                                sweep skip their once-per-sweep renormalisation s <- s/|s|
@@ -284,6 +292,9 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
  *   "path", "block_threads", "replicas_per_block", "flags": hsg_tuning fields, one
  *          value or an array with one per ensemble
  *   "streams": 0 to capture all ensembles on one stream (default 1)
+ *   "unroll": cycles per graph of the plan's second, unrolled form (default 8; runs of
+ *             at least that many cycles launch it, so a graph launch is paid once per
+ *             `unroll` cycles)
  * Unknown keys and malformed values are refused (HSG_ERR_INVALID).  The plan copies the
  * descriptors: the caller's device buffers must stay allocated, and the descriptors'
  * pointers unchanged, until hsg_plan_destroy.  Creating a plan enqueues nothing on the

@@ -155,11 +155,28 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
     if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
         return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
                     n_sweeps, n_hb, n_or);
-    if (tuning && (tuning->path < 0 || tuning->path > 4 || tuning->block_threads < 0 ||
+    if (tuning && (tuning->path < 0 || tuning->path > 5 || tuning->block_threads < 0 ||
                    tuning->replicas_per_block < 0 || (tuning->flags & ~HSG_TUNE_NO_RENORM) != 0))
         return fail(HSG_ERR_INVALID, "bad tuning values");
     hsg_status s = check_all(ens, n_ens, kState);
     if (s != HSG_OK) return s;
+    if (tuning && tuning->path == 5) {
+        if (n_ens > 8) return fail(HSG_ERR_UNSUPPORTED, "the persistent batch launch takes at most 8 ensembles");
+        hsg_ensemble copy[8];
+        for (int i = 0; i < n_ens; ++i) copy[i] = launch_copy(ens[i], tuning);
+        if (!hsg::batch_supported(copy, n_ens))
+            return fail(HSG_ERR_UNSUPPORTED,
+                        "the persistent batch launch needs one precision, L >= 4, and the scratch of the first "
+                        "ensemble and of every ensemble it sweeps in tiles (L other than 12, 14, 16)");
+        for (int i = 0; i < n_ens; ++i) {
+            s = check_one(ens[i], i, i == 0 || hsg::batch_needs_scratch(ens[i]) ? kScratch : 0u);
+            if (s != HSG_OK) return s;
+        }
+        if (n_sweeps == 0) return ok();
+        return device(hsg::launch_batch_sweeps(copy, n_ens, n_sweeps, n_hb, n_or, tuning->block_threads,
+                                               as_stream(stream)),
+                      "persistent batch sweep");
+    }
     for (int i = 0; i < n_ens; ++i) {
         if (tuning && tuning->path == 1 && !hsg::persistent_supported(ens[i]))
             return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the persistent LDS-resident path", i, ens[i].L);
@@ -386,11 +403,12 @@ hsg_status hsg_check(const hsg_ensemble* ens, int n_ens, void* stream) {
         err = hipMemcpy(&g, ens[i].guard, sizeof(g), hipMemcpyDeviceToHost);
         if (err != hipSuccess) return device(err, "check: read guard");
         if (g != 0)
-            return fail(HSG_ERR_NUMERIC, "ensemble %d: guard = %d (%s%s%s%s)", i, g,
+            return fail(HSG_ERR_NUMERIC, "ensemble %d: guard = %d (%s%s%s%s%s)", i, g,
                         (g & 1) ? "non-finite or non-unit spin or energy; " : "",
                         (g & 2) ? "protocol length outside [0, anneal_K_max]; " : "",
                         (g & 4) ? "temperature label outside [0, R); " : "",
-                        (g & 8) ? "cooling map not a bijection (eps |S| >= 1)" : "");
+                        (g & 8) ? "cooling map not a bijection (eps |S| >= 1); " : "",
+                        (g & 16) ? "a wait of the persistent batch launch timed out (results invalid)" : "");
     }
     return ok();
 }

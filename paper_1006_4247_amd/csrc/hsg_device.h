@@ -340,9 +340,9 @@ __device__ __forceinline__ uint32_t heatbath_c3(int hs) {
 // Scratch layout (bytes, each region aligned to 256):
 //   candidate spins [slots][3][2][N/2] T | candidate energy [slots] double |
 //   accept flags [slots] int32 | partial sums [slots][max_tiles] double |
-//   work accumulators [slots] double
+//   work accumulators [slots] double | counters (256 bytes)
 struct ScratchLayout {
-    size_t cand, cand_energy, flags, partial, wacc, total;
+    size_t cand, cand_energy, flags, partial, wacc, ctr, total;
     int max_tiles;
 };
 
@@ -366,6 +366,8 @@ __host__ __device__ inline ScratchLayout scratch_layout(const hsg_ensemble& e) {
     off += align256(slots * static_cast<size_t>(s.max_tiles) * 8);
     s.wacc = off;
     off += align256(slots * 8);
+    s.ctr = off;  // work and barrier counters of the persistent batch launch
+    off += 256;
     s.total = off;
     return s;
 }

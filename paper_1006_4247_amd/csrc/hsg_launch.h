@@ -16,6 +16,21 @@ size_t max_block_lds();
 // kernel and device; thread-safe).
 hipError_t allow_dynamic_lds(const void* kern, size_t lds);
 
+// Compute units of the current device, and how many workgroups of `kern` (nt
+// threads, lds bytes of dynamic LDS) one CU holds (queried once per kernel and device).
+int device_cus();
+hipError_t blocks_per_cu_query(const void* kern, int nt, size_t lds, int* out);
+
+// One persistent launch over the regular sweeps of all the ensembles of a call (at most
+// 8, one precision; L >= 4; ensembles swept in tiles and the first one need their
+// scratch): L = 12..16 classes in LDS from a work counter, the others half-sweep by
+// half-sweep behind a barrier of their own partition of `g_str` workgroups (0: by the
+// classes' share of the work).
+bool batch_supported(const hsg_ensemble* ens, int n_ens);
+bool batch_needs_scratch(const hsg_ensemble& e);
+hipError_t launch_batch_sweeps(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or, int g_str,
+                               hipStream_t st);
+
 // LDS-resident path: true if one replica of `e` fits in a workgroup's LDS and
 // an instantiation for e.L exists.
 bool resident_supported(const hsg_ensemble& e);

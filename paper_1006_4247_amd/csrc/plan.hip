@@ -3,7 +3,9 @@
 // by hsg_plan_run.  Each ensemble's work is forked onto a capture stream of its own, so
 // the size classes of an uneven batch run concurrently in the graph; the whole cycle
 // is one graph launch.  Exchanges that alternate between even and odd pairs keep two
-// graphs (one per parity) and the plan remembers which parity comes next.
+// graphs (one per parity) and the plan remembers which parity comes next.  A second
+// pair of graphs holds `unroll` cycles each (default 8): long runs launch those, so
+// the per-launch cost of a graph is paid once per `unroll` cycles.
 //
 // The cycle's settings come from a small JSON object (a flat set of keys whose values
 // are numbers, strings or arrays of numbers); unknown keys are refused.
@@ -41,6 +43,7 @@ struct Settings {
     int anneal_n_hb = -1, anneal_n_or = -1;
     int measure = 1;
     int streams = 1;
+    int unroll = 8;  // cycles per graph of the unrolled form (1: single-cycle graphs only)
     double eps = 0.0;
     std::vector<double> eps_pairs;  // per pair of every ensemble, ensembles in order
     std::vector<int> path, block_threads, replicas_per_block, flags;  // one value or one per ensemble
@@ -173,6 +176,7 @@ hsg_status parse(const char* json, Settings& s) {
                 else if (key == "anneal_n_or") ok = as_int(v, s.anneal_n_or);
                 else if (key == "measure") ok = as_int(v, s.measure);
                 else if (key == "streams") ok = as_int(v, s.streams);
+                else if (key == "unroll") ok = as_int(v, s.unroll);
                 else if (key == "eps") {
                     if (v.size() == 1) s.eps = v[0];
                     else s.eps_pairs = v;
@@ -207,8 +211,9 @@ struct Plan {
     int next_parity = 0;
     int device = 0;
     double* eps_dev = nullptr;  // per-pair cooling / heating parameters (library-owned)
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    // [0], [1]: one cycle starting with exchange parity 0 / 1; [2], [3]: `unroll` cycles
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 // One cycle of ensemble i on stream st: sweep and measurement, then the exchange.
@@ -240,8 +245,9 @@ hsg_status enqueue_cycle(const Plan& pl, int i, int parity, hipStream_t st) {
     }
 }
 
-// Capture one cycle (exchange parity `parity`) of every ensemble into pl.graph/exec[slot].
-hsg_status capture(Plan& pl, int parity, int slot) {
+// Capture n_cyc cycles of every ensemble, the first with exchange parity `parity`
+// (alternating from there for alternating plans), into pl.graph/exec[slot].
+hsg_status capture(Plan& pl, int parity, int n_cyc, int slot) {
     const int n = static_cast<int>(pl.ens.size());
     const bool fork = pl.set.streams != 0 && n > 1;
     hipStream_t cap = nullptr;
@@ -260,6 +266,7 @@ hsg_status capture(Plan& pl, int parity, int slot) {
         result = plan_fail(HSG_ERR_DEVICE, "plan capture setup: %s", hipGetErrorString(err));
     } else {
         if (fork) err = hipEventRecord(start, cap);
+        // each ensemble's cycles follow one another on its stream; the streams join at the end
         for (int i = 0; i < n && err == hipSuccess && result == HSG_OK; ++i) {
             hipStream_t st = cap;
             if (fork) {
@@ -267,7 +274,11 @@ hsg_status capture(Plan& pl, int parity, int slot) {
                 err = hipStreamWaitEvent(st, start, 0);
                 if (err != hipSuccess) break;
             }
-            result = enqueue_cycle(pl, i, parity, st);
+            int par = parity;
+            for (int c = 0; c < n_cyc && result == HSG_OK; ++c) {
+                result = enqueue_cycle(pl, i, par, st);
+                if (pl.alternating) par ^= 1;
+            }
             if (result != HSG_OK) {
                 const std::string why = hsg_last_error();
                 plan_fail(result, "plan capture, ensemble %d: %s", i, why.c_str());
@@ -305,7 +316,7 @@ void release(Plan* pl) {
     int cur = 0;
     const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != pl->device;
     if (switch_dev) (void)hipSetDevice(pl->device);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (pl->exec[k]) (void)hipGraphExecDestroy(pl->exec[k]);
         if (pl->graph[k]) (void)hipGraphDestroy(pl->graph[k]);
     }
@@ -337,6 +348,7 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         return plan_fail(HSG_ERR_INVALID, "plan settings: %s", msg);
     };
     if (s.pairing < -1 || s.pairing > 2) return bad("pairing must be -1 (alternate), 0, 1 or 2");
+    if (s.unroll < 1 || s.unroll > 256) return bad("unroll must be in [1, 256]");
     if (s.exchange == 1 && s.pairing >= 0) return bad("the annealed exchange alternates even and odd pairs (pairing -1)");
     if (s.n_hb < 0 || s.n_hb > 127 || s.n_or < 0 || s.n_hb + s.n_or < 1) return bad("need 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1");
     if (!(s.eps >= 0.0)) return bad("eps must be >= 0");
@@ -377,8 +389,10 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         }
     }
     // the exchange parity of the first cycle is 0; alternating plans keep a second graph
-    r = capture(*pl, 0, 0);
-    if (r == HSG_OK && pl->alternating) r = capture(*pl, 1, 1);
+    r = capture(*pl, 0, 1, 0);
+    if (r == HSG_OK && pl->alternating) r = capture(*pl, 1, 1, 1);
+    if (r == HSG_OK && s.unroll > 1) r = capture(*pl, 0, s.unroll, 2);
+    if (r == HSG_OK && s.unroll > 1 && pl->alternating) r = capture(*pl, 1, s.unroll, 3);
     if (r != HSG_OK) {
         release(pl);
         return r;
@@ -393,11 +407,16 @@ hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream) {
     if (n_cycles < 0) return plan_fail(HSG_ERR_INVALID, "plan: n_cycles must be >= 0");
     Plan* pl = static_cast<Plan*>(plan);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < n_cycles; ++k) {
-        const int g = pl->alternating ? pl->next_parity : 0;
+    const int U = pl->set.unroll;
+    int left = n_cycles;
+    while (left > 0) {
+        const bool big = U > 1 && left >= U;
+        const int g = (big ? 2 : 0) + (pl->alternating ? pl->next_parity : 0);
         const hipError_t err = hipGraphLaunch(pl->exec[g], st);
         if (err != hipSuccess) return plan_fail(HSG_ERR_DEVICE, "plan run: %s", hipGetErrorString(err));
-        if (pl->alternating) pl->next_parity ^= 1;
+        const int done = big ? U : 1;
+        if (pl->alternating) pl->next_parity ^= (done & 1);
+        left -= done;
     }
     hsg::set_last_error("");
     return HSG_OK;

@@ -4,8 +4,9 @@
 sweep and measurement of the swept configurations (one launch where an ensemble's two
 chains fit one workgroup per temperature) -> exchange (plain, Eq. (1), annealed,
 decimated or cooling / heating).  Each size class runs
-on its own HIP stream, so the kernels of an uneven batch (several L, sample counts and
-ladders) overlap on the chip; `capture()` builds a plan of the library
+on its own HIP stream if asked (concurrent=True), so the kernels of an uneven batch
+(several L, sample counts and ladders) overlap on the chip; `capture()` builds a plan of
+the library
 (hsg_plan_create: the library captures one cycle of every class into a HIP graph,
 each class on a capture stream of its own) and `replay()` runs it (hsg_plan_run, one
 graph launch per cycle).  Observables are copied into device-resident time series.
@@ -29,10 +30,13 @@ class PTRun:
     `eps` (one number, R - 1 per-pair values, or one such sequence per ensemble),
     pairs as for 'decimate'.  tunings: None (the library's default kernels), 'auto' (the
     autotuner's fastest sweep variant per ensemble shape, cached per device), or one
-    tuning dict (or None) per ensemble."""
+    tuning dict (or None) per ensemble.  concurrent: size classes one after another on
+    the current stream (False), each on a stream of its own so that their kernels
+    overlap (True), or whichever of the two runs the cycle faster ('auto', timed on
+    the run's own steps)."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
-                 series_len=0, tunings=None, anneal_sweep=None, eps=0.0):
+                 series_len=0, tunings=None, anneal_sweep=None, eps=0.0, concurrent=False):
         if mode not in ("plain", "anneal", "decimate", "coolheat"):
             raise ValueError("mode must be 'plain', 'anneal', 'decimate' or 'coolheat'")
         # cooling / heating parameter: one number, R - 1 per-pair values shared by the
@@ -66,7 +70,10 @@ class PTRun:
         self.anneal_sweep = anneal_sweep or (n_hb, n_or)
         dev = self.ens[0].device
         self.device = dev
-        self.streams = [torch.cuda.Stream(device=dev) for _ in self.ens]
+        if concurrent not in (False, True, "auto"):
+            raise ValueError("concurrent must be False, True or 'auto'")
+        self.concurrent = bool(concurrent) and len(self.ens) > 1
+        self.streams = [torch.cuda.Stream(device=dev) for _ in self.ens] if len(self.ens) > 1 else []
         self.parity = 0
         self.steps_done = 0
         self.graph = None
@@ -79,8 +86,10 @@ class PTRun:
                                            device=dev) for e in self.ens]
             self.e_series = [torch.zeros((self.series_len,) + tuple(e.e_temp.shape), dtype=torch.float64,
                                          device=dev) for e in self.ens]
-        for e, s in zip(self.ens, self.streams):
-            e.stream = s
+        for e in self.ens:
+            e.stream = None  # steps run on the current stream, or on self.streams when concurrent
+        if concurrent == "auto" and len(self.ens) > 1 and not self.series_len:
+            self.concurrent = self._pick_concurrency()
 
     # ------------------------------------------------------------ one step
     def _step_one(self, i, parity, slot):
@@ -104,6 +113,10 @@ class PTRun:
             e.anneal_swap(parity, *self.anneal_sweep)
 
     def _fork(self, fn):
+        if not self.concurrent:
+            for i in range(len(self.ens)):
+                fn(i)
+            return
         cur = torch.cuda.current_stream(self.device)
         for s in self.streams:
             s.wait_stream(cur)
@@ -112,6 +125,26 @@ class PTRun:
                 fn(i)
         for s in self.streams:
             cur.wait_stream(s)
+
+    def _pick_concurrency(self, steps=20):
+        """Autotuning of the batch's order: time captured cycles with the size classes one
+        after another and with each on its own stream (real steps of the run, counted),
+        and keep the faster."""
+        import time
+        best, best_t = False, None
+        for conc in (False, True):
+            self.concurrent = conc
+            self.capture()
+            self.replay(2)
+            self.synchronize()
+            t0 = time.perf_counter()
+            self.replay(steps)
+            self.synchronize()
+            dt = time.perf_counter() - t0
+            self.release()
+            if best_t is None or dt < best_t:
+                best, best_t = conc, dt
+        return best
 
     def step(self, n=1):
         """n eager steps (asynchronous)."""
@@ -150,12 +183,13 @@ class PTRun:
                 st["eps"] = float(self.eps)
             else:
                 st["eps"] = [float(v) for t in self.eps_of for v in t.detach().cpu().numpy()]
+        st["streams"] = int(self.concurrent)
         if any(t is not None for t in self.tunings):
             for k in ("path", "block_threads", "replicas_per_block"):
                 st[k] = [int((t or {}).get(k, 0)) for t in self.tunings]
         return st
 
-    def capture(self, n_steps=None):
+    def capture(self, n_steps=None, unroll=None):
         """Build the library plan of one cycle of every size class (captured into HIP
         graphs inside the library).  Time series are not recorded by plans.  The plan
         reads the ensembles' descriptors as they are now (schedules included)."""
@@ -167,7 +201,10 @@ class PTRun:
             e._fill_desc()
         descs = (_abi.HsgEnsemble * len(self.ens))(*[e.desc for e in self.ens])
         plan = ctypes.c_void_p()
-        txt = json.dumps(self.plan_settings()).encode()
+        st = self.plan_settings()
+        if unroll is not None:
+            st["unroll"] = int(unroll)
+        txt = json.dumps(st).encode()
         _abi.check(_abi.lib().hsg_plan_create(descs, len(self.ens), txt, ctypes.byref(plan)))
         self.plan = plan
         self._plan_descs = descs

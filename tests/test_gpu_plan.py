@@ -78,7 +78,7 @@ def test_plan_replay_equals_eager_cycles(settings):
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     try:
         parity = 0
-        for n in (3, 0, 2):
+        for n in (3, 0, 19, 2):
             for _ in range(n):
                 for e in a:
                     _eager_cycle(e, settings, parity)

@@ -41,15 +41,16 @@ def _equal(a, b):
             assert np.array_equal(sa[k], sb[k]), k
 
 
-@pytest.mark.parametrize("mode", ["plain", "anneal"])
-def test_graph_replay_equals_eager(mode):
+@pytest.mark.parametrize("mode,concurrent", [("plain", False), ("anneal", False), ("plain", True),
+                                             ("anneal", True)])
+def test_graph_replay_equals_eager(mode, concurrent):
     K = 2 if mode == "anneal" else None
     a = _classes(K_max=2)
     b = _classes(K_max=2)
     _init(a, K)
     _init(b, K)
-    ra = runtime.PTRun(a, mode=mode)
-    rb = runtime.PTRun(b, mode=mode)
+    ra = runtime.PTRun(a, mode=mode, concurrent=concurrent)
+    rb = runtime.PTRun(b, mode=mode, concurrent=concurrent)
     rb.capture()
     per = rb.graph_steps
     for it in range(4):
@@ -70,7 +71,7 @@ def test_classes_on_streams_equal_classes_alone():
     _init(together)
     alone = _classes()
     _init(alone)
-    runtime.PTRun(together).step(3)
+    runtime.PTRun(together, concurrent=True).step(3)
     for e in alone:
         runtime.PTRun([e]).step(3)
     torch.cuda.synchronize()
@@ -114,3 +115,21 @@ def test_autotuner_picks_supported_variant(tmp_path, monkeypatch):
     e.init_spins()
     e.sweep(1, 1, 3, tuning=best)
     e.check()
+
+
+def test_concurrency_autotuning_keeps_the_chain():
+    """concurrent='auto' times captured cycles both ways on the run's own steps; those
+    steps are real (counted), and the run then continues exactly like a run that took
+    the same number of steps."""
+    a = _classes()
+    _init(a)
+    b = _classes()
+    _init(b)
+    ra = runtime.PTRun(a, concurrent="auto")
+    assert ra.concurrent in (False, True)
+    rb = runtime.PTRun(b)
+    rb.step(ra.steps_done)
+    ra.step(3)
+    rb.step(3)
+    ra.synchronize()
+    _equal(a, b)
