@@ -621,9 +621,10 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
         run.replay(200)
         run.synchronize()
         n_clock += 200
-    run.replay(warmup)
-    run.synchronize()
+    # exchange statistics over the warm-up and timed steps (read before, so that the timed
+    # launches follow the warm-up without a pause in which the clocks could drop)
     stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
+    run.replay(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run.replay(steps)
@@ -670,6 +671,7 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
                 "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
                 "sweep_site_updates_per_ns": round(upd_per_step / avg_launch_s / 1e9, 2)}
     return {"value": round(steps * upd_per_step / (elapsed * 1e9), 3),
+            "acceptance_over": "the %d warm-up and %d timed steps" % (warmup, steps),
             "ms_per_step": round(elapsed * 1e3 / steps, 5),
             "timing": {"timed": "%d replays of the captured cycle (hsg_plan_run), one graph launch per step"
                                 % steps,
@@ -677,7 +679,7 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
                                        % (n_clock, clock_warmup_s, warmup)},
             "roofline": roofline,
             "acceptance": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
-            "accepted_swaps_per_gpu_s": round(float(acc.sum()) / elapsed, 1)}
+            "accepted_swaps_per_gpu_s": round(float(acc.sum()) * steps / max(steps + warmup, 1) / elapsed, 1)}
 
 
 def main():
