@@ -81,7 +81,8 @@ def resident_kernel_name(w):
 
 # Sources of the sweep kernel whose HBM traffic the counter summary records; the
 # summary is used only while they and the compiler flags are unchanged.
-KERNEL_SOURCES = ["paper_1006_4247_amd/csrc/sweep_resident.hip", "paper_1006_4247_amd/csrc/hsg_device.h"]
+KERNEL_SOURCES = ["paper_1006_4247_amd/csrc/sweep_resident.hip", "paper_1006_4247_amd/csrc/resident_body.h",
+                  "paper_1006_4247_amd/csrc/hsg_device.h"]
 
 
 def kernel_sources_sha256():

@@ -124,7 +124,11 @@ typedef struct hsg_tuning {
                                replica per work item from a counter, the others in tiles
                                half-sweep by half-sweep behind a barrier of their own
                                part of the grid (they, and the first ensemble, need their
-                               scratch); spins as with the other paths, bit for bit */
+                               scratch); spins as with the other paths, bit for bit;
+                               6 LDS-resident lattice on persistent single-buffer
+                               workgroups, each sweeping a contiguous range of replicas
+                               with the next one's loads in flight (binary32, L = 16;
+                               spins and energies as with path 3, bit for bit) */
     int32_t block_threads;  /* threads per workgroup (path 5: workgroups of the tiled part,
                                a multiple of 8; 0 = by its share of the work) */
     int32_t replicas_per_block; /* streaming path: replicas sharing one coupling tile */

@@ -19,6 +19,7 @@ from .ensemble import Ensemble, geometric_betas
 CANDIDATES = (
     [{"path": 3, "block_threads": nt} for nt in (0, 256, 512)]
     + [{"path": 1, "block_threads": 0}]
+    + [{"path": 6, "block_threads": 0}]
     + [{"path": 4, "block_threads": 0}]
     + [{"path": 2, "block_threads": nt, "replicas_per_block": rb}
        for nt in (128, 256, 512) for rb in (1, 2, 4)]

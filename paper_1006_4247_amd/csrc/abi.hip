@@ -92,8 +92,9 @@ hsg_status check_all(const hsg_ensemble* ens, int n_ens, unsigned need) {
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 // 1: LDS-resident, persistent double-buffered; 3: LDS-resident, one workgroup per
-// replica; 2: streaming half-sweeps; 4: wavefront over z-planes; 0: 3 if a replica
-// fits in LDS, else 2 (measured faster than 4 at L = 20 .. 40).
+// replica; 2: streaming half-sweeps; 4: wavefront over z-planes; 6: LDS-resident,
+// persistent single-buffer; 0: 3 if a replica fits in LDS, else 2 (measured faster
+// than 4 at L = 20 .. 40).
 int sweep_path(const hsg_ensemble& e, const hsg_tuning* t) {
     const int path = t ? t->path : 0;
     if (path != 0) return path;
@@ -155,7 +156,7 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
     if (n_sweeps < 0 || n_hb < 0 || n_hb > 127 || n_or < 0 || n_hb + n_or < 1)
         return fail(HSG_ERR_INVALID, "need n_sweeps >= 0, 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1 (got %d, %d, %d)",
                     n_sweeps, n_hb, n_or);
-    if (tuning && (tuning->path < 0 || tuning->path > 5 || tuning->block_threads < 0 ||
+    if (tuning && (tuning->path < 0 || tuning->path > 6 || tuning->block_threads < 0 ||
                    tuning->replicas_per_block < 0 || (tuning->flags & ~HSG_TUNE_NO_RENORM) != 0))
         return fail(HSG_ERR_INVALID, "bad tuning values");
     hsg_status s = check_all(ens, n_ens, kState);
@@ -184,6 +185,9 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
             return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the LDS-resident path", i, ens[i].L);
         if (tuning && tuning->path == 4 && !hsg::wave_supported(ens[i]))
             return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: L = %d does not fit the wavefront path", i, ens[i].L);
+        if (tuning && tuning->path == 6 && !hsg::chain_supported(ens[i]))
+            return fail(HSG_ERR_UNSUPPORTED,
+                        "ensemble %d: the persistent single-buffer path takes binary32 at L = 16", i);
         if (!use_resident(ens[i], tuning)) {
             s = check_one(ens[i], i, kScratch);
             if (s != HSG_OK) return s;
@@ -199,6 +203,8 @@ hsg_status hsg_sweep_tuned(const hsg_ensemble* ens, int n_ens, int n_sweeps, int
             err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 2, 0, nt, as_stream(stream));
         } else if (path == 3) {
             err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 0, 0, nt, as_stream(stream));
+        } else if (path == 6) {
+            err = hsg::launch_resident(e, n_sweeps, n_hb, n_or, 3, 0, nt, as_stream(stream));
         } else if (path == 4) {
             if (nt != 0) return fail(HSG_ERR_UNSUPPORTED, "ensemble %d: the wavefront path takes no block_threads", i);
             err = hsg::launch_wave_sweeps(e, n_sweeps, n_hb, n_or, as_stream(stream));

@@ -37,9 +37,11 @@ bool resident_supported(const hsg_ensemble& e);
 // ... and twice that fits (the two replica buffers of the persistent
 // double-buffered workgroups).
 bool persistent_supported(const hsg_ensemble& e);
+// The persistent single-buffer workgroups (k_resident_chain): binary32, L = 16.
+bool chain_supported(const hsg_ensemble& e);
 // Regular sweeps, one workgroup per replica (anneal = 0), the annealing legs of
 // one parity (anneal = 1), or regular sweeps on persistent double-buffered
-// workgroups (anneal = 2).
+// workgroups (anneal = 2) or on persistent single-buffer ones (anneal = 3).
 hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
                            int parity, int block_threads, hipStream_t st);
 

@@ -20,15 +20,20 @@ struct Owned {
     T j[2][MQ][2][6];  // [parity][pair][half][direction] couplings of the owned sites
 };
 
-// Owned-site geometry.  Thread t owns the sites h = t + NT m + NQ half of each
-// sublattice (h = ih + (L/2)(j + L k), x = 2 ih + o, o = (p + j + k) & 1).  When
-// NT is a whole number of sublattice k-planes (L/2 * L sites), NT divides NQ and
-// the k-steps NT/(L/2 L) (between m) and L/2 (between halves) keep the parity of
-// k, all sites of a thread share (ih, j, o): their neighbours are those of the
-// first site shifted by the compile-time NT m + NQ half, except the z-neighbours
-// across the periodic boundary, which only the first site (-z) and the last site
-// (+z) can have.  Nine per-thread indices then address every neighbour and the
-// site offsets fold into the LDS instructions.
+// Owned-site geometry.  Thread t owns the sites h = q_m + NQ half of each
+// sublattice (h = ih + (L/2)(j + L k), x = 2 ih + o, o = (p + j + k) & 1), m < MQ;
+// q_m is also the site's Philox counter, shared by its two halves.  In general
+// q_m = t + NT m.  When NT is a whole number G of sublattice k-planes (L/2 * L
+// sites), NT divides NQ and the owned planes of a thread keep the parity of k,
+// all sites of a thread share (ih, j, o): their neighbours are those of the first
+// site shifted by compile-time offsets, except the z-neighbours across the
+// periodic boundary, which only the first site (-z) and the last site (+z) can
+// have.  Nine per-thread indices then address every neighbour and the site
+// offsets fold into the LDS instructions.  With G even and MQ >= 2 (z-pairs), a
+// thread owns the planes k0 + 2m of each half, k0 = (g & 1) + 2 MQ (g >> 1) for
+// the thread's plane group g = t / (L/2 * L): the +z neighbour of its site m is
+// the -z neighbour of its site m + 1, read once (MQ + 1 instead of 2 MQ z-reads
+// per half); otherwise the planes g + G m (G even, or MQ = 1).
 template <int L, int NT>
 struct SiteMap {
     static constexpr int HL = L / 2, N = L * L * L, NQ = N / 4, PLANE = HL * L;
@@ -36,19 +41,35 @@ struct SiteMap {
     static constexpr int STEPK = NT / PLANE;
     static constexpr bool invariant = (NT % PLANE == 0) && (NQ % NT == 0) &&
                                       (STEPK % 2 == 0 || MQ == 1) && ((L / 2) % 2 == 0);
+    static constexpr bool zpair = invariant && (STEPK % 2 == 0) && MQ >= 2;
+    static constexpr int STEPM = zpair ? 2 * PLANE : NT;  // site offset between m and m + 1
 };
+
+// Counter (site index within the first half) of owned site m of thread t.
+template <int L, int NT>
+__device__ __forceinline__ int owned_q(int t, int m) {
+    using M = SiteMap<L, NT>;
+    if constexpr (M::zpair) {
+        const int g = t / M::PLANE;
+        return t - g * M::PLANE + M::PLANE * ((g & 1) + 2 * M::MQ * (g >> 1)) + M::STEPM * m;
+    } else {
+        return t + NT * m;
+    }
+}
 
 struct FirstNbr {
     int x[2][2];  // [parity][+x, -x] of the first site
     int yp, ym;   // +y, -y of the first site (either parity)
     int zm_first, zp_last;
+    int q0;       // the first site
 };
 
 template <int L, int NT>
 __device__ __forceinline__ FirstNbr first_neighbours(int t) {
     using M = SiteMap<L, NT>;
     FirstNbr f;
-    const Nbr a = neighbours<L>(t, 0, L), b = neighbours<L>(t, 1, L);
+    const int q0 = M::invariant ? owned_q<L, NT>(t, 0) : t;
+    const Nbr a = neighbours<L>(q0, 0, L), b = neighbours<L>(q0, 1, L);
     f.x[0][0] = a.n[0];
     f.x[0][1] = a.n[1];
     f.x[1][0] = b.n[0];
@@ -56,7 +77,8 @@ __device__ __forceinline__ FirstNbr first_neighbours(int t) {
     f.yp = a.n[2];
     f.ym = a.n[3];
     f.zm_first = a.n[5];
-    f.zp_last = neighbours<L>(t + NT * (M::MQ - 1) + M::NQ, 0, L).n[4];
+    f.zp_last = neighbours<L>(q0 + M::STEPM * (M::MQ - 1) + M::NQ, 0, L).n[4];
+    f.q0 = q0;
     return f;
 }
 
@@ -75,13 +97,13 @@ __device__ __forceinline__ Nbr site_nbrs(const FirstNbr& fn, int p, int m, int h
     using M = SiteMap<L, NT>;
     Nbr nb;
     if constexpr (M::invariant) {
-        const int c = NT * m + M::NQ * half;
+        const int c = M::STEPM * m + M::NQ * half;
         nb.n[0] = fn.x[p][0] + c;
         nb.n[1] = fn.x[p][1] + c;
         nb.n[2] = fn.yp + c;
         nb.n[3] = fn.ym + c;
-        nb.n[4] = (m == MQ - 1 && half == 1) ? fn.zp_last : t + M::PLANE + c;
-        nb.n[5] = (m == 0 && half == 0) ? fn.zm_first : t - M::PLANE + c;
+        nb.n[4] = (m == MQ - 1 && half == 1) ? fn.zp_last : fn.q0 + M::PLANE + c;
+        nb.n[5] = (m == 0 && half == 0) ? fn.zm_first : fn.q0 - M::PLANE + c;
     } else {
         nb = neighbours<L>(h, p, L);
     }
@@ -101,7 +123,7 @@ __device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restric
         for (int m = 0; m < MQ; ++m)
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
-                const int q = t + NT * m;
+                const int q = SiteMap<L, NT>::invariant ? owned_q<L, NT>(t, m) : t + NT * m;
                 const int h = (q < NQ ? q : 0) + half * NQ;
                 const Nbr nb = site_nbrs<L, NT, MQ>(fn, p, m, half, h, t);
 #pragma unroll
@@ -126,10 +148,12 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
     T* __restrict__ w0 = sh + (0 * 2 + P) * NH;
     T* __restrict__ w1 = sh + (1 * 2 + P) * NH;
     T* __restrict__ w2 = sh + (2 * 2 + P) * NH;
+    constexpr bool ZP = SiteMap<L, NT>::zpair;
     const uint32_t c3 = heatbath_c3(hs);
+    T zc[2][3];  // z-pairs: the +z neighbour of site (m - 1, half), the -z one of (m, half)
 #pragma unroll
     for (int m = 0; m < MQ; ++m) {
-        int q = t + NT * m;
+        int q = INV ? fn.q0 + SiteMap<L, NT>::STEPM * m : t + NT * m;
         // Generic geometry: an opaque copy keeps the site arithmetic (neighbour
         // offsets, LDS addresses) inside each half-sweep instead of letting it be
         // hoisted and held live in registers across the whole kernel (empty asm,
@@ -143,13 +167,34 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
             const int h = q + half * NQ;
             const Nbr nb = site_nbrs<L, NT, MQ>(fn, P, m, half, h, t);
             T Sx = T(0), Sy = T(0), Sz = T(0);
+            T zm[3];  // the -z neighbour carried from site (m - 1, half)
+            if (ZP && m > 0) {
+                zm[0] = zc[half][0];
+                zm[1] = zc[half][1];
+                zm[2] = zc[half][2];
+            }
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
                 const int idx = nb.n[d];
                 const T jj = own.j[P][m][half][d];
-                Sx = fma(jj, o0[idx], Sx);
-                Sy = fma(jj, o1[idx], Sy);
-                Sz = fma(jj, o2[idx], Sz);
+                T vx, vy, vz;
+                if (ZP && d == 5 && m > 0) {
+                    vx = zm[0];
+                    vy = zm[1];
+                    vz = zm[2];
+                } else {
+                    vx = o0[idx];
+                    vy = o1[idx];
+                    vz = o2[idx];
+                }
+                if (ZP && d == 4) {
+                    zc[half][0] = vx;
+                    zc[half][1] = vy;
+                    zc[half][2] = vz;
+                }
+                Sx = fma(jj, vx, Sx);
+                Sy = fma(jj, vy, Sy);
+                Sz = fma(jj, vz, Sz);
             }
             T ox, oy, oz;
             if (hb) {

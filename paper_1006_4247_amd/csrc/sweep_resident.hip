@@ -10,6 +10,7 @@
 // into the last half-sweep of each sweep (every bond has one end in p).
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "hsg_device.h"
@@ -303,6 +304,115 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
+// Persistent variant with a replica buffer and a staging area, for regular sweeps
+// that open with a heat-bath half-sweep of parity 0 (which reads no parity-0 spin,
+// so only the three parity-1 planes of a replica are loaded): each workgroup takes a
+// contiguous range of slots, which share a sample (and its couplings, kept in
+// registers) whenever the range lies within one.  While a replica is swept, the next
+// one's parity-1 planes travel from HBM straight into the staging area (loads that
+// write the LDS without passing through registers); after the write-back they are
+// copied into the replica buffer.  48 KB + 24 KB of LDS let two 512-thread
+// workgroups share a CU, as with k_resident.  Every half-sweep is the one k_resident
+// takes, so spins are bit for bit the same; the energy is the same reduction.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT)
+    k_resident_chain(hsg_ensemble e, int n_sweeps, int n_hb, int n_or, int n_tasks) {
+    constexpr int N = L * L * L, NQ = N / 4;
+    constexpr int MQ = (NQ + NT - 1) / NT;
+    constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per replica
+    constexpr int NVP = NV / 6;                                    // per plane
+    constexpr int NL = NV / 2;                                     // loaded: the parity-1 planes
+    static_assert(NL % NT == 0 && NT % 64 == 0, "whole waves of staged vectors");
+    constexpr int PF = NL / NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ uint4 stage[NL];
+    uint4* buf = reinterpret_cast<uint4*>(smem_raw);
+    T* sh = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[(NT + 63) / 64];
+    __shared__ double s_H;
+
+    const int C = e.n_chains, R = e.n_temps;
+    const long long bid = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int t_begin = static_cast<int>(bid * n_tasks / gridDim.x);
+    const int t_end = static_cast<int>((bid + 1) * n_tasks / gridDim.x);
+    if (t_begin >= t_end) return;
+    const uint4* gsrc = static_cast<const uint4*>(e.spins);
+    uint4* gdst = static_cast<uint4*>(e.spins);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int nhalf = 2 * (n_hb + n_or);
+    const int t = static_cast<int>(threadIdx.x);
+    const int wave_base = t & ~63;
+
+    for (int v = t; v < NL; v += NT) {
+        const int o = loaded_vec<NVP>(v, true);
+        buf[o] = gsrc[static_cast<size_t>(t_begin) * NV + o];
+    }
+    int cur_sample = -1;
+    Owned<T, MQ> own;
+    const FirstNbr fn = first_neighbours<L, NT>(t);
+    for (int slot = t_begin; slot < t_end; ++slot) {
+        const int smp = slot / (C * R);
+        if (smp != cur_sample) {
+            const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
+            load_owned<T, L, NT, MQ>(own, J, fn, t);
+            cur_sample = smp;
+        }
+        const bool has_next = slot + 1 < t_end;
+        // read before the staged loads go out: a wait for a later load waits for them too
+        T beta = static_cast<T>(e.betas[label(e.temp_of_slot[slot], R, e.guard)]);
+        asm volatile("" : "+v"(beta));  // converted here (no instruction emitted)
+        const uint32_t g = e.slot_base + static_cast<uint32_t>(slot);
+        const uint32_t t0 = e.sweep_ctr[slot];
+        lds_barrier();  // this replica's parity-1 planes are in the buffer
+        if (has_next) {
+            // vector v = k NT + t of the staging area; a wave writes 64 consecutive ones
+            const uint4* nsrc = gsrc + static_cast<size_t>(slot + 1) * NV;
+#pragma unroll
+            for (int k = 0; k < PF; ++k)
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void*>(nsrc + loaded_vec<NVP>(k * NT + t, true)),
+                    (__attribute__((address_space(3))) void*)(stage + k * NT + wave_base), 16, 0, 0);
+        }
+
+        double acc = 0.0;
+        bool bad = false;
+        for (int k = 0; k < n_sweeps; ++k) {
+            const bool last = (k == n_sweeps - 1);
+            const uint32_t tsw = t0 + static_cast<uint32_t>(k);
+            for (int pos = 0; pos < nhalf; ++pos) {
+                const bool hb = pos < 2 * n_hb;
+                const bool want = last && pos == nhalf - 1;
+                if ((pos & 1) == 0)
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, false, pos, beta, tsw, g, k0, k1, want, acc, bad, t);
+                else
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, false, pos, beta, tsw, g, k0, k1, want, acc, bad, t);
+                lds_barrier();
+            }
+        }
+        double H;
+        {
+            const double tot = block_sum<NT, true>(acc, red);
+            if (t == 0) s_H = -tot;
+            lds_barrier();
+            H = s_H;
+        }
+        if (bad || !isfinite(H)) atomicOr(e.guard, 1);
+        // this wave's staged loads have landed (issued a replica ago; waited for here,
+        // before the write-back's stores join the same counter)
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // gfx9 encoding: vmcnt = 0, expcnt = 7, lgkmcnt = 15
+        for (int v = t; v < NV; v += NT) gdst[static_cast<size_t>(slot) * NV + v] = buf[v];
+        if (has_next) {
+            lds_barrier();  // every wave's staging is complete and this replica has been read
+#pragma unroll
+            for (int k = 0; k < PF; ++k) buf[loaded_vec<NVP>(k * NT + t, true)] = stage[k * NT + t];
+        }
+        if (t == 0) {
+            e.energy[slot] = H;
+            e.sweep_ctr[slot] = t0 + static_cast<uint32_t>(n_sweeps);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 static int default_threads(int L) {
     const int NQ = L * L * L / 4;
@@ -401,6 +511,30 @@ static hipError_t go_persist(const hsg_ensemble& e, int n_sweeps, int n_hb, int 
 
 template <typename T, int L, int NT>
 static hipError_t go(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
+                     int parity, hipStream_t st);
+
+// One persistent workgroup per resident slot of the CUs, each sweeping a contiguous
+// range of replicas (k_resident_chain); sweeps without a heat-bath half-sweep, which
+// read both parities, go to k_resident (the same results).
+template <typename T, int L, int NT>
+static hipError_t go_chain(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    if (n_hb == 0) return go<T, L, NT>(e, n_sweeps, n_hb, n_or, 0, 0, st);
+    constexpr int N = L * L * L;
+    const size_t lds = 3 * N * sizeof(T);
+    const int n_tasks = e.n_samples * e.n_chains * e.n_temps;
+    if (n_tasks <= 0 || n_sweeps <= 0) return hipSuccess;
+    auto kern = k_resident_chain<T, L, NT>;
+    int per_cu = 1;
+    hipError_t a = blocks_per_cu_query(reinterpret_cast<const void*>(kern), NT, lds, &per_cu);
+    if (a != hipSuccess) return a;
+    int grid = num_cus() * per_cu;
+    if (grid > n_tasks) grid = n_tasks;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or, n_tasks);
+    return hipGetLastError();
+}
+
+template <typename T, int L, int NT>
+static hipError_t go(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, int anneal,
                      int parity, hipStream_t st) {
     constexpr int N = L * L * L;
     const size_t lds = 3 * N * sizeof(T);
@@ -427,6 +561,12 @@ static hipError_t go_nt(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
     constexpr int DEF = ((NQ + 63) / 64) * 64 > 1024 ? 1024 : ((NQ + 63) / 64) * 64;
     if (anneal == 2) {  // regular sweeps, persistent double-buffered workgroups
         if (nt == 0 || nt == DEF) return go_persist<T, L, DEF>(e, n_sweeps, n_hb, n_or, st);
+        return hipErrorInvalidValue;
+    }
+    if (anneal == 3) {  // regular sweeps, persistent single-buffer workgroups
+        if constexpr (std::is_same<T, float>::value && L == 16) {
+            if (nt == 0 || nt == 512) return go_chain<T, L, 512>(e, n_sweeps, n_hb, n_or, st);
+        }
         return hipErrorInvalidValue;
     }
     // default: one 512-thread workgroup per replica where a replica has >= 1024 site
@@ -521,6 +661,10 @@ bool resident_pair_supported(const hsg_ensemble& e) {
     if (e.L > pair_max_L(e.precision == HSG_FP64)) return false;
     const size_t N = static_cast<size_t>(e.L) * e.L * e.L;
     return 2 * 3 * N * (e.precision == HSG_FP64 ? 8 : 4) <= max_block_lds();
+}
+
+bool chain_supported(const hsg_ensemble& e) {
+    return resident_supported(e) && e.precision == HSG_FP32 && e.L == 16;
 }
 
 hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {

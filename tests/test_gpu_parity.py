@@ -349,3 +349,48 @@ def test_guard_trips_on_nan_and_reports():
     with pytest.raises(hsg.HsgError) as ei:
         gpu.check()
     assert ei.value.code == 3
+
+
+@pytest.mark.parametrize("S,C,R", [(64, 2, 24), (13, 2, 23), (3, 1, 3)])
+@pytest.mark.parametrize("n_sweeps,n_hb,n_or", [(1, 1, 3), (3, 1, 3), (1, 2, 0), (2, 0, 2)])
+def test_persistent_single_buffer_equals_one_workgroup_per_replica(S, C, R, n_sweeps, n_hb, n_or):
+    """Tuning path 6 (persistent single-buffer workgroups at binary32 L = 16, each
+    sweeping a contiguous range of replicas that may cross sample boundaries, the next
+    replica staged into LDS meanwhile) against path 3 (one workgroup per replica): spins,
+    energies and counters bit for bit, including shapes whose replica count is not a
+    multiple of the grid; sweeps without a heat-bath half-sweep take path 3's kernel."""
+    L = 16
+    betas = hsgref.geometric_betas(1.0, 8.0, R)
+    a = hsg.Ensemble(L, S, C, betas, SEED + 7, precision="fp32")
+    b = hsg.Ensemble(L, S, C, betas, SEED + 7, precision="fp32")
+    for e in (a, b):
+        e.init_couplings()
+        e.init_spins()
+        e.sweep(1, 1, 3)
+        e.swap(0)
+    a.sweep(n_sweeps, n_hb, n_or, tuning={"path": 6})
+    b.sweep(n_sweeps, n_hb, n_or, tuning={"path": 3})
+    torch.cuda.synchronize()
+    sa, sb = a.host_state(), b.host_state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    a.check()
+
+
+@pytest.mark.parametrize("kind", ["hb", "hb+3or", "hb+1or"])
+def test_sweep_parity_persistent_single_buffer(kind):
+    """Path 6 against the oracle on sampled replicas (first, last and random ones) of a
+    shape whose workgroups sweep several replicas across sample boundaries."""
+    L, S, C, R = 16, 13, 2, 23
+    n_hb, n_or = KINDS[kind]
+    gpu = hsg.Ensemble(L, S, C, hsgref.geometric_betas(1.0, 8.0, R), SEED + 8, precision="fp32")
+    gpu.init_couplings()
+    gpu.init_spins()
+    gpu.sweep(2, 1, 3)
+    gpu.swap(0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(21)
+    picks = [(0, 0, 0), (S - 1, C - 1, R - 1)] + [tuple(int(v) for v in rng.integers((S, C, R))) for _ in range(4)]
+    what = "L=16 13x2x23 fp32 %s path 6" % kind
+    _report(sweep_and_check(gpu, n_hb, n_or, tuning={"path": 6}, slots=picks, what=what), what)
+    gpu.check()
