@@ -383,203 +383,6 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 && NT <= 256 ? 3 : 1) k_dec
     }
 }
 
-// ---------------------------------------------------------------- pipelined ascending pass
-// All pairs of a binary32 chain in ascending order, one workgroup per chain, as
-// k_decimate_res with pairing 0 (same site arithmetic, sums and random numbers: the
-// same results bit for bit), with the next pair's data fetched while the current
-// pair is worked on.  Pair i + 1 keeps the sublattice D_i that pair i decimates
-// (the roles alternate), of the configurations then at beta_{i+1} and beta_{i+2}:
-//   beta_{i+2}: untouched by pair i, loaded during pair i;
-//   beta_{i+1}: if pair i is rejected, its own configuration y, whose D_i spins pair i
-//     leaves alone (loaded during pair i as well); if accepted, x, whose D_i spins pair
-//     i has just redrawn (written to LDS as they are drawn).
-// Two LDS buffers of the two kept sublattices alternate between the pairs, and the
-// decision uniforms of every pair are drawn in parallel at the start.
-constexpr int kAscMaxPairs = 256;
-constexpr int kAscThreads = 1024;
-
-template <int L, int NT>
-__global__ void __launch_bounds__(NT) k_decimate_asc(hsg_ensemble e) {
-    using T = float;
-    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
-    constexpr int NVP = NH * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per plane
-    constexpr int PV = (3 * NVP + NT - 1) / NT;                  // per thread and configuration
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* bufs = reinterpret_cast<T*>(smem_raw);  // [2 buffers][2 configurations][3][NH]
-    __shared__ double red[NT / 64];
-    __shared__ double s_logu[kAscMaxPairs];
-    __shared__ int s_acc;
-    const int R = e.n_temps, C = e.n_chains;
-    const int ch = blockIdx.x;
-    const int smp = ch / C;
-    const T* __restrict__ J = static_cast<const T*>(e.couplings) + static_cast<size_t>(smp) * 3 * N;
-    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
-    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
-    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
-    const uint32_t n = e.swap_ctr[ch];
-    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
-    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
-    const int d0 = static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u);
-    for (int i = threadIdx.x; i < R - 1; i += NT) {
-        const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, k0, k1);
-        s_logu[i] = log(u01_52(w.w0, w.w1));
-    }
-
-    // the kept sublattice (parity 1 - d) of configurations x and y into buffer b
-    auto stage = [&](int b, int x, int y, int d) {
-        const uint4* srcx = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) +
-                                                           (static_cast<size_t>(ch) * R + x) * 3 * N);
-        const uint4* srcy = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) +
-                                                           (static_cast<size_t>(ch) * R + y) * 3 * N);
-        uint4* dst = reinterpret_cast<uint4*>(bufs + b * 6 * NH);
-        for (int v = threadIdx.x; v < 3 * NVP; v += NT) {
-            const int mu = v / NVP, r = v - mu * NVP;
-            const int src = (2 * mu + 1 - d) * NVP + r;
-            dst[v] = srcx[src];
-            dst[3 * NVP + v] = srcy[src];
-        }
-    };
-    int x = label(sot[0], R, e.guard), y = label(sot[1], R, e.guard);
-    stage(0, x, y, d0 & 1);
-    __syncthreads();
-
-    for (int i = 0; i < R - 1; ++i) {
-        const int d = (d0 + i) & 1;
-        const T* kept = bufs + (i & 1) * 6 * NH;
-        T* nxt = bufs + ((i + 1) & 1) * 6 * NH;
-        const bool has_next = i + 1 < R - 1;
-        const int y2 = has_next ? label(sot[i + 2], R, e.guard) : 0;
-        const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
-        T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
-        T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
-        // the next pair's sublattice d of y (used if this pair is rejected) and of the
-        // configuration at beta_{i+2}, in flight while this pair is worked on
-        uint4 py[PV], pz[PV];
-        if (has_next) {
-            const uint4* srcy = reinterpret_cast<const uint4*>(sy);
-            const uint4* srcz = reinterpret_cast<const uint4*>(static_cast<const T*>(e.spins) +
-                                                               (static_cast<size_t>(ch) * R + y2) * 3 * N);
-#pragma unroll
-            for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
-                if (v < 3 * NVP) {
-                    const int mu = v / NVP, r = v - mu * NVP;
-                    const int src = (2 * mu + d) * NVP + r;
-                    py[k] = srcy[src];
-                    pz[k] = srcz[src];
-                }
-            }
-        }
-        const double b1 = e.betas[i], b2 = e.betas[i + 1];
-        const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
-        const float fr0 = static_cast<float>(b2 / b1);
-        double lin = 0.0, lg = 0.0;
-        for (int h = threadIdx.x; h < NH; h += NT) {
-            const Nbr nb = neighbours<L>(h, d, L);
-            T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
-#pragma unroll
-            for (int dd = 0; dd < 6; ++dd) {
-                const int mu = dd >> 1;
-                const T jj = (dd & 1) ? J[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : J[(mu * 2 + d) * NH + h];
-                const int idx = nb.n[dd];
-                ax = fma(jj, kept[0 * NH + idx], ax);
-                ay = fma(jj, kept[1 * NH + idx], ay);
-                az = fma(jj, kept[2 * NH + idx], az);
-                cx = fma(jj, kept[3 * NH + idx], cx);
-                cy = fma(jj, kept[4 * NH + idx], cy);
-                cz = fma(jj, kept[5 * NH + idx], cz);
-            }
-            const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
-            lin += a - c;
-            lg += static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0));
-        }
-        const double lnA = block_sum<NT>(fma(b2 - b1, lin, lg), red);
-        if (threadIdx.x == 0) {
-            if (e.work) {
-                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
-                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = static_cast<double>(d);
-            }
-            if (!isfinite(lnA)) atomicOr(e.guard, 1);
-            const bool ok = s_logu[i] < lnA;
-            st[2 * i] += 1;
-            if (ok) {
-                sot[i] = y;
-                sot[i + 1] = x;
-                tos[x] = i + 1;
-                tos[y] = i;
-                st[2 * i + 1] += 1;
-            }
-            s_acc = ok ? 1 : 0;
-        }
-        __syncthreads();
-        const bool acc = s_acc != 0;
-        if (has_next) {  // the prefetched spins into the next buffer (y's only if rejected)
-            uint4* dst = reinterpret_cast<uint4*>(nxt);
-#pragma unroll
-            for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
-                if (v < 3 * NVP) {
-                    if (!acc) dst[v] = py[k];
-                    dst[3 * NVP + v] = pz[k];
-                }
-            }
-        }
-        if (acc) {
-            const uint32_t c3 = (kTagDecimate << 24) | (static_cast<uint32_t>(i) & 0xFFFFu);
-            const T tb[2] = {static_cast<T>(b2), static_cast<T>(b1)};  // x -> beta_2, y -> beta_1
-            T* out[2] = {sx, sy};
-            const uint32_t gs[2] = {e.slot_base + static_cast<uint32_t>(gx), e.slot_base + static_cast<uint32_t>(gy)};
-            double en[2] = {0.0, 0.0};
-            for (int q = threadIdx.x; q < NQ; q += NT) {
-#pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    const Words w = philox(static_cast<uint32_t>(q), n, gs[r], c3, k0, k1);
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const int h = q + half * NQ;
-                        const Nbr nb = neighbours<L>(h, d, L);
-                        T Sx = T(0), Sy = T(0), Sz = T(0);
-#pragma unroll
-                        for (int dd = 0; dd < 6; ++dd) {
-                            const int mu = dd >> 1;
-                            const T jj = (dd & 1) ? J[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : J[(mu * 2 + d) * NH + h];
-                            const int idx = nb.n[dd];
-                            Sx = fma(jj, kept[(3 * r + 0) * NH + idx], Sx);
-                            Sy = fma(jj, kept[(3 * r + 1) * NH + idx], Sy);
-                            Sz = fma(jj, kept[(3 * r + 2) * NH + idx], Sz);
-                        }
-                        const T r1 = static_cast<T>(u01_23(half ? w.w2 : w.w0));
-                        const T r2 = static_cast<T>(u01_23(half ? w.w3 : w.w1));
-                        T ox, oy, oz;
-                        heatbath<T>(Sx, Sy, Sz, tb[r], r1, r2, ox, oy, oz);
-                        out[r][(0 * 2 + d) * NH + h] = ox;
-                        out[r][(1 * 2 + d) * NH + h] = oy;
-                        out[r][(2 * 2 + d) * NH + h] = oz;
-                        if (r == 0 && has_next) {  // x, now at beta_{i+1}: the next pair's kept spins
-                            nxt[0 * NH + h] = ox;
-                            nxt[1 * NH + h] = oy;
-                            nxt[2 * NH + h] = oz;
-                        }
-                        const double dx = ox, dy = oy, dz = oz;
-                        en[r] += fma(dz, static_cast<double>(Sz),
-                                     fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
-                    }
-                }
-            }
-            const double Hx = -block_sum<NT>(en[0], red);
-            const double Hy = -block_sum<NT>(en[1], red);
-            if (threadIdx.x == 0) {
-                e.energy[gx] = Hx;
-                e.energy[gy] = Hy;
-                if (!isfinite(Hx) || !isfinite(Hy)) atomicOr(e.guard, 1);
-            }
-        }
-        x = acc ? x : y;  // the configuration now at beta_{i+1}
-        y = y2;
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- split ascending pass
 // With few chains, one workgroup per chain (k_decimate) leaves most CUs idle through
 // the R - 1 sequential pairs.  Here pair i of every chain is spread over G workgroups,
@@ -799,16 +602,6 @@ static hipError_t go_decimate_nt(const hsg_ensemble& e, int pairing, int blocks,
 
 template <typename T, int L>
 static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
-    if constexpr (sizeof(T) == 4) {
-        if (pairing == 0 && e.n_temps - 1 <= kAscMaxPairs) {  // pipelined ascending pass
-            constexpr size_t lds = 2 * 2 * 3 * (L * L * L / 2) * sizeof(T);
-            auto kern = k_decimate_asc<L, kAscThreads>;
-            const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
-            if (a != hipSuccess) return a;
-            hipLaunchKernelGGL(kern, dim3(blocks), dim3(kAscThreads), lds, st, e);
-            return hipGetLastError();
-        }
-    }
     // binary64 site terms need more than the 128 registers of a 1024-thread workgroup
     if (pairing == 0 && sizeof(T) == 4) return go_decimate_nt<T, L, 1024>(e, pairing, blocks, st);
     return go_decimate_nt<T, L, kDecThreads>(e, pairing, blocks, st);
