@@ -210,13 +210,16 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
         e.init_spins()
         return e
 
-    def timed(e, mode, steps, eps=0.0):
-        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode, eps=eps)
+    def timed(e, mode, steps, eps=0.0, **kw):
+        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode=mode, eps=eps, **kw)
         run.step(max(300, steps // 10))  # equilibration, also of the round-trip state
-        run.capture()
         run.synchronize()
+        # read before the capture: host reads between warm and timed replays slow the
+        # replays that follow
         st0 = e.swap_stats.cpu().numpy().copy()
         rt0 = e.rt_trips.cpu().numpy().copy()
+        run.capture()
+        run.synchronize()
         t0 = time.perf_counter()
         run.replay(max(1, steps // run.graph_steps))
         run.synchronize()
@@ -243,20 +246,41 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     r = timed(e, "anneal", steps_anneal)
     r["K"] = K_uni
     out["annealed_uniform_K"] = r
+    # the learned schedule: legs of 1 HB + 1 OR lattice sweeps per annealing step, per-pair
+    # protocols chosen to minimise the predicted GPU time per round trip from the step's
+    # and one annealing sweep's measured cost
     e = make(R0)
     t0 = time.perf_counter()
     rng = np.random.default_rng(1)
-    K_grid = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    K_grid = [0, 1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    leg = (1, 1)
     e.sweep(100, w["n_hb"], w["n_or"])
-    x, y, wt = sch.generate_data(e, 120, K_grid, rng, n_hb=w["n_hb"], n_or=w["n_or"])
+
+    def step_ms(K):
+        e.set_schedule(np.full(R0 - 1, K, np.int32))
+        run = runtime.PTRun([e], w["n_hb"], w["n_or"], mode="anneal", anneal_sweep=leg)
+        run.capture()
+        run.replay(10)
+        run.synchronize()
+        t1 = time.perf_counter()
+        run.replay(100)
+        run.synchronize()
+        dt = (time.perf_counter() - t1) / 100 * 1e3
+        run.release()
+        return dt
+
+    t_base = step_ms(0)
+    t_leg = (step_ms(4) - t_base) / (4 * (R0 - 1) / 2.0)
+    x, y, wt = sch.generate_data(e, 120, K_grid, rng, n_hb=w["n_hb"], n_or=w["n_or"], leg=leg)
     net, loss = sch.train(x, y, wt, steps=3000)
     _, _, et = e.measure()
     ebar = et.mean(dim=(0, 1)).cpu().numpy()
-    K, G, pred = sch.select_schedule(net, e.betas_host, ebar, L, K_grid)
+    K, G, pred = sch.select_schedule_round_trips(net, e.betas_host, ebar, L, K_grid, t_base, t_leg)
     learn_s = time.perf_counter() - t0
     e.set_schedule(K, sch.protocol(e.betas_host, K, G, e.K_max))
-    r = timed(e, "anneal", steps_anneal)
-    r.update({"K": [int(k) for k in K], "learner_s": round(learn_s, 2), "train_mse": round(loss, 5)})
+    r = timed(e, "anneal", steps_anneal, anneal_sweep=leg)
+    r.update({"K": [int(k) for k in K], "leg_sweep": "1 HB + 1 OR", "t_base_ms": round(t_base, 4),
+              "t_leg_ms": round(t_leg, 5), "learner_s": round(learn_s, 2), "train_mse": round(loss, 5)})
     out["annealed_learned"] = r
     # decimated exchange (paper Sec. III.A), even / odd pairs alternating
     out["decimated_dense_ladder"] = timed(make(R_dense), "decimate", steps_plain)
@@ -290,6 +314,100 @@ def exchange_comparison(torch, hsg, w, steps_plain, steps_anneal, seed=0x5EED):
     # paper-ladder study (--paper-ladder L).
     out["round_trips_note"] = ("transient counts: each run is short against the round-trip time of its "
                                "ladder; steady-state round-trip speed-ups are in the paper-ladder study")
+    return out
+
+
+def learned_workload_study(torch, hsg, steps=200, seed=0x100642470005):
+    """The learned schedule at its own workload: L = 32, 16 samples x 2 chains x 10
+    temperatures, beta geometric 1..8 (plain exchange accepts ~0 on this ladder), FP32.
+    The network is trained on annealed exchanges of random protocols (K in 0..32, path
+    shapes gamma) generated on this ensemble with the project's kernels; the schedule
+    minimises the predicted GPU time per round trip from the measured cost of a step and
+    of one annealing sweep of one pair.  Against the fallback (linear protocol, the same
+    K for every pair, K = 4 and K = 32): acceptance per pair, GPU time per step, accepted
+    exchanges per GPU-second and the round-trip cost (sum_i 1/acc_i) x (ms per step)
+    from the measured values."""
+    from paper_1006_4247_amd import runtime
+    from paper_1006_4247_amd import schedule as sch
+
+    L, S, C, R = 32, 16, 2, 10
+    betas = hsg.geometric_betas(1.0, 8.0, R)
+    K_grid = [0, 1, 2, 4, 8, 16, 32]
+    K_long = 256  # beyond the schedule's range: where acceptance appears on this ladder
+    leg = (1, 1)
+
+    def make(K_max):
+        # the streaming annealing legs launch 2 K_max (n_hb + n_or) half-sweeps (pairs with
+        # shorter protocols idle in the later ones), so K_max is kept to what a run uses
+        x = hsg.Ensemble(L, S, C, betas, seed, precision="fp32", K_max=K_max)
+        x.init_couplings()
+        x.init_spins()
+        x.sweep(100, 1, 3)
+        return x
+
+    e = make(max(K_grid))
+
+    def run_ms(K, lam, n):
+        e.set_schedule(K, lam)
+        # statistics read before the capture (host reads between warm and timed replays
+        # slow the replays that follow); they then cover the 4 warm replays too
+        st0 = e.swap_stats.cpu().numpy().copy()
+        run = runtime.PTRun([e], 1, 3, mode="anneal", anneal_sweep=leg)
+        run.capture()
+        run.replay(4)
+        run.synchronize()
+        t0 = time.perf_counter()
+        run.replay(n)
+        run.synchronize()
+        dt = time.perf_counter() - t0
+        run.release()
+        st = e.swap_stats.cpu().numpy() - st0
+        acc = st[..., 1].sum(axis=(0, 1)) / np.maximum(st[..., 0].sum(axis=(0, 1)), 1)
+        return dt / n * 1e3, acc, float(st[..., 1].sum()) * n / (n + 4) / dt
+
+    t0 = time.perf_counter()
+    zero = np.zeros(R - 1, np.int32)
+    t_base = run_ms(zero, None, 20)[0]
+    t_leg = (run_ms(np.full(R - 1, 8, np.int32), None, 20)[0] - t_base) / (8 * (R - 1) / 2.0)
+    rng = np.random.default_rng(5)
+    x, y, wt = sch.generate_data(e, 40, K_grid, rng, n_hb=1, n_or=3, leg=leg)
+    net, loss = sch.train(x, y, wt, steps=3000)
+    _, _, et = e.measure()
+    ebar = et.mean(dim=(0, 1)).cpu().numpy()
+    K, G, pred = sch.select_schedule_round_trips(net, betas, ebar, L, K_grid, t_base, t_leg)
+    learn_s = time.perf_counter() - t0
+    out = {"study": "learned-schedule", "L": L, "samples": S, "chains": C, "temperatures": R, "beta": [1.0, 8.0],
+           "sweep": "1 HB + 3 OR", "leg_sweep": "1 HB + 1 OR", "steps": steps,
+           "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % seed,
+           "t_base_ms": round(t_base, 4), "t_leg_ms": round(t_leg, 5), "train_mse": round(loss, 5),
+           "learner_s": round(learn_s, 2)}
+
+    def entry(K, Gm, n=steps):
+        ms, acc, aps = run_ms(K, sch.protocol(betas, K, Gm, e.K_max), n)
+        return {"K": [int(k) for k in K], "ms_per_step": round(ms, 4),
+                "acceptance": [round(float(a), 4) for a in acc], "acceptance_min": round(float(acc.min()), 4),
+                "accepted_swaps_per_gpu_s": round(aps, 1),
+                "round_trip_cost_ms": round(float(np.sum(1.0 / np.maximum(acc, 1e-3)) * ms), 2)}
+
+    out["learned"] = dict(entry(K, G), gamma=[float(g) for g in G],
+                          predicted_acceptance=[round(float(a), 4) for a in pred])
+    for kf in (4, 32):
+        out["fixed_linear_K%d" % kf] = entry(*sch.fixed_schedule(R, kf))
+    e.check()
+    e = make(K_long)
+    out["fixed_linear_K%d" % K_long] = entry(*sch.fixed_schedule(R, K_long), n=max(20, steps // 4))
+    e.check()
+    if max(out[k]["acceptance_min"] for k in ("learned", "fixed_linear_K4", "fixed_linear_K32")) == 0.0:
+        # no protocol in the schedule's range is ever accepted on this ladder: every cost
+        # is set by the acceptance floor, and a speed-up would be an artefact of it
+        out["note"] = ("no exchange accepted at K <= 32 on this ladder (every pair of every protocol in the "
+                       "schedule's range); the learner then keeps the cheapest protocol; see the K = %d row "
+                       "for the protocol length at which acceptance appears" % K_long)
+    else:
+        for kf in (4, 32):
+            f = out["fixed_linear_K%d" % kf]
+            out["learned_round_trip_speedup_vs_K%d" % kf] = round(f["round_trip_cost_ms"] /
+                                                                 max(out["learned"]["round_trip_cost_ms"], 1e-9), 3)
     return out
 
 
@@ -524,7 +642,7 @@ def uneven_study(torch, hsg, steps, warm=20):
         for e, t in zip(ens, run.tunings):
             N, slots = e.N, e.n_slots
             path = (t or {}).get("path", 0) or (3 if e.L <= 16 else 2)
-            if path in (1, 3):  # one launch per sweep
+            if path in (1, 3, 6):  # one launch per sweep
                 b = slots * (3 * (N // 2) * 4 + 3 * N * 4) + e.S * 3 * N * 4
             elif path == 4:  # one pass per lattice sweep: read all, write all
                 b = 4 * (slots * 2 * 3 * N * 4 + e.S * 3 * N * 4)
@@ -615,6 +733,11 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
     run = runtime.PTRun([ens], w["n_hb"], w["n_or"], mode="plain", pairing=0)
     run.capture()
     stream = torch.cuda.current_stream(dev)
+    # exchange statistics over every replay of the cycle, read before the first one: a
+    # PyTorch kernel and device-to-host copy on this stream between the clock warm-up
+    # and the timed replays slowed the replays that followed by about 8 % for tens of
+    # steps (measured: 0.168 against 0.155 ms per step)
+    stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
     # steady clocks: replay until clock_warmup_s has passed (not counted)
     t_w = time.perf_counter()
     n_clock = 0
@@ -622,16 +745,17 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
         run.replay(200)
         run.synchronize()
         n_clock += 200
-    # exchange statistics over the warm-up and timed steps (read before, so that the timed
-    # launches follow the warm-up without a pause in which the clocks could drop)
-    stats0 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
     run.replay(warmup)
     torch.cuda.synchronize()
+    evs = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     t0 = time.perf_counter()
+    evs[0].record(stream)  # replays go to this stream
     run.replay(steps)
+    evs[1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    device_ms = evs[0].elapsed_time(evs[1])
     run.check()
     stats1 = ens.swap_stats.sum(dim=(0, 1)).cpu().numpy()
     acc = (stats1[:, 1] - stats0[:, 1]).astype(np.float64)
@@ -672,15 +796,16 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
                 "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
                 "sweep_site_updates_per_ns": round(upd_per_step / avg_launch_s / 1e9, 2)}
     return {"value": round(steps * upd_per_step / (elapsed * 1e9), 3),
-            "acceptance_over": "the %d warm-up and %d timed steps" % (warmup, steps),
+            "acceptance_over": "the %d clock warm-up, %d warm-up and %d timed steps" % (n_clock, warmup, steps),
             "ms_per_step": round(elapsed * 1e3 / steps, 5),
             "timing": {"timed": "%d replays of the captured cycle (hsg_plan_run), one graph launch per step"
                                 % steps,
+                       "device_ms_per_step": round(device_ms / max(steps, 1), 5),
                        "clock_warmup": "%d untimed replays (%.2f s) before the %d warm-up steps"
                                        % (n_clock, clock_warmup_s, warmup)},
             "roofline": roofline,
             "acceptance": [round(a / max(t, 1), 4) for a, t in zip(acc, att)],
-            "accepted_swaps_per_gpu_s": round(float(acc.sum()) * steps / max(steps + warmup, 1) / elapsed, 1)}
+            "accepted_swaps_per_gpu_s": round(float(acc.sum()) * steps / max(n_clock + steps + warmup, 1) / elapsed, 1)}
 
 
 def main():
@@ -773,6 +898,8 @@ def main():
                                        "kernel": h64["roofline"]["kernel"], "steps": max(args.steps, 200)}
         phase("uneven batch (five size classes, beyond the MALL)")
         line["uneven_batch"] = uneven_study(torch, hsg, args.uneven_steps)
+        phase("learned schedule at L=32 (16 x 2 x 10)")
+        line["learned_schedule_L32"] = learned_workload_study(torch, hsg)
         phase("paper-ladder study L=16 (round trips per GPU-second)")
         line["paper_ladder_L16"] = paper_ladder_study(torch, hsg, 16, args.study_sets_default,
                                                       args.study_cycles_default[1], args.study_cycles_default[0],
