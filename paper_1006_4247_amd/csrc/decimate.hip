@@ -17,6 +17,8 @@
 // disjoint: one workgroup per pair.  Fields and ln A terms are per site, ln A and
 // the energies are deterministic FP64 block sums; one lane decides.
 #include "hsg_device.h"
+#include <type_traits>
+
 #include "hsg_launch.h"
 
 namespace hsg {
@@ -383,6 +385,225 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 && NT <= 256 ? 3 : 1) k_dec
     }
 }
 
+// ---------------------------------------------------------------- staged ascending pass
+// Binary32 ascending pass (one 1024-thread workgroup per chain) with every load of the
+// pair loop taken off its critical path.  The chain's couplings sit in LDS for the
+// whole pass (48 KB at L = 16), beside four buffers of one sublattice's three planes
+// (24 KB each): the current pair's kept planes of its lower and upper configuration,
+// and two staging buffers.  Pair i keeps sublattice 1 - d and pair i + 1 keeps d, so
+// when pair i starts, the planes of sublattice d that pair i + 1 will keep are
+// requested straight from HBM into LDS (loads that bypass the registers): those of the
+// configuration at beta_{i+2} (pair i cannot touch it) into one staging buffer, those
+// of the configuration at beta_{i+1} (pair i's upper one, the lower one of pair i + 1
+// if pair i is rejected) into the other.  If pair i is accepted, its lower configuration
+// moves to beta_{i+1} and its sublattice d is drawn anew: the new spins are written over
+// that second buffer as well as to HBM, so either way the next pair's lower planes are
+// in it.  The decision uniforms of all pairs, which do not depend on the states, are
+// drawn up front.  Labels live in LDS too; barriers are LDS-only, so the staged loads
+// stay in flight across them until the wait before the re-insertion.  Site
+// arithmetic, its order and the reductions are k_decimate_res's, so results are the
+// same bit for bit.
+constexpr int kPfThreads = 1024;
+constexpr int kPfMaxPairs = 256;
+
+template <int L>
+__global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
+    using T = float;
+    constexpr int NT = kPfThreads;
+    constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
+    constexpr int NVP = NH * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per plane
+    constexpr int NVB = 3 * NVP;                                 // per buffer
+    static_assert(NVB % 64 == 0, "whole waves of staged vectors");
+    static_assert(NQ <= NT && NH <= 2 * NT, "one re-insertion site pair and two terms per thread at most");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Js = reinterpret_cast<T*>(smem_raw);  // [3][2][NH]
+    T* pool = Js + 3 * N;                    // [4][3][NH]
+    __shared__ double red[NT / 64];
+    __shared__ double s_logu[kPfMaxPairs];
+    __shared__ double s_beta[kPfMaxPairs + 1];
+    __shared__ long long s_st[2 * kPfMaxPairs];
+    __shared__ int s_sot[kPfMaxPairs + 1];
+    __shared__ int s_acc;
+    const int R = e.n_temps, C = e.n_chains;
+    const int ch = blockIdx.x;
+    const int t = static_cast<int>(threadIdx.x);
+    const int wave_base = t & ~63;
+    const int smp = ch / C;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    const uint32_t k0 = key_lo(e.seed), k1 = key_hi(e.seed);
+    const int d0 = static_cast<int>(philox(0u, n, cg, kTagDecimateRole << 24, k0, k1).w0 & 1u);
+    const uint4* gsp = static_cast<const uint4*>(e.spins);
+
+    for (int i = t; i < R - 1; i += NT) {
+        const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, k0, k1);
+        s_logu[i] = log(u01_52(w.w0, w.w1));
+    }
+    for (int i = t; i < R; i += NT) {
+        s_sot[i] = label(sot[i], R, e.guard);
+        s_beta[i] = e.betas[i];
+    }
+    for (int i = t; i < 2 * (R - 1); i += NT) s_st[i] = st[i];
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(static_cast<const T*>(e.couplings) +
+                                                          static_cast<size_t>(smp) * 3 * N);
+        uint4* dst = reinterpret_cast<uint4*>(Js);
+        for (int v = t; v < 6 * NVP; v += NT) dst[v] = src[v];
+    }
+    __syncthreads();
+    auto buf = [&](int b) { return pool + static_cast<size_t>(b) * 3 * NH; };
+    // planes of sublattice p of the chain's configuration in slot `slot` -> buffer b
+    auto stage_now = [&](int b, int slot, int p) {
+        const uint4* src = gsp + (static_cast<size_t>(ch) * R + slot) * 3 * N / 4;
+        uint4* dst = reinterpret_cast<uint4*>(buf(b));
+        for (int v = t; v < NVB; v += NT) {
+            const int mu = v / NVP, r = v - mu * NVP;
+            dst[v] = src[(2 * mu + p) * NVP + r];
+        }
+    };
+    auto stage_ahead = [&](int b, int slot, int p) {
+        const uint4* src = gsp + (static_cast<size_t>(ch) * R + slot) * 3 * N / 4;
+        uint4* dst = reinterpret_cast<uint4*>(buf(b));
+#pragma unroll
+        for (int k = 0; k < (NVB + NT - 1) / NT; ++k) {
+            const int v0 = k * NT + wave_base;  // this wave's first vector (64 consecutive)
+            if (v0 < NVB) {
+                const int v = v0 + (t & 63);
+                const int mu = v / NVP, r = v - mu * NVP;
+                __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + (2 * mu + p) * NVP + r),
+                                                 (__attribute__((address_space(3))) void*)(dst + v0), 16, 0, 0);
+            }
+        }
+    };
+    int bl = 0, bu = 1, bp = 2, bn = 3;  // lower, upper, staging for the next lower / upper
+    stage_now(bl, s_sot[0], 1 - (d0 & 1));
+    stage_now(bu, s_sot[1], 1 - (d0 & 1));
+    __syncthreads();
+
+    for (int i = 0; i < R - 1; ++i) {
+        const int d = (d0 + i) & 1;
+        const int x = s_sot[i], y = s_sot[i + 1];
+        const bool more = i + 2 < R;
+        if (more) {
+            stage_ahead(bp, y, d);
+            stage_ahead(bn, s_sot[i + 2], d);
+        }
+        const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
+        T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
+        T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
+        const T* kx = buf(bl);
+        const T* ky = buf(bu);
+        const double b1 = s_beta[i], b2 = s_beta[i + 1];
+        const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
+        const float fr0 = static_cast<float>(b2 / b1);
+        double lin = 0.0, lg = 0.0;
+        for (int h = t; h < NH; h += NT) {
+            const Nbr nb = neighbours<L>(h, d, L);
+            T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
+#pragma unroll
+            for (int dd = 0; dd < 6; ++dd) {
+                const int mu = dd >> 1;
+                const T jj = (dd & 1) ? Js[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : Js[(mu * 2 + d) * NH + h];
+                const int idx = nb.n[dd];
+                ax = fma(jj, kx[0 * NH + idx], ax);
+                ay = fma(jj, kx[1 * NH + idx], ay);
+                az = fma(jj, kx[2 * NH + idx], az);
+                cx = fma(jj, ky[0 * NH + idx], cx);
+                cy = fma(jj, ky[1 * NH + idx], cy);
+                cz = fma(jj, ky[2 * NH + idx], cz);
+            }
+            const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
+            lin += a - c;
+            lg += static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0));
+        }
+        const double lnA = block_sum<NT, true>(fma(b2 - b1, lin, lg), red);
+        if (t == 0) {
+            if (e.work) {
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
+                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = static_cast<double>(d);
+            }
+            if (!isfinite(lnA)) atomicOr(e.guard, 1);
+            const bool ok = s_logu[i] < lnA;
+            st[2 * i] = s_st[2 * i] + 1;  // counts kept in LDS: no global read in the loop
+            if (ok) {
+                sot[i] = y;
+                sot[i + 1] = x;
+                s_sot[i] = y;
+                s_sot[i + 1] = x;
+                tos[x] = i + 1;
+                tos[y] = i;
+                st[2 * i + 1] = s_st[2 * i + 1] + 1;
+            }
+            s_acc = ok ? 1 : 0;
+        }
+        // this wave's staged planes have landed (requested at the start of the pair);
+        // the barrier then makes every wave's visible, and the decision
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // gfx9 encoding: vmcnt = 0, expcnt = 7, lgkmcnt = 15
+        lds_barrier();
+        if (s_acc) {
+            const uint32_t c3 = (kTagDecimate << 24) | (static_cast<uint32_t>(i) & 0xFFFFu);
+            const T tb[2] = {static_cast<T>(b2), static_cast<T>(b1)};  // x -> beta_2, y -> beta_1
+            const T* kin[2] = {kx, ky};
+            T* out[2] = {sx, sy};
+            T* nxt = buf(bp);  // x's new sublattice d: the next pair's lower planes
+            const uint32_t gs[2] = {e.slot_base + static_cast<uint32_t>(gx), e.slot_base + static_cast<uint32_t>(gy)};
+            double en[2] = {0.0, 0.0};
+            for (int q = t; q < NQ; q += NT) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const Words w = philox(static_cast<uint32_t>(q), n, gs[r], c3, k0, k1);
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int h = q + half * NQ;
+                        const Nbr nb = neighbours<L>(h, d, L);
+                        T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+                        for (int dd = 0; dd < 6; ++dd) {
+                            const int mu = dd >> 1;
+                            const T jj = (dd & 1) ? Js[(mu * 2 + (1 - d)) * NH + nb.n[dd]] : Js[(mu * 2 + d) * NH + h];
+                            const int idx = nb.n[dd];
+                            Sx = fma(jj, kin[r][0 * NH + idx], Sx);
+                            Sy = fma(jj, kin[r][1 * NH + idx], Sy);
+                            Sz = fma(jj, kin[r][2 * NH + idx], Sz);
+                        }
+                        const T r1 = static_cast<T>(u01_23(half ? w.w2 : w.w0));
+                        const T r2 = static_cast<T>(u01_23(half ? w.w3 : w.w1));
+                        T ox, oy, oz;
+                        heatbath<T>(Sx, Sy, Sz, tb[r], r1, r2, ox, oy, oz);
+                        out[r][(0 * 2 + d) * NH + h] = ox;
+                        out[r][(1 * 2 + d) * NH + h] = oy;
+                        out[r][(2 * 2 + d) * NH + h] = oz;
+                        if (r == 0) {
+                            nxt[0 * NH + h] = ox;
+                            nxt[1 * NH + h] = oy;
+                            nxt[2 * NH + h] = oz;
+                        }
+                        const double dx = ox, dy = oy, dz = oz;
+                        en[r] += fma(dz, static_cast<double>(Sz),
+                                     fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+                    }
+                }
+            }
+            const double Hx = -block_sum<NT, true>(en[0], red);
+            const double Hy = -block_sum<NT, true>(en[1], red);
+            if (t == 0) {
+                e.energy[gx] = Hx;
+                e.energy[gy] = Hy;
+                if (!isfinite(Hx) || !isfinite(Hy)) atomicOr(e.guard, 1);
+            }
+        }
+        lds_barrier();  // the next pair reads the staged planes and reuses the others
+        const int ol = bl, ou = bu;
+        bl = bp;
+        bu = bn;
+        bp = ol;
+        bn = ou;
+    }
+}
+
 // ---------------------------------------------------------------- split ascending pass
 // With few chains, one workgroup per chain (k_decimate) leaves most CUs idle through
 // the R - 1 sequential pairs.  Here pair i of every chain is spread over G workgroups,
@@ -602,6 +823,16 @@ static hipError_t go_decimate_nt(const hsg_ensemble& e, int pairing, int blocks,
 
 template <typename T, int L>
 static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value && (L == 8 || L == 16)) {
+        constexpr size_t lds = (3 * L * L * L + 4 * 3 * (L * L * L / 2)) * sizeof(float);
+        if (pairing == 0 && e.n_temps - 1 <= kPfMaxPairs && lds <= max_block_lds()) {
+            auto kern = k_decimate_pf<L>;
+            const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+            if (a != hipSuccess) return a;
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(kPfThreads), lds, st, e);
+            return hipGetLastError();
+        }
+    }
     // binary64 site terms need more than the 128 registers of a 1024-thread workgroup
     if (pairing == 0 && sizeof(T) == 4) return go_decimate_nt<T, L, 1024>(e, pairing, blocks, st);
     return go_decimate_nt<T, L, kDecThreads>(e, pairing, blocks, st);
