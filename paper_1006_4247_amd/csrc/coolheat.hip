@@ -185,7 +185,12 @@ __device__ __forceinline__ T ch_eps(const ChEps& c, int i) {
 // (read from the candidate buffer if the exchange was accepted).  Only that leg
 // depends on pair i0 - 1; the heating leg takes the configuration at beta_{i0+1},
 // which pair i0 - 1 does not touch, and runs meanwhile.
-template <typename T, int L, int NT, bool PREV>
+//
+// HEATALL (ascending passes in two launches, see k_coolheat_cool_chain): work item b
+// heats, for pair i = b mod (R - 1) of chain b / (R - 1), the configuration at
+// beta_{i+1} as the pass finds it — no pair before i touches that temperature, so the
+// heating legs of all pairs run at once, before any decision.
+template <typename T, int L, int NT, bool PREV, bool HEATALL = false>
 __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, ChEps ce, int i0, int istep, int npc) {
     constexpr int N = L * L * L, NH = N / 2;
     constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
@@ -221,6 +226,12 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, ChEps c
         } else {
             it.slot = it.ch * R + label(e.slot_of_temp[it.ch * R + i0 + 1], R, e.guard);
         }
+    } else if constexpr (HEATALL) {
+        const int R = e.n_temps;
+        it.ch = static_cast<int>(blockIdx.x) / (R - 1);
+        it.i = static_cast<int>(blockIdx.x) - it.ch * (R - 1);
+        it.leg = 1;
+        it.slot = it.ch * R + label(e.slot_of_temp[it.ch * R + it.i + 1], R, e.guard);
     } else {
         it = ch_item(e, blockIdx.x, i0, istep, npc);
     }
@@ -537,11 +548,202 @@ __global__ void k_coolheat_finish(hsg_ensemble e, int i0, int istep) {
     if (ch < e.n_samples * e.n_chains) coolheat_finish_chain(e, ch, i0, istep);
 }
 
-template <typename T, int L, int NT, bool PREV>
+// Ascending binary32 pass, second launch (the first heats the configuration at
+// beta_{i+1} for every pair i at once, HEATALL legs): one workgroup per chain walks
+// the pairs.  The configuration at beta_i sits in LDS; the workgroup cools it (the
+// cooling legs' arithmetic, thread mapping and reductions) and decides the pair with
+// the decision kernels' formula, from copies in LDS of the chain's labels, energies,
+// statistics, temperatures and of the heating legs' results, with the decision
+// uniforms drawn up front (the decision then waits for no memory round trip; its
+// results go out as stores).  An accepted pair writes the cooled configuration, now at
+// beta_{i+1}, over its slot and the heated one over the other slot (its vectors were
+// requested into registers when the pair began); the cooled configuration stays in LDS
+// as the next pair's lower one.  A rejected pair leaves the next pair's lower
+// configuration where pair i's upper one was: its planes were requested from HBM
+// straight into a second LDS buffer (loads that bypass the registers) when pair i
+// began.  The chain's couplings sit in LDS for the whole pass; barriers are LDS-only
+// so that those loads stay in flight until the wait before the decision.  Results
+// equal the per-pair launches' bit for bit.
+constexpr int kChainMaxPairs = 128;
+
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_coolheat_cool_chain(hsg_ensemble e, ChEps ce) {
+    using T = float;
+    constexpr int N = L * L * L, NH = N / 2;
+    constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per replica
+    constexpr int PC = (NV + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Js = reinterpret_cast<T*>(smem_raw);  // [3][2][NH]
+    T* bufs = Js + 3 * N;                    // two replicas [3][2][NH]
+    __shared__ double red[NT / 64];
+    __shared__ double s_en[kChainMaxPairs + 1], s_cen[kChainMaxPairs + 1], s_beta[kChainMaxPairs + 1];
+    __shared__ double s_wh[kChainMaxPairs], s_logu[kChainMaxPairs];
+    __shared__ long long s_st[2 * kChainMaxPairs];
+    __shared__ int s_sot[kChainMaxPairs + 1];
+    __shared__ int s_ok;
+    const int R = e.n_temps;
+    const int ch = static_cast<int>(blockIdx.x);
+    const int t = static_cast<int>(threadIdx.x);
+    const int smp = ch / e.n_chains;
+    const ScratchLayout sl = scratch_layout(e);
+    unsigned char* scr = static_cast<unsigned char*>(e.scratch);
+    const T* cand = reinterpret_cast<const T*>(scr + sl.cand);
+    double* cen = reinterpret_cast<double*>(scr + sl.cand_energy) + static_cast<size_t>(ch) * R;
+    T* spins = static_cast<T*>(e.spins);
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    double* en = e.energy + static_cast<size_t>(ch) * R;
+    double* W = e.work + static_cast<size_t>(ch) * (R - 1) * 2;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    for (int r = t; r < R; r += NT) {
+        s_sot[r] = label(sot[r], R, e.guard);
+        s_en[r] = en[r];
+        s_cen[r] = cen[r];  // the heated configurations' energies, by slot
+        s_beta[r] = e.betas[r];
+    }
+    for (int i = t; i < R - 1; i += NT) {
+        s_wh[i] = W[2 * i + 1];
+        const Words w = philox(static_cast<uint32_t>(i), n, cg, kTagSwap << 24, key_lo(e.seed), key_hi(e.seed));
+        s_logu[i] = log(u01_52(w.w0, w.w1));
+        s_st[2 * i] = st[2 * i];
+        s_st[2 * i + 1] = st[2 * i + 1];
+    }
+    __syncthreads();
+    int xs = s_sot[0];  // slot of the configuration at beta_i
+    {
+        const uint4* js = reinterpret_cast<const uint4*>(static_cast<const T*>(e.couplings) +
+                                                         static_cast<size_t>(smp) * 3 * N);
+        const uint4* xv = reinterpret_cast<const uint4*>(spins + (static_cast<size_t>(ch) * R + xs) * 3 * N);
+        uint4* jd = reinterpret_cast<uint4*>(Js);
+        uint4* xd = reinterpret_cast<uint4*>(bufs);
+        for (int v = t; v < NV; v += NT) {
+            jd[v] = js[v];
+            xd[v] = xv[v];
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int i = 0; i < R - 1; ++i) {
+        // the configuration at beta_{i+1}: pairs before i never touch it
+        const int ys = s_sot[i + 1];
+        const T eps = ch_eps<T>(ce, i);
+        T* sh = bufs + static_cast<size_t>(cur) * 3 * N;
+        T* other = bufs + static_cast<size_t>(1 - cur) * 3 * N;
+        const size_t gy = static_cast<size_t>(ch) * R + ys;
+        uint4 hv[PC];  // the heated candidate, copied over slot ys if the pair is accepted
+        {
+            const uint4* cy = reinterpret_cast<const uint4*>(cand + gy * 3 * N);
+#pragma unroll
+            for (int k = 0; k < PC; ++k) {
+                const int v = t + k * NT;
+                hv[k] = v < NV ? cy[v] : make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (i + 2 < R) {  // its planes, the next lower configuration should pair i be rejected
+            const uint4* src = reinterpret_cast<const uint4*>(spins + gy * 3 * N);
+            uint4* dst = reinterpret_cast<uint4*>(other);
+            const int wave_base = t & ~63;
+            for (int v0 = wave_base; v0 < NV; v0 += NT) {
+                const int v = v0 + (t & 63);
+                if (v < NV)
+                    __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + v),
+                                                     (__attribute__((address_space(3))) void*)(dst + v0), 16, 0, 0);
+            }
+        }
+        double ld = 0.0, en_acc = 0.0;
+        for (int step = 0; step < 2; ++step) {
+            const int p = step;  // cooling maps parity 0, then parity 1
+            const T* o0 = sh + (0 * 2 + (1 - p)) * NH;
+            const T* o1 = sh + (1 * 2 + (1 - p)) * NH;
+            const T* o2 = sh + (2 * 2 + (1 - p)) * NH;
+            T* w0 = sh + (0 * 2 + p) * NH;
+            T* w1 = sh + (1 * 2 + p) * NH;
+            T* w2 = sh + (2 * 2 + p) * NH;
+            for (int h = t; h < NH; h += NT) {
+                const Nbr nb = neighbours<L>(h, p, L);
+                T Sx = T(0), Sy = T(0), Sz = T(0);
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const int mu = d >> 1;
+                    const T jj = (d & 1) ? Js[(mu * 2 + (1 - p)) * NH + nb.n[d]] : Js[(mu * 2 + p) * NH + h];
+                    const int idx = nb.n[d];
+                    Sx = fma(jj, o0[idx], Sx);
+                    Sy = fma(jj, o1[idx], Sy);
+                    Sz = fma(jj, o2[idx], Sz);
+                }
+                T sx = w0[h], sy = w1[h], sz = w2[h];
+                ld += coolheat_site<T, false>(sx, sy, sz, Sx, Sy, Sz, eps);
+                w0[h] = sx;
+                w1[h] = sy;
+                w2[h] = sz;
+                if (step == 1) {
+                    const double dx = sx, dy = sy, dz = sz;
+                    en_acc += fma(dz, static_cast<double>(Sz),
+                                  fma(dy, static_cast<double>(Sy), dx * static_cast<double>(Sx)));
+                }
+            }
+            lds_barrier();
+        }
+        const double LD = block_sum<NT, true>(ld, red);
+        const double H = -block_sum<NT, true>(en_acc, red);
+        if (t == 0) {  // the decision kernels' formula and updates, from the LDS copies
+            const int x = xs, y = ys;
+            W[2 * i] = LD;
+            cen[x] = H;
+            s_cen[x] = H;
+            if (isnan(LD)) atomicOr(e.guard, 8);
+            const double b1 = s_beta[i], b2 = s_beta[i + 1];
+            const double lnA = b1 * s_en[x] + b2 * s_en[y] - b1 * s_cen[y] - b2 * s_cen[x] + LD - s_wh[i];
+            st[2 * i] = s_st[2 * i] + 1;
+            const bool ok = s_logu[i] < lnA;
+            if (ok) {
+                s_en[x] = s_cen[x];
+                s_en[y] = s_cen[y];
+                en[x] = s_en[x];
+                en[y] = s_en[y];
+                s_sot[i] = y;
+                s_sot[i + 1] = x;
+                sot[i] = y;
+                sot[i + 1] = x;
+                tos[x] = i + 1;
+                tos[y] = i;
+                st[2 * i + 1] = s_st[2 * i + 1] + 1;
+            }
+            s_ok = ok ? 1 : 0;
+        }
+        // this wave's requested planes and vectors have landed; the barrier makes every
+        // wave's planes visible, and the decision
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // gfx9 encoding: vmcnt = 0, expcnt = 7, lgkmcnt = 15
+        lds_barrier();
+        if (s_ok) {  // uniform: C x over slot xs (it moved to beta_{i+1}), C^-1 y over slot ys
+            const size_t gx = static_cast<size_t>(ch) * R + xs;
+            const uint4* sv = reinterpret_cast<const uint4*>(sh);
+            uint4* xd = reinterpret_cast<uint4*>(spins + gx * 3 * N);
+            uint4* yd = reinterpret_cast<uint4*>(spins + gy * 3 * N);
+#pragma unroll
+            for (int k = 0; k < PC; ++k) {
+                const int v = t + k * NT;
+                if (v < NV) {
+                    xd[v] = sv[v];
+                    yd[v] = hv[k];
+                }
+            }
+            lds_barrier();  // the write-back has read the LDS before the next pair cools it
+        } else {
+            xs = ys;
+            cur = 1 - cur;
+        }
+    }
+    if (t == 0) coolheat_finish_chain(e, ch, R - 2, 1);
+}
+
+template <typename T, int L, int NT, bool PREV, bool HEATALL = false>
 static hipError_t go_leg_nt(const hsg_ensemble& e, const ChEps& ce, int i0, int istep, int npc, int blocks,
                             hipStream_t st) {
     constexpr size_t lds = 3 * L * L * L * sizeof(T);
-    auto kern = k_coolheat_leg_res<T, L, NT, PREV>;
+    auto kern = k_coolheat_leg_res<T, L, NT, PREV, HEATALL>;
     const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
     if (a != hipSuccess) return a;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, ce, i0, istep, npc);
@@ -927,6 +1129,40 @@ static hipError_t coolheat_split_pass(const hsg_ensemble& e, const ChEps& ce, in
     return hipGetLastError();
 }
 
+// Ascending binary32 pass at L <= 16 in two launches: every pair's heating leg at once,
+// then one workgroup per chain for the cooling legs and decisions (thread counts as in
+// the per-pair launches, so the sums are the same).  hipErrorNotSupported if the
+// couplings and two replicas do not fit one workgroup's LDS.
+template <int L>
+static hipError_t coolheat_asc_two_L(const hsg_ensemble& e, const ChEps& ce, hipStream_t st) {
+    constexpr int NH = L * L * L / 2;
+    constexpr int NT1 = NH >= 1024 ? 1024 : ((NH + 63) / 64) * 64;
+    constexpr int NTS = NT1 > kChThreads ? NT1 : kChThreads;
+    constexpr size_t lds = 3 * 3 * L * L * L * sizeof(float);
+    const int chains = e.n_samples * e.n_chains, R = e.n_temps;
+    if (lds > max_block_lds() || R - 1 > kChainMaxPairs) return hipErrorNotSupported;
+    hipError_t err = go_leg_nt<float, L, NTS, false, true>(e, ce, 0, 1, 1, chains * (R - 1), st);
+    if (err != hipSuccess) return err;
+    auto kern = k_coolheat_cool_chain<L, NTS>;
+    err = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3(chains), dim3(NTS), lds, st, e, ce);
+    return hipGetLastError();
+}
+
+static hipError_t coolheat_asc_two(const hsg_ensemble& e, const ChEps& ce, hipStream_t st) {
+    switch (e.L) {
+        case 4: return coolheat_asc_two_L<4>(e, ce, st);
+        case 6: return coolheat_asc_two_L<6>(e, ce, st);
+        case 8: return coolheat_asc_two_L<8>(e, ce, st);
+        case 10: return coolheat_asc_two_L<10>(e, ce, st);
+        case 12: return coolheat_asc_two_L<12>(e, ce, st);
+        case 14: return coolheat_asc_two_L<14>(e, ce, st);
+        case 16: return coolheat_asc_two_L<16>(e, ce, st);
+        default: return hipErrorNotSupported;
+    }
+}
+
 hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, const double* eps_pair, hipStream_t st) {
     const ChEps ce{eps, eps_pair};
     const int R = e.n_temps;
@@ -937,6 +1173,10 @@ hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, const
         if (G > 1)
             return e.precision == HSG_FP64 ? coolheat_split_pass<double>(e, ce, G, st)
                                            : coolheat_split_pass<float>(e, ce, G, st);
+        if (e.precision == HSG_FP32 && e.L <= 16) {
+            const hipError_t err = coolheat_asc_two(e, ce, st);
+            if (err != hipErrorNotSupported) return err;
+        }
         // (pair i - 1 decided inside pair i's launch, the last pair by its own)
         for (int i = 0; i < R - 1; ++i) {
             hipError_t err = e.precision == HSG_FP64 ? go_legs<double>(e, ce, i, 1, 1, i > 0, st)
