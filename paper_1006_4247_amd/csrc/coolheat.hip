@@ -262,6 +262,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_leg_res(hsg_ensemble e, ChEps c
         T* w0 = sh + (0 * 2 + p) * NH;
         T* w1 = sh + (1 * 2 + p) * NH;
         T* w2 = sh + (2 * 2 + p) * NH;
+#pragma unroll  // the sites of a thread are independent: their latency chains interleave
         for (int h = threadIdx.x; h < NH; h += NT) {
             const Nbr nb = neighbours<L>(h, p, L);
             T Sx = T(0), Sy = T(0), Sz = T(0);
@@ -575,7 +576,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_cool_chain(hsg_ensemble e, ChEp
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* Js = reinterpret_cast<T*>(smem_raw);  // [3][2][NH]
     T* bufs = Js + 3 * N;                    // two replicas [3][2][NH]
-    __shared__ double red[NT / 64];
+    __shared__ double red[2 * (NT / 64)];
     __shared__ double s_en[kChainMaxPairs + 1], s_cen[kChainMaxPairs + 1], s_beta[kChainMaxPairs + 1];
     __shared__ double s_wh[kChainMaxPairs], s_logu[kChainMaxPairs];
     __shared__ long long s_st[2 * kChainMaxPairs];
@@ -661,6 +662,7 @@ __global__ void __launch_bounds__(NT) k_coolheat_cool_chain(hsg_ensemble e, ChEp
             T* w0 = sh + (0 * 2 + p) * NH;
             T* w1 = sh + (1 * 2 + p) * NH;
             T* w2 = sh + (2 * 2 + p) * NH;
+#pragma unroll  // the sites of a thread are independent: their latency chains interleave
             for (int h = t; h < NH; h += NT) {
                 const Nbr nb = neighbours<L>(h, p, L);
                 T Sx = T(0), Sy = T(0), Sz = T(0);
@@ -686,8 +688,22 @@ __global__ void __launch_bounds__(NT) k_coolheat_cool_chain(hsg_ensemble e, ChEp
             }
             lds_barrier();
         }
-        const double LD = block_sum<NT, true>(ld, red);
-        const double H = -block_sum<NT, true>(en_acc, red);
+        // both sums in one pass, each in block_sum's order (valid in thread 0)
+        ld = wave_sum(ld);
+        en_acc = wave_sum(en_acc);
+        if ((t & 63) == 0) {
+            red[t >> 6] = ld;
+            red[NT / 64 + (t >> 6)] = en_acc;
+        }
+        lds_barrier();
+        double LD = 0.0, H = 0.0;
+        if (t == 0) {
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) LD += red[w];
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) H += red[NT / 64 + w];
+            H = -H;
+        }
         if (t == 0) {  // the decision kernels' formula and updates, from the LDS copies
             const int x = xs, y = ys;
             W[2 * i] = LD;

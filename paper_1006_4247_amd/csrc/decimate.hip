@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* Js = reinterpret_cast<T*>(smem_raw);  // [3][2][NH]
     T* pool = Js + 3 * N;                    // [4][3][NH]
-    __shared__ double red[NT / 64];
+    __shared__ double red[2 * (NT / 64)];
     __shared__ double s_logu[kPfMaxPairs];
     __shared__ double s_beta[kPfMaxPairs + 1];
     __shared__ long long s_st[2 * kPfMaxPairs];
@@ -500,6 +500,7 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
         const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
         const float fr0 = static_cast<float>(b2 / b1);
         double lin = 0.0, lg = 0.0;
+#pragma unroll  // the sites of a thread are independent: their latency chains interleave
         for (int h = t; h < NH; h += NT) {
             const Nbr nb = neighbours<L>(h, d, L);
             T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
@@ -587,9 +588,20 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
                     }
                 }
             }
-            const double Hx = -block_sum<NT, true>(en[0], red);
-            const double Hy = -block_sum<NT, true>(en[1], red);
+            // both energies in one pass, each in block_sum's order (valid in thread 0)
+            const double ex = wave_sum(en[0]), ey = wave_sum(en[1]);
+            if ((t & 63) == 0) {
+                red[t >> 6] = ex;
+                red[NT / 64 + (t >> 6)] = ey;
+            }
+            lds_barrier();
             if (t == 0) {
+                double sx = 0.0, sy = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) sx += red[w];
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) sy += red[NT / 64 + w];
+                const double Hx = -sx, Hy = -sy;
                 e.energy[gx] = Hx;
                 e.energy[gy] = Hy;
                 if (!isfinite(Hx) || !isfinite(Hy)) atomicOr(e.guard, 1);
