@@ -487,10 +487,7 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
         const int d = (d0 + i) & 1;
         const int x = s_sot[i], y = s_sot[i + 1];
         const bool more = i + 2 < R;
-        if (more) {
-            stage_ahead(bp, y, d);
-            stage_ahead(bn, s_sot[i + 2], d);
-        }
+        if (more) stage_ahead(bp, y, d);  // the other request goes out between the site terms
         const size_t gx = static_cast<size_t>(ch) * R + x, gy = static_cast<size_t>(ch) * R + y;
         T* sx = static_cast<T*>(e.spins) + gx * 3 * N;
         T* sy = static_cast<T*>(e.spins) + gy * 3 * N;
@@ -500,8 +497,7 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
         const float fb1 = static_cast<float>(b1), fb2 = static_cast<float>(b2);
         const float fr0 = static_cast<float>(b2 / b1);
         double lin = 0.0, lg = 0.0;
-#pragma unroll  // the sites of a thread are independent: their latency chains interleave
-        for (int h = t; h < NH; h += NT) {
+        auto term = [&](int h) {
             const Nbr nb = neighbours<L>(h, d, L);
             T ax = T(0), ay = T(0), az = T(0), cx = T(0), cy = T(0), cz = T(0);
 #pragma unroll
@@ -519,8 +515,23 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
             const double a = norm3<T>(ax, ay, az), c = norm3<T>(cx, cy, cz);
             lin += a - c;
             lg += static_cast<double>(dec_log_ratio_f(static_cast<float>(a), static_cast<float>(c), fb1, fb2, fr0));
+        };
+        // the memory pipeline is idle during the site terms: the second request goes
+        // out between a thread's first and later sites (same summation order)
+        if (t < NH) term(t);
+        if (more) stage_ahead(bn, s_sot[i + 2], d);
+        for (int h = t + NT; h < NH; h += NT) term(h);
+        // ln A in block_sum's order; only thread 0 reads it, before the decision's barrier
+        double lnA;
+        {
+            const double v = wave_sum(fma(b2 - b1, lin, lg));
+            if ((t & 63) == 0) red[t >> 6] = v;
+            lds_barrier();
+            lnA = 0.0;
+            if (t == 0)
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) lnA += red[w];
         }
-        const double lnA = block_sum<NT, true>(fma(b2 - b1, lin, lg), red);
         if (t == 0) {
             if (e.work) {
                 e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = lnA;
