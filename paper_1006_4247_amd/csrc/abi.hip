@@ -389,6 +389,11 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
             if (err != hipSuccess) return device(err, "sweep and measure");
             continue;
         }
+        if (n_sweeps > 0 && hsg::resident_mseq_supported(ens[i])) {
+            err = hsg::launch_resident_mseq(launch_copy(ens[i]), n_sweeps, n_hb, n_or, as_stream(stream));
+            if (err != hipSuccess) return device(err, "sweep and measure");
+            continue;
+        }
         if (n_sweeps > 0) {
             s = hsg_sweep(&ens[i], 1, n_sweeps, n_hb, n_or, stream);
             if (s != HSG_OK) return s;

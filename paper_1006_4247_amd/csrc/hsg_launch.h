@@ -50,6 +50,11 @@ hipError_t launch_resident(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_
 // anneal = 0 and then launch_measure): ensembles of exactly two chains at the sizes
 // where this one launch is faster (binary32 L <= 10, binary64 L <= 12).
 bool resident_pair_supported(const hsg_ensemble& e);
+// One workgroup per (sample, temperature) sweeping the chain-0 then the chain-1 replica
+// and measuring the pair (binary32, L = 16, two chains): the results of launch_resident
+// with anneal = 0 and launch_measure, Q and chi within rounding.
+bool resident_mseq_supported(const hsg_ensemble& e);
+hipError_t launch_resident_mseq(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st);
 hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st);
 
 // Wavefront path: one workgroup per replica walking its z-planes, one HBM pass per

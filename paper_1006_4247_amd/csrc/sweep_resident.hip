@@ -188,6 +188,83 @@ __global__ void __launch_bounds__(2 * NT)
     }
 }
 
+// Regular sweeps and the measurement of one (sample, temperature), ensembles of two
+// chains, binary32 L = 16 with 512 threads per replica: the workgroup sweeps the chain-0
+// replica at that temperature and then the chain-1 replica, each exactly as k_resident
+// does (same site order, random numbers and energy reduction, hence the same spins and
+// energies bit for bit), and measures the pair as the measurement pass does: e = H/N
+// of both, Q^{mu nu} = sum_x s1^mu(x) s2^nu(x) and chi = (1/N) sum Q^2 (paper Sec. IV),
+// from the chain-1 replica still in LDS and the chain-0 replica read back — each thread
+// reads the 16-byte vectors it wrote itself, one position of every plane, so its own
+// writes are all it needs to see.  This saves the measurement pass's second read of
+// every replica; Q is summed in another order (within rounding of the pass's).
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_resident_mseq(hsg_ensemble e, int n_sweeps, int n_hb, int n_or) {
+    constexpr int N = L * L * L;
+    constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // 16-byte vectors per replica
+    constexpr int NVP = NV / 6;                                    // per plane [component][parity]
+    constexpr int W = 16 / static_cast<int>(sizeof(T));            // sites per vector
+    static_assert(NVP == NT, "each thread holds the same position of every plane");
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[9 * NW];
+    __shared__ double s_H;
+    const int R = e.n_temps;
+    const int t = static_cast<int>(threadIdx.x);
+    const int item = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int smp = item / R, b = item - smp * R;
+    int slots[2];
+    double H[2];
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+        const int chain = smp * 2 + rep;
+        slots[rep] = chain * R + label(e.slot_of_temp[chain * R + b], R, e.guard);
+        resident_item<T, L, NT>(e, slots[rep], n_sweeps, n_hb, n_or, 0, 0, smem_raw, red, s_H);
+        H[rep] = s_H;  // written before the energy's barrier
+        __syncthreads();  // every thread has read it; the write-back has read the LDS
+    }
+    if (t == 0) {
+        e.e_temp[(static_cast<size_t>(smp) * 2 + 0) * R + b] = H[0] / static_cast<double>(N);
+        e.e_temp[(static_cast<size_t>(smp) * 2 + 1) * R + b] = H[1] / static_cast<double>(N);
+    }
+    struct alignas(16) Vec { T v[W]; };
+    const Vec* a = reinterpret_cast<const Vec*>(static_cast<const T*>(e.spins) + static_cast<size_t>(slots[0]) * 3 * N);
+    const Vec* c = reinterpret_cast<const Vec*>(smem_raw);
+    Vec av[6], cv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {  // plane k = 2 mu + parity, position t
+        av[k] = a[k * NVP + t];
+        cv[k] = c[k * NVP + t];
+    }
+    double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const double x0 = av[0 + p].v[w], x1 = av[2 + p].v[w], x2 = av[4 + p].v[w];
+            const double y0 = cv[0 + p].v[w], y1 = cv[2 + p].v[w], y2 = cv[4 + p].v[w];
+            q[0] = fma(x0, y0, q[0]); q[1] = fma(x0, y1, q[1]); q[2] = fma(x0, y2, q[2]);
+            q[3] = fma(x1, y0, q[3]); q[4] = fma(x1, y1, q[4]); q[5] = fma(x1, y2, q[5]);
+            q[6] = fma(x2, y0, q[6]); q[7] = fma(x2, y1, q[7]); q[8] = fma(x2, y2, q[8]);
+        }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double w = wave_sum(q[k]);
+        if ((t & 63) == 0) red[k * NW + (t >> 6)] = w;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double chi = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            double u = 0.0;
+            for (int w = 0; w < NW; ++w) u += red[k * NW + w];
+            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = u;
+            chi += u * u;
+        }
+        e.chi[static_cast<size_t>(smp) * R + b] = chi / static_cast<double>(N);
+    }
+}
+
 // Persistent variant for regular sweeps: each workgroup takes a contiguous range
 // of slots (consecutive replicas mostly share a sample, whose couplings then stay
 // in registers) and double-buffers the replicas in LDS: the next replica's loads
@@ -665,6 +742,23 @@ bool resident_pair_supported(const hsg_ensemble& e) {
 
 bool chain_supported(const hsg_ensemble& e) {
     return resident_supported(e) && e.precision == HSG_FP32 && e.L == 16;
+}
+
+bool resident_mseq_supported(const hsg_ensemble& e) {
+    return resident_supported(e) && e.precision == HSG_FP32 && e.L == 16 && e.n_chains == 2 && e.Q && e.chi &&
+           e.e_temp;
+}
+
+hipError_t launch_resident_mseq(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
+    constexpr int L = 16, NT = 512;
+    const size_t lds = 3 * L * L * L * sizeof(float);
+    const int blocks = e.n_samples * e.n_temps;
+    if (blocks <= 0) return hipSuccess;
+    auto kern = k_resident_mseq<float, L, NT>;
+    const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+    if (a != hipSuccess) return a;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, e, n_sweeps, n_hb, n_or);
+    return hipGetLastError();
 }
 
 hipError_t launch_resident_pair(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or, hipStream_t st) {
