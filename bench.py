@@ -59,24 +59,34 @@ def algorithmic_ops_per_update(n_hb, n_or):
     return (n_hb * OPS_HEATBATH_UPDATE + n_or * OPS_OVERRELAX_UPDATE) / (n_hb + n_or)
 
 
-def hbm_bytes_per_launch(w, n_sweeps=1):
+def hbm_bytes_per_launch(w, measure=False):
     """Algorithmic HBM bytes of one LDS-resident sweep launch: every replica written
     once and read once, where a sweep that opens with a heat-bath half-sweep needs only
     the sublattice that half-sweep does not update (the other one is redrawn unread);
-    the couplings of every sample read once."""
+    the couplings of every sample read once.  With the measurement in the same launch
+    (measure=True), the chain-0 replica of every (sample, temperature) is read once more
+    for the overlap (the chain-1 replica is still in LDS)."""
     t = 4 if w["prec"] == "fp32" else 8
     N = w["L"] ** 3
     slots = w["S"] * w["C"] * w["R"]
     read = 3 * (N // 2) * t if w["n_hb"] > 0 else 3 * N * t
-    return slots * (read + 3 * N * t) + w["S"] * 3 * N * t
+    extra = w["S"] * w["R"] * 3 * N * t if measure else 0
+    return slots * (read + 3 * N * t) + w["S"] * 3 * N * t + extra
 
 
-def resident_kernel_name(w):
-    """The LDS-resident sweep instance the library picks by default for this workload."""
+def step_kernel(w):
+    """The kernel of the workload's step that sweeps every replica (the step's dominant
+    kernel), as the library picks it: (name, whether it also measures).  With two
+    chains at binary32 L = 16 the sweep and the measurement are one launch."""
+    if w["prec"] == "fp32" and w["L"] == 16 and w["C"] == 2:
+        return "k_resident_mseq<float,16,512>", True
     nq = w["L"] ** 3 // 4
     nt = min(1024, (nq + 63) // 64 * 64)
     nt = 512 if nt >= 1024 else nt
-    return "k_resident<%s,%d,%d>" % ("float" if w["prec"] == "fp32" else "double", w["L"], nt)
+    return "k_resident<%s,%d,%d>" % ("float" if w["prec"] == "fp32" else "double", w["L"], nt), False
+
+
+OPS_OVERLAP_SITE = 9  # the overlap tensor: nine products per site of a (sample, temperature)
 
 
 # Sources of the sweep kernel whose HBM traffic the counter summary records; the
@@ -97,11 +107,16 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in
-    profiles/ (each counter scaled by its reading on a plain copy of known size), or None
-    if the summary was taken on other kernel sources or for another workload."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_resident_%s.md" % workload)
+def _kernel_base(kernel):
+    return kernel.split("<")[0]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary in profiles/ (each counter scaled by its reading on a plain copy of known
+    size), or None if the summary was taken on other kernel sources, for another
+    workload or another kernel."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s.md" % (_kernel_base(kernel), workload))
     if not os.path.exists(path):
         return None
     digest = kernel_sources_sha256()
@@ -109,7 +124,8 @@ def measured_traffic(workload):
         for line in fh:
             if line.startswith("traffic:"):
                 kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
-                if kv.get("workload") == workload and kv.get("sources_sha256") == digest:
+                if (kv.get("workload") == workload and kv.get("sources_sha256") == digest
+                        and kv.get("kernel") == kernel.replace(" ", "")):
                     return int(kv["bytes_per_launch"])
     return None
 
@@ -120,7 +136,7 @@ def measured_valu_instructions(workload, kernel):
     sources or for another workload."""
     if workload is None:
         return None
-    path = os.path.join(ROOT, "profiles", "valu_lds_counters_k_resident_%s.md" % workload)
+    path = os.path.join(ROOT, "profiles", "valu_lds_counters_%s_%s.md" % (_kernel_base(kernel), workload))
     if not os.path.exists(path):
         return None
     digest = kernel_sources_sha256()
@@ -762,13 +778,23 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
     att = (stats1[:, 0] - stats0[:, 0]).astype(np.float64)
     run.release()
     ens.stream = None  # eager calls below go to this stream (the run had given it its own)
-    # the dominant kernel: back-to-back sweep launches on this stream, events around them
+    # the dominant kernel (the step's sweep, with the measurement where the library
+    # fuses it): back-to-back launches on this stream, events around them
+    name, fused = step_kernel(w)
+
+    def launch():
+        if fused:
+            ens.sweep_measure(1, w["n_hb"], w["n_or"])
+        else:
+            ens.sweep(1, w["n_hb"], w["n_or"])
+
     n_k = max(50, min(400, int(0.05 / max(elapsed / max(steps, 1), 1e-5))))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ens.sweep(5, w["n_hb"], w["n_or"])
+    for _ in range(5):
+        launch()
     ev0.record(stream)
     for _ in range(n_k):
-        ens.sweep(1, w["n_hb"], w["n_or"])
+        launch()
     ev1.record(stream)
     torch.cuda.synchronize()
     avg_launch_s = ev0.elapsed_time(ev1) / 1e3 / n_k
@@ -778,18 +804,22 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
     slots = w["S"] * w["C"] * w["R"]
     upd_per_step = slots * N * (w["n_hb"] + w["n_or"])
     ops = algorithmic_ops_per_update(w["n_hb"], w["n_or"]) * upd_per_step
+    if fused:
+        ops += OPS_OVERLAP_SITE * N * w["S"] * w["R"]
     alu_achieved = ops / avg_launch_s / 1e12
-    hbm_achieved = hbm_bytes_per_launch(w) / avg_launch_s / 1e9
-    name = resident_kernel_name(w)
+    hbm_achieved = hbm_bytes_per_launch(w, measure=fused) / avg_launch_s / 1e9
     workload = [k for k, v in WORKLOADS.items() if v == w]
     valu = measured_valu_instructions(workload[0] if workload else None, name)
     roofline = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(workload[0]) if workload else None,
-                "kernel": "%s (one sweep of every replica per launch)" % name,
+                "traffic": measured_traffic(workload[0], name) if workload else None,
+                "kernel": "%s (one sweep of every replica%s per launch)" % (
+                    name, " and the measurement" if fused else ""),
                 "avg_launch_ms": round(avg_launch_s * 1e3, 5),
-                "avg_launch_from": "HIP events around %d back-to-back sweep launches on the run's stream" % n_k,
+                "avg_launch_from": "HIP events around %d back-to-back %s launches on the run's stream" % (
+                    n_k, "sweep-and-measurement" if fused else "sweep"),
                 "ops_per_site_update": algorithmic_ops_per_update(w["n_hb"], w["n_or"]),
+                "ops_per_launch": int(ops),
                 "valu_issue_frac": (round(valu / (N_CU * CLOCK_GHZ * 1e9 * avg_launch_s), 4) if valu else None),
                 "valu_wave_instructions_per_launch": valu,
                 "hbm_algorithmic_GBs": round(hbm_achieved, 1),

@@ -221,7 +221,9 @@ __global__ void __launch_bounds__(NT) k_resident_mseq(hsg_ensemble e, int n_swee
         slots[rep] = chain * R + label(e.slot_of_temp[chain * R + b], R, e.guard);
         resident_item<T, L, NT>(e, slots[rep], n_sweeps, n_hb, n_or, 0, 0, smem_raw, red, s_H);
         H[rep] = s_H;  // written before the energy's barrier
-        __syncthreads();  // every thread has read it; the write-back has read the LDS
+        // every thread has read it and the write-back has read the LDS; its stores stay
+        // in flight (a thread's later reads of its own writes see them)
+        lds_barrier();
     }
     if (t == 0) {
         e.e_temp[(static_cast<size_t>(smp) * 2 + 0) * R + b] = H[0] / static_cast<double>(N);
@@ -247,19 +249,28 @@ __global__ void __launch_bounds__(NT) k_resident_mseq(hsg_ensemble e, int n_swee
             q[3] = fma(x1, y0, q[3]); q[4] = fma(x1, y1, q[4]); q[5] = fma(x1, y2, q[5]);
             q[6] = fma(x2, y0, q[6]); q[7] = fma(x2, y1, q[7]); q[8] = fma(x2, y2, q[8]);
         }
+    // the nine sums: every thread's partials into LDS (over the replica, now read),
+    // then wave w adds up component k = w (and k = 8 for wave 0): each lane the
+    // partials of threads lane, lane + 64, ..., then a butterfly over the lanes
+    double* part = reinterpret_cast<double*>(smem_raw);  // [9][NT]
+    lds_barrier();  // every thread has read its replica vectors
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double w = wave_sum(q[k]);
-        if ((t & 63) == 0) red[k * NW + (t >> 6)] = w;
+    for (int k = 0; k < 9; ++k) part[k * NT + t] = q[k];
+    lds_barrier();
+    const int wv = t >> 6, lane = t & 63;
+    for (int k = wv; k < 9; k += NW) {
+        double u = 0.0;
+#pragma unroll
+        for (int j = lane; j < NT; j += 64) u += part[k * NT + j];
+        u = wave_sum(u);
+        if (lane == 0) red[k] = u;
     }
-    __syncthreads();
+    lds_barrier();
     if (t == 0) {
         double chi = 0.0;
         for (int k = 0; k < 9; ++k) {
-            double u = 0.0;
-            for (int w = 0; w < NW; ++w) u += red[k * NW + w];
-            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = u;
-            chi += u * u;
+            e.Q[(static_cast<size_t>(smp) * R + b) * 9 + k] = red[k];
+            chi += red[k] * red[k];
         }
         e.chi[static_cast<size_t>(smp) * R + b] = chi / static_cast<double>(N);
     }
