@@ -5,9 +5,11 @@
   equal the oracle's measurement (Sec. IV) of the GPU's own final configurations.
 * Equality with the two calls it stands for (hsg_sweep, then hsg_measure): identical
   spins and counters, energies and measurements up to the rounding order of FP64 sums,
-  on the fused launch (two chains, binary32 L <= 10 or binary64 L <= 12) and on cases
-  that take the two launches (larger L, one or three chains, streaming sizes), and at
-  two full shapes (L = 8, 128 x 2 x 8, fused; L = 16, 64 x 2 x 24, two launches).
+  on the fused launches (two chains: binary32 L <= 10 and binary64 L <= 12 with both
+  replicas side by side, binary32 L = 16 with the two swept in sequence by one
+  workgroup) and on cases that take the two launches (other L, one or three chains,
+  streaming sizes), and at two full shapes (L = 8, 128 x 2 x 8; L = 16, 64 x 2 x 24,
+  the benchmark's launch), where the fused measurement also meets the oracle's.
 """
 import numpy as np
 import pytest
@@ -121,8 +123,8 @@ def _assert_same(a, b, fused_energy_bitwise):
     ("fp32", 8, 2, 2),
     ("fp64", 8, 2, 1),
     ("fp64", 12, 2, 2),   # one launch with 256 threads per replica (the sweep alone: 448)
-    ("fp32", 16, 2, 2),   # two launches from here on
-    ("fp32", 12, 2, 1),
+    ("fp32", 16, 2, 2),   # one launch, the two replicas in sequence
+    ("fp32", 12, 2, 1),   # two launches from here on
     ("fp32", 8, 1, 1),    # one chain: no overlap
     ("fp32", 8, 3, 2),    # three chains: Q of chains 0 and 1
     ("fp64", 16, 2, 1),
@@ -139,9 +141,9 @@ def test_sweep_measure_equals_sweep_then_measure(prec, L, C, n_sweeps):
 
 @pytest.mark.parametrize("L,S,R", [(8, 128, 8), (16, 64, 24)])
 def test_sweep_measure_full_shape(L, S, R):
-    """Full binary32 shapes (the smallest class of the uneven batch, fused; the L = 16
-    benchmark shape, two launches), 1 HB + 3 OR, two steps in a row with a plain
-    exchange between."""
+    """Full binary32 shapes (the smallest class of the uneven batch; the L = 16
+    benchmark shape and launch), 1 HB + 3 OR, two steps in a row with a plain exchange
+    between."""
     C = 2
     a = hsg.Ensemble(L, S, C, _betas(R), SEED + 7, precision="fp32")
     b = hsg.Ensemble(L, S, C, _betas(R), SEED + 7, precision="fp32")
@@ -156,3 +158,9 @@ def test_sweep_measure_full_shape(L, S, R):
         b.swap(0)
     _assert_same(a, b, fused_energy_bitwise=True)
     assert torch.equal(a.slot_of_temp, b.slot_of_temp)
+    # the fused launch's measurement against the oracle's measurement of its own final
+    # configurations, every (sample, temperature)
+    rQ, rchi, re = _oracle_measure_of(b)
+    assert np.max(np.abs(b.Q.cpu().numpy() - rQ)) <= 1e-10
+    assert np.max(np.abs(b.chi.cpu().numpy() - rchi)) <= 1e-10 * max(1.0, float(np.max(rchi)))
+    assert np.array_equal(b.e_temp.cpu().numpy(), re)
