@@ -233,11 +233,14 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 //         (chain, pair, leg); leg 0 = up (forward order), 1 = down (adjoint).
 // The work of one workgroup: work item `bid` (see above), the replica in the LDS at
 // smem_raw, `red` and `s_H` workgroup-shared scratch of >= NT/64 and 1 doubles.  Used
-// by k_resident and by the persistent batch kernel (sweep_batch.hip).
-template <typename T, int L, int NT>
+// by k_resident and by the persistent batch kernel (sweep_batch.hip).  KEEP (regular
+// sweeps of replicas of one sample in a row): 1 loads the couplings into *keep, 2 takes
+// them from there and loads only the replica.
+template <typename T, int L, int NT, int KEEP = 0>
 __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, int n_sweeps, int n_hb, int n_or,
                                               int anneal, int parity, unsigned char* smem_raw, double* red,
-                                              double& s_H) {
+                                              double& s_H,
+                                              Owned<T, (L * L * L / 4 + NT - 1) / NT>* keep = nullptr) {
     constexpr int N = L * L * L, NQ = N / 4;
     constexpr int MQ = (NQ + NT - 1) / NT;
     T* sh = reinterpret_cast<T*>(smem_raw);
@@ -297,9 +300,21 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
     // then only the three parity-1 planes are loaded.  Where the vectors fit in
     // registers, the replica's loads are issued right after the couplings' loads
     // and stay in flight while the couplings pass through LDS.
-    Owned<T, MQ> own;
+    Owned<T, MQ> own_local;
+    Owned<T, MQ>& own = KEEP ? *keep : own_local;
     const FirstNbr fn = first_neighbours<L, NT>(static_cast<int>(threadIdx.x));
-    {
+    if constexpr (KEEP == 2) {  // the couplings are in registers already: the replica only
+        constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
+        constexpr int NVP = NV / 6;
+        const bool hb_first = n_hb > 0 && n_sweeps > 0;
+        const uint4* src = reinterpret_cast<const uint4*>(gs);
+        uint4* dst = reinterpret_cast<uint4*>(sh);
+        const int n_load = hb_first ? NV / 2 : NV;
+        for (int v = threadIdx.x; v < n_load; v += NT) {
+            const int o = loaded_vec<NVP>(v, hb_first);
+            dst[o] = src[o];
+        }
+    } else {
         constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;  // vectors per replica
         constexpr int NVP = NV / 6;                                    // per plane
         constexpr int PV = (NV + NT - 1) / NT;                         // per thread

@@ -215,11 +215,15 @@ __global__ void __launch_bounds__(NT) k_resident_mseq(hsg_ensemble e, int n_swee
     const int smp = item / R, b = item - smp * R;
     int slots[2];
     double H[2];
+    Owned<T, (N / 4 + NT - 1) / NT> own;  // both replicas belong to one sample: couplings loaded once
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
         const int chain = smp * 2 + rep;
         slots[rep] = chain * R + label(e.slot_of_temp[chain * R + b], R, e.guard);
-        resident_item<T, L, NT>(e, slots[rep], n_sweeps, n_hb, n_or, 0, 0, smem_raw, red, s_H);
+        if (rep == 0)
+            resident_item<T, L, NT, 1>(e, slots[rep], n_sweeps, n_hb, n_or, 0, 0, smem_raw, red, s_H, &own);
+        else
+            resident_item<T, L, NT, 2>(e, slots[rep], n_sweeps, n_hb, n_or, 0, 0, smem_raw, red, s_H, &own);
         H[rep] = s_H;  // written before the energy's barrier
         // every thread has read it and the write-back has read the LDS; its stores stay
         // in flight (a thread's later reads of its own writes see them)

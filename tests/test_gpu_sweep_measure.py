@@ -158,8 +158,10 @@ def test_sweep_measure_full_shape(L, S, R):
         b.swap(0)
     _assert_same(a, b, fused_energy_bitwise=True)
     assert torch.equal(a.slot_of_temp, b.slot_of_temp)
-    # the fused launch's measurement against the oracle's measurement of its own final
-    # configurations, every (sample, temperature)
+    # one more fused launch, its measurement against the oracle's measurement of its own
+    # final configurations (no exchange after it), every (sample, temperature)
+    b.sweep_measure(1, 1, 3)
+    torch.cuda.synchronize()
     rQ, rchi, re = _oracle_measure_of(b)
     assert np.max(np.abs(b.Q.cpu().numpy() - rQ)) <= 1e-10
     assert np.max(np.abs(b.chi.cpu().numpy() - rchi)) <= 1e-10 * max(1.0, float(np.max(rchi)))
