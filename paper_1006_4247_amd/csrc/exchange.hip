@@ -242,6 +242,97 @@ __global__ void __launch_bounds__(64) k_swap(hsg_ensemble e, int pairing) {
     if (lane == 0) e.swap_ctr[ch] = n + 1u;
 }
 
+// The same exchange for ladders of at most 64 temperatures, one wave per chain with
+// lane r holding temperature r's label, slot r's energy and its round-trip state, and
+// pair r's statistics.  Nothing it loads depends on a decision, so every load is issued
+// at entry and the kernel makes one trip to memory instead of three; labels and
+// energies move between lanes by cross-lane permutes, and the ascending pass reads each
+// pair's inputs from the lane that holds them.  Decisions, labels, statistics and round
+// trips are those of k_swap bit for bit (the same operations on the same values).
+constexpr int kSwapWaveMaxR = 64;
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFll), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__global__ void __launch_bounds__(64) k_swap_wave(hsg_ensemble e, int pairing) {
+    const int ch = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int R = e.n_temps;
+    const bool tl = lane < R, pl = lane < R - 1;
+    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
+    int* sot = e.slot_of_temp + static_cast<size_t>(ch) * R;
+    const double* en = e.energy + static_cast<size_t>(ch) * R;
+    long long* st = reinterpret_cast<long long*>(e.swap_stats) + static_cast<size_t>(ch) * (R - 1) * 2;
+    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
+    const uint32_t n = e.swap_ctr[ch];
+    const uint32_t cg = e.chain_base + static_cast<uint32_t>(ch);
+    int x = tl ? sot[lane] : lane;
+    const double e_slot = tl ? en[lane] : 0.0;
+    const double b0 = pl ? e.betas[lane] : 0.0, b1 = pl ? e.betas[lane + 1] : 0.0;
+    const long long n_att = pl ? st[2 * lane] : 0, n_acc = pl ? st[2 * lane + 1] : 0;
+    const int rs_old = tl ? rs[lane] : 0;
+    const long long trips = tl ? rtt[lane] : 0;
+    if (tl) x = label(x, R, e.guard);
+    const bool sel = pl && (pairing == 0 || (pairing == 1 && !(lane & 1)) || (pairing == 2 && (lane & 1)));
+    const double lu = sel ? log(swap_uniform(e, lane, n, cg)) : 0.0;
+    const double db = b1 - b0;
+    const double ex = __shfl(e_slot, x);  // energy of the configuration at temperature lane
+    const int up = __shfl_down(x, 1);      // the configuration above pair lane, before the pass
+    const double eup = __shfl_down(ex, 1);
+    int nx = x;
+    int acc = sel ? 2 : 0;  // 2 = attempted, 3 = accepted
+    if (pairing == 0) {
+        int carry = __builtin_amdgcn_readlane(x, 0);
+        double ec = readlane_f64(ex, 0);
+        for (int i = 0; i < R - 1; ++i) {
+            const int y = __builtin_amdgcn_readlane(up, i);
+            const double ey = readlane_f64(eup, i);
+            const bool ok = readlane_f64(lu, i) < readlane_f64(db, i) * (ey - ec);
+            if (lane == i) {
+                nx = ok ? y : carry;
+                acc = ok ? 3 : 2;
+            }
+            if (!ok) {
+                carry = y;
+                ec = ey;
+            }
+        }
+        if (lane == R - 1) nx = carry;
+    } else {
+        const bool ok = sel && lu < db * (eup - ex);
+        const int below = __shfl_up(x, 1);
+        const bool ok_below = __shfl_up(static_cast<int>(ok), 1) != 0 && lane > 0;
+        if (ok) {
+            nx = up;
+            acc = 3;
+        } else if (ok_below) {
+            nx = below;
+        }
+    }
+    // temperature of every slot: lane nx receives lane (lanes >= R map to themselves)
+    const int T = __builtin_amdgcn_ds_permute(nx << 2, lane);
+    if (tl) {
+        sot[lane] = nx;
+        tos[lane] = T;
+        if (T == 0) {
+            if (rs_old == 2) rtt[lane] = trips + 1;
+            rs[lane] = 1;
+        } else if (T == R - 1) {
+            if (rs_old == 1) rs[lane] = 2;
+        }
+    }
+    if (acc) {
+        st[2 * lane] = n_att + 1;
+        if (acc == 3) st[2 * lane + 1] = n_acc + 1;
+    }
+    if (lane == 0) e.swap_ctr[ch] = n + 1u;
+}
+
 // Annealed exchange decision: accept iff ln u < -(W_up + W_dn); the annealed
 // states (candidate buffer) replace the accepted slots, energies follow.
 __global__ void k_anneal_decide(hsg_ensemble e, int parity) {
@@ -392,7 +483,10 @@ hipError_t launch_energy(const hsg_ensemble& e, double* out, hipStream_t st) {
 hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st) {
     const int n_chains = e.n_samples * e.n_chains;
     if (e.n_temps > kSwapMaxR) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_swap, dim3(n_chains), dim3(64), 0, st, e, pairing);
+    if (e.n_temps <= kSwapWaveMaxR)
+        hipLaunchKernelGGL(k_swap_wave, dim3(n_chains), dim3(64), 0, st, e, pairing);
+    else
+        hipLaunchKernelGGL(k_swap, dim3(n_chains), dim3(64), 0, st, e, pairing);
     return hipGetLastError();
 }
 

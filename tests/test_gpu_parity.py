@@ -230,6 +230,24 @@ def test_swap_parity(pairing):
     compare_states(gpu, ref, "fp64", check_energy=False, what="swap")
 
 
+@pytest.mark.parametrize("R", [2, 3, 24, 63, 64, 65, 100])
+def test_swap_parity_ladder_lengths(R):
+    """Ladders up to 64 temperatures take the one-wave exchange kernel, longer ones the
+    general one: both against the oracle, every pairing, labels, statistics, counters
+    and round trips bit for bit."""
+    S, C = 2, 3
+    gpu, ref = make_pair(2, S, C, _betas(R, 0.3, 5.0), SEED, prec="fp64")
+    for rnd in range(30):
+        en = inputs.synthetic_energies(S, C, R, 2000 + rnd, scale=2.0)
+        ref.energy[...] = en
+        gpu.energy.copy_(torch.from_numpy(en))
+        p = rnd % 3
+        ref.swap(p)
+        gpu.swap(p)
+    torch.cuda.synchronize()
+    compare_states(gpu, ref, "fp64", check_energy=False, what="swap R=%d" % R)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_measure_parity(prec):
     L, S, C, R = 4, 2, 2, 3
