@@ -134,12 +134,19 @@ __device__ __forceinline__ void load_owned(Owned<T, MQ>& own, const T* __restric
             }
 }
 
-// One half-sweep over the sites of parity P (compile-time), HB or OR.
-template <typename T, int L, int NT, int MQ, int P>
+// One half-sweep over the sites of parity P (compile-time), HB or OR.  KIND 0 takes
+// the kind, the renormalisation and the energy from the arguments; KIND 1 (heat-bath)
+// and 2 (overrelaxation) fix them at compile time, without renormalisation or energy,
+// so that the owned sites form one branch-free block the compiler can schedule as a
+// whole (the LDS reads of a site issued under the arithmetic of the one before).
+template <typename T, int L, int NT, int MQ, int P, int KIND = 0>
 __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T, MQ>& own,
-                                              const FirstNbr& fn, bool hb, bool rn, int hs, T beta,
+                                              const FirstNbr& fn, bool hb_arg, bool rn_arg, int hs, T beta,
                                               uint32_t tsw, uint32_t g, uint32_t k0, uint32_t k1,
-                                              bool want, double& acc, bool& bad, int t) {
+                                              bool want_arg, double& acc, bool& bad, int t) {
+    const bool hb = KIND == 0 ? hb_arg : KIND == 1;
+    const bool rn = KIND == 0 && rn_arg;
+    const bool want = KIND == 0 && want_arg;
     constexpr int N = L * L * L, NH = N / 2, NQ = N / 4;
     constexpr bool INV = SiteMap<L, NT>::invariant;
     const T* __restrict__ o0 = sh + (0 * 2 + (1 - P)) * NH;
@@ -235,12 +242,15 @@ __device__ __forceinline__ void resident_half(T* __restrict__ sh, const Owned<T,
 // smem_raw, `red` and `s_H` workgroup-shared scratch of >= NT/64 and 1 doubles.  Used
 // by k_resident and by the persistent batch kernel (sweep_batch.hip).  KEEP (regular
 // sweeps of replicas of one sample in a row): 1 loads the couplings into *keep, 2 takes
-// them from there and loads only the replica.
-template <typename T, int L, int NT, int KEEP = 0>
+// them from there and loads only the replica.  FIXED_KINDS: bit 0 runs heat-bath, bit 1
+// overrelaxation half-sweeps (without renormalisation or energy) in the form with the
+// kind fixed at compile time, the others in the general form.
+template <typename T, int L, int NT, int KEEP = 0, int FIXED_KINDS = 3>
 __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, int n_sweeps, int n_hb, int n_or,
                                               int anneal, int parity, unsigned char* smem_raw, double* red,
                                               double& s_H,
                                               Owned<T, (L * L * L / 4 + NT - 1) / NT>* keep = nullptr) {
+    const int tid = static_cast<int>(threadIdx.x);
     constexpr int N = L * L * L, NQ = N / 4;
     constexpr int MQ = (NQ + NT - 1) / NT;
     T* sh = reinterpret_cast<T*>(smem_raw);
@@ -260,7 +270,7 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
         slot = ch * R + label(e.slot_of_temp[ch * R + ipair + leg], R, e.guard);
         K = e.anneal_K[ipair];
         if (K < 0 || K > e.anneal_K_max) {
-            if (threadIdx.x == 0) atomicOr(e.guard, 2);
+            if (tid == 0) atomicOr(e.guard, 2);
             K = K < 0 ? 0 : e.anneal_K_max;
         }
         lam_a = e.betas[ipair];
@@ -285,7 +295,7 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
 
     double H = anneal ? e.energy[slot] : 0.0;
     if (anneal && K == 0) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             const double W = leg == 0 ? (lam_b - lam_a) * H : (lam_a - lam_b) * H;
             e.work[(static_cast<size_t>(ch) * (R - 1) + ipair) * 2 + leg] = W;
             reinterpret_cast<double*>(scr + sl.cand_energy)[slot] = H;
@@ -302,7 +312,7 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
     // and stay in flight while the couplings pass through LDS.
     Owned<T, MQ> own_local;
     Owned<T, MQ>& own = KEEP ? *keep : own_local;
-    const FirstNbr fn = first_neighbours<L, NT>(static_cast<int>(threadIdx.x));
+    const FirstNbr fn = first_neighbours<L, NT>(tid);
     if constexpr (KEEP == 2) {  // the couplings are in registers already: the replica only
         constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
         constexpr int NVP = NV / 6;
@@ -310,7 +320,7 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
         const uint4* src = reinterpret_cast<const uint4*>(gs);
         uint4* dst = reinterpret_cast<uint4*>(sh);
         const int n_load = hb_first ? NV / 2 : NV;
-        for (int v = threadIdx.x; v < n_load; v += NT) {
+        for (int v = tid; v < n_load; v += NT) {
             const int o = loaded_vec<NVP>(v, hb_first);
             dst[o] = src[o];
         }
@@ -328,36 +338,36 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
             uint4 jv[PV], sv[PV];
 #pragma unroll
             for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                const int v = tid + k * NT;
                 jv[k] = (v < NV) ? js[v] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                const int v = tid + k * NT;
                 sv[k] = (v < n_load) ? src[loaded_vec<NVP>(v, hb_first)] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                const int v = tid + k * NT;
                 if (v < NV) dst[v] = jv[k];
             }
             lds_barrier();
-            load_owned<T, L, NT, MQ>(own, sh, fn, static_cast<int>(threadIdx.x));
+            load_owned<T, L, NT, MQ>(own, sh, fn, tid);
             lds_barrier();  // every thread holds its couplings before the LDS is reused
 #pragma unroll
             for (int k = 0; k < PV; ++k) {
-                const int v = static_cast<int>(threadIdx.x) + k * NT;
+                const int v = tid + k * NT;
                 if (v < n_load) {
                     const int o = loaded_vec<NVP>(v, hb_first);
                     dst[o] = sv[k];
                 }
             }
         } else {
-            for (int v = threadIdx.x; v < NV; v += NT) dst[v] = js[v];
+            for (int v = tid; v < NV; v += NT) dst[v] = js[v];
             __syncthreads();
-            load_owned<T, L, NT, MQ>(own, sh, fn, static_cast<int>(threadIdx.x));
+            load_owned<T, L, NT, MQ>(own, sh, fn, tid);
             __syncthreads();
-            for (int v = threadIdx.x; v < n_load; v += NT) {
+            for (int v = tid; v < n_load; v += NT) {
                 const int o = loaded_vec<NVP>(v, hb_first);
                 dst[o] = src[o];
             }
@@ -391,15 +401,27 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
             const bool rn = renorm_on(e) && n_hb == 0 && pos >= nhalf - 2;  // renormalised once per sweep
             const int p = pos & 1;
             const bool want = need_e && (step == nhalf - 1);
-            if (p == 0)
-                resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
-            else
-                resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, static_cast<int>(threadIdx.x));
+            if (rn || want || !(FIXED_KINDS & (hb ? 1 : 2))) {
+                if (p == 0)
+                    resident_half<T, L, NT, MQ, 0>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+                else
+                    resident_half<T, L, NT, MQ, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+            } else if (hb) {
+                if (p == 0)
+                    resident_half<T, L, NT, MQ, 0, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+                else
+                    resident_half<T, L, NT, MQ, 1, 1>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+            } else {
+                if (p == 0)
+                    resident_half<T, L, NT, MQ, 0, 2>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+                else
+                    resident_half<T, L, NT, MQ, 1, 2>(sh, own, fn, hb, rn, pos, beta, tsw, g, k0, k1, want, acc, bad, tid);
+            }
             __syncthreads();
         }
         if (need_e) {
             const double tot = block_sum<NT>(acc, red);
-            if (threadIdx.x == 0) s_H = -tot;
+            if (tid == 0) s_H = -tot;
             __syncthreads();
             H = s_H;
         }
@@ -412,9 +434,9 @@ __device__ __forceinline__ void resident_item(const hsg_ensemble& e, int bid, in
         const uint4* src = reinterpret_cast<const uint4*>(sh);
         uint4* dst = reinterpret_cast<uint4*>(dstp);
         constexpr int NV = 3 * N * static_cast<int>(sizeof(T)) / 16;
-        for (int v = threadIdx.x; v < NV; v += NT) dst[v] = src[v];
+        for (int v = tid; v < NV; v += NT) dst[v] = src[v];
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         if (anneal) {
             e.work[(static_cast<size_t>(ch) * (R - 1) + ipair) * 2 + leg] = W;
             reinterpret_cast<double*>(scr + sl.cand_energy)[slot] = H;

@@ -99,9 +99,9 @@ template <typename T>
 __device__ __forceinline__ void batch_resident_any(const hsg_ensemble& e, int slot, const BatchArgs& a,
                                                    unsigned char* smem, double* red, double& s_H) {
     switch (e.L) {
-    case 12: resident_item<T, 12, kBatchNT>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
-    case 14: resident_item<T, 14, kBatchNT>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
-    case 16: resident_item<T, 16, kBatchNT>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
+    case 12: resident_item<T, 12, kBatchNT, 0, 0>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
+    case 14: resident_item<T, 14, kBatchNT, 0, 0>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
+    case 16: resident_item<T, 16, kBatchNT, 0, 0>(e, slot, a.n_sweeps, a.n_hb, a.n_or, 0, 0, smem, red, s_H); break;
     default: break;
     }
 }
