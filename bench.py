@@ -13,6 +13,7 @@ events on the launch stream); cpu_baseline = the FP64 oracle on the host cores
 on a bounded sample of the same workload.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -23,10 +24,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the chip's unit counts
+# MI355X published peaks and the chip's unit counts.  VALU: 256 CUs x 4 SIMDs, each
+# accepting a wave64 binary32 instruction every two clocks (32 lanes per clock), at
+# 2.4 GHz = 78.6 T lane-instructions/s, the published 157.3 TFLOP/s binary32 vector peak
+# with an FMA counted as two (transcendentals issue at a quarter of that rate).
+# `--issue-probe` measures these rates on the device.
 HBM_PEAK_GBS = 8000.0
-N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
-VALU_PEAK_TOPS = N_CU * LANES_PER_CU * CLOCK_GHZ / 1e3  # 39.3 T lane-instructions/s
+N_CU, CLOCK_GHZ, SIMDS_PER_CU, LANES_PER_SIMD_CLOCK = 256, 2.4, 4, 32
+VALU_PEAK_TOPS = N_CU * SIMDS_PER_CU * LANES_PER_SIMD_CLOCK * CLOCK_GHZ / 1e3  # 78.6 T lane-instr/s
+WAVE_INSTR_PER_CU_CLOCK = SIMDS_PER_CU * LANES_PER_SIMD_CLOCK / 64  # 2 wave64 instructions
 
 # Algorithmic VALU operations per site update, the op model of the scope table's
 # measurement row (one add/mul/FMA/compare, one transcendental or one integer op = 1):
@@ -74,11 +80,12 @@ def hbm_bytes_per_launch(w, measure=False):
     return slots * (read + 3 * N * t) + w["S"] * 3 * N * t + extra
 
 
-def step_kernel(w):
+def step_kernel(w, fused_ok=True):
     """The kernel of the workload's step that sweeps every replica (the step's dominant
     kernel), as the library picks it: (name, whether it also measures).  With two
-    chains at binary32 L = 16 the sweep and the measurement are one launch."""
-    if w["prec"] == "fp32" and w["L"] == 16 and w["C"] == 2:
+    chains at binary32 L = 16 the sweep and the measurement are one launch, unless
+    the step is asked for unfused (the measurement as a launch of its own)."""
+    if fused_ok and w["prec"] == "fp32" and w["L"] == 16 and w["C"] == 2:
         return "k_resident_mseq<float,16,512>", True
     nq = w["L"] ** 3 // 4
     nt = min(1024, (nq + 63) // 64 * 64)
@@ -724,6 +731,52 @@ def copy_probe(torch, mib, reps=10):
                       "GBs": 2 * n * 4 / (ms.mean() / 1e3) / 1e9}), flush=True)
 
 
+PROBE_KINDS = ("fp32_fma", "fp64_fma", "fp32_exp2", "lds_4B_reads", "lds_16B_reads")
+
+
+def issue_probe(torch, reps=5):
+    """Issue rates of the compute units (hsg_probe_issue): every thread runs rounds of 16
+    independent operations of one kind.  Prints, per kind and launch shape, the lane
+    operations (VALU kinds) or LDS bytes per second from HIP events on the launch
+    stream, and the same per CU and clock at the published 2.4 GHz."""
+    from paper_1006_4247_amd import _abi
+    lib = _abi.lib()
+    shapes = (("1 wave per SIMD", 256, 256), ("full occupancy", 2048, 1024))
+    sink = torch.empty(2048 * 1024, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"probe": "issue", "clock_GHz_assumed": CLOCK_GHZ, "n_cu": N_CU, "results": []}
+    for kind, kname in enumerate(PROBE_KINDS):
+        for sname, groups, threads in shapes:
+            iters = 2000 if kind in (1, 2) else 4000
+
+            def run():
+                _abi.check(lib.hsg_probe_issue(kind, groups, threads, iters, ctypes.c_void_p(sink.data_ptr()),
+                                               ctypes.c_void_p(stream.cuda_stream)))
+            run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            s_per = e0.elapsed_time(e1) / 1e3 / reps
+            lane_ops = groups * threads * iters * 16
+            rec = {"kind": kname, "shape": sname, "groups": groups, "threads": threads,
+                   "ms": round(s_per * 1e3, 4)}
+            if kind <= 2:
+                rate = lane_ops / s_per
+                rec.update(T_lane_ops_per_s=round(rate / 1e12, 2),
+                           lane_ops_per_cu_clock=round(rate / N_CU / (CLOCK_GHZ * 1e9), 1))
+            else:
+                rate = lane_ops * 4 / s_per
+                rec.update(TB_per_s=round(rate / 1e12, 2),
+                           bytes_per_cu_clock=round(rate / N_CU / (CLOCK_GHZ * 1e9), 1))
+            out["results"].append(rec)
+            phase("probe %s, %s done" % (kname, sname))
+    print(json.dumps(out), flush=True)
+
+
 def phase(name):
     """A progress line on stderr naming the phase that starts (so a log says where a
     run stopped)."""
@@ -733,7 +786,7 @@ def phase(name):
 _T0 = time.perf_counter()
 
 
-def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
+def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True):
     """The workload's step (sweep of every replica, measurement, plain exchange of all
     pairs ascending) as the library's captured cycle (a plan: one graph launch per step),
     timed over exactly `steps` replays after `warmup` untimed ones; before those, the
@@ -746,7 +799,10 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
     ens = hsg.Ensemble(w["L"], w["S"], w["C"], betas, w["seed"], precision=w["prec"], device=dev)
     ens.init_couplings()
     ens.init_spins()
-    run = runtime.PTRun([ens], w["n_hb"], w["n_or"], mode="plain", pairing=0)
+    # unfused: the sweep kernel with one workgroup per replica (tuning path 3), then the
+    # measurement pass
+    run = runtime.PTRun([ens], w["n_hb"], w["n_or"], mode="plain", pairing=0,
+                        tunings=None if fused_ok else [{"path": 3}])
     run.capture()
     stream = torch.cuda.current_stream(dev)
     # exchange statistics over every replay of the cycle, read before the first one: a
@@ -780,7 +836,7 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
     ens.stream = None  # eager calls below go to this stream (the run had given it its own)
     # the dominant kernel (the step's sweep, with the measurement where the library
     # fuses it): back-to-back launches on this stream, events around them
-    name, fused = step_kernel(w)
+    name, fused = step_kernel(w, fused_ok)
 
     def launch():
         if fused:
@@ -820,7 +876,8 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s):
                     n_k, "sweep-and-measurement" if fused else "sweep"),
                 "ops_per_site_update": algorithmic_ops_per_update(w["n_hb"], w["n_or"]),
                 "ops_per_launch": int(ops),
-                "valu_issue_frac": (round(valu / (N_CU * CLOCK_GHZ * 1e9 * avg_launch_s), 4) if valu else None),
+                "valu_issue_frac": (round(valu / (N_CU * WAVE_INSTR_PER_CU_CLOCK * CLOCK_GHZ * 1e9 * avg_launch_s), 4)
+                                    if valu else None),
                 "valu_wave_instructions_per_launch": valu,
                 "hbm_algorithmic_GBs": round(hbm_achieved, 1),
                 "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
@@ -870,6 +927,11 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps of the uneven batch (five size classes, 424 MB of "
                          "spins) and print its JSON line")
+    ap.add_argument("--unfused", action="store_true",
+                    help="headline step with the sweep kernel and the measurement as two launches "
+                         "(profiles the sweep kernel as the dominant one)")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="issue rates of the compute units (VALU kinds, LDS reads), then exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM bandwidth probe and the "
                          "calibration of rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -883,6 +945,9 @@ def main():
     import torch
     import paper_1006_4247_amd as hsg
 
+    if args.issue_probe:
+        issue_probe(torch)
+        return
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)
         return
@@ -902,7 +967,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     phase("headline: %s" % args.workload)
-    head = headline(torch, hsg, w, args.steps, args.warmup, args.clock_warmup)
+    head = headline(torch, hsg, w, args.steps, args.warmup, args.clock_warmup, fused_ok=not args.unfused)
     line = {
         "metric": "site-updates/ns & HBM roofline %; accepted swaps per GPU-s vs plain PT",
         "value": head["value"], "unit": "site-updates/ns", "n_gpus": 1, "steps": args.steps,
@@ -911,7 +976,9 @@ def main():
         "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % w["seed"],
         "config": {"workload": args.workload, "L": w["L"], "samples": w["S"], "chains": w["C"],
                    "temperatures": w["R"], "beta": [w["bmin"], w["bmax"]], "sweep": "%d HB + %d OR" % (w["n_hb"], w["n_or"]),
-                   "exchange": "all neighbour pairs, ascending, every step", "measure": "every step"},
+                   "exchange": "all neighbour pairs, ascending, every step", "measure": "every step",
+                   "step_kernels": ("sweep, then the measurement as a launch of its own" if args.unfused
+                                    else "the library's choice (sweep and measurement fused where it fuses)")},
         "timing": head["timing"],
         "roofline": head["roofline"],
         "swap_acceptance_per_pair": head["acceptance"],

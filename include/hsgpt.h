@@ -337,6 +337,19 @@ hsg_status hsg_mlp_mse_grad(const float* y, const float* t, const float* w, int 
 hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
                         float beta1, float beta2, float eps, int t, void* stream);
 
+/* --- diagnostics: issue rates of the compute units ----------------------------
+ * The measured basis of the roofline peaks (the VALU and LDS rates the sweep kernels
+ * are held against).  Launches n_groups workgroups of group_threads threads (a
+ * multiple of 64 in [64, 1024]; 1 <= n_groups <= 2^20) on `stream`; every thread runs
+ * `iters` >= 1 rounds of 16 independent operations of one kind: 0 binary32 FMA,
+ * 1 binary64 FMA, 2 binary32 exp2 (a transcendental), 3 LDS reads of 4-byte words,
+ * 4 LDS reads of 16-byte vectors (kinds 3 and 4: each wave reads consecutive
+ * addresses, 64 bytes per thread per round).  `sink` (device, caller-owned,
+ * n_groups * group_threads floats) receives one value per thread, so that no work is
+ * optimised away.  The caller times the launch on `stream`: lane-operations =
+ * n_groups * group_threads * iters * 16.  Reads nothing else and keeps no state. */
+hsg_status hsg_probe_issue(int kind, int n_groups, int group_threads, int iters, float* sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

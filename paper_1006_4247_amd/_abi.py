@@ -70,6 +70,7 @@ SIGNATURES = {
     "hsg_mlp_mse_grad": (_i, [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),
     "hsg_mlp_adam": (_i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, _i, _vp]),
+    "hsg_probe_issue": (_i, [_i, _i, _i, _i, _vp, _vp]),
 }
 
 _lib = None

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libhsgpt.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["abi.hip", "sweep_resident.hip", "sweep_stream.hip", "sweep_wave.hip", "exchange.hip",
-           "decimate.hip", "coolheat.hip", "mlp.hip", "plan.hip", "sweep_batch.hip"]
+           "decimate.hip", "coolheat.hip", "mlp.hip", "plan.hip", "sweep_batch.hip", "probe.hip"]
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

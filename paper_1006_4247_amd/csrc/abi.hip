@@ -466,4 +466,16 @@ hsg_status hsg_mlp_adam(float* params, const float* grad, float* m, float* v, in
                   "mlp_adam");
 }
 
+hsg_status hsg_probe_issue(int kind, int n_groups, int group_threads, int iters, float* sink, void* stream) {
+    if (kind < 0 || kind > 4) return fail(HSG_ERR_INVALID, "probe: kind %d outside [0, 4]", kind);
+    if (n_groups < 1 || n_groups > (1 << 20) || group_threads < 64 || group_threads > 1024 ||
+        group_threads % 64 != 0 || iters < 1)
+        return fail(HSG_ERR_INVALID, "probe: need 1 <= n_groups <= 2^20, group_threads a multiple of 64 "
+                                     "in [64, 1024], iters >= 1 (got %d, %d, %d)",
+                    n_groups, group_threads, iters);
+    if (!sink || !aligned(sink, 4)) return fail(HSG_ERR_INVALID, "probe: sink is NULL or misaligned");
+    return device(hsg::launch_probe_issue(kind, n_groups, group_threads, iters, sink, as_stream(stream)),
+                  "probe_issue");
+}
+
 }  // extern "C"

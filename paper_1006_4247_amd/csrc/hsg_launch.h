@@ -96,4 +96,7 @@ hipError_t launch_mlp_mse_grad(const float* y, const float* t, const float* w, i
 hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr,
                            float b1, float b2, float eps, int t, hipStream_t st);
 
+// issue-rate probe (probe.hip); arguments checked by the caller
+hipError_t launch_probe_issue(int kind, int n_groups, int threads, int iters, float* sink, hipStream_t st);
+
 }  // namespace hsg

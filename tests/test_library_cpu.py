@@ -79,6 +79,13 @@ def test_abi_version_and_validation_without_gpu():
     assert lib.hsg_coolheat_swap_pairs(ctypes.byref(d), 1, 5, None, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_coolheat_swap(ctypes.byref(d), 1, 0, -1.0, None) == _abi.HSG_ERR_INVALID
     assert lib.hsg_mlp_forward(None, 0, 64, 2, None, 1, None, None, None) == _abi.HSG_ERR_INVALID
+    sink = ctypes.c_void_p(64)  # never dereferenced: each call below fails its checks first
+    assert lib.hsg_probe_issue(5, 1, 64, 1, sink, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_probe_issue(0, 1, 96, 1, sink, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_probe_issue(0, 1, 2048, 1, sink, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_probe_issue(0, 0, 64, 1, sink, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_probe_issue(0, 1, 64, 0, sink, None) == _abi.HSG_ERR_INVALID
+    assert lib.hsg_probe_issue(0, 1, 64, 1, None, None) == _abi.HSG_ERR_INVALID
 
 
 @pytest.mark.parametrize("L", [2, 4, 6, 8])
