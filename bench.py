@@ -786,7 +786,7 @@ def phase(name):
 _T0 = time.perf_counter()
 
 
-def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True):
+def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True, split=2):
     """The workload's step (sweep of every replica, measurement, plain exchange of all
     pairs ascending) as the library's captured cycle (a plan: one graph launch per step),
     timed over exactly `steps` replays after `warmup` untimed ones; before those, the
@@ -800,9 +800,11 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True):
     ens.init_couplings()
     ens.init_spins()
     # unfused: the sweep kernel with one workgroup per replica (tuning path 3), then the
-    # measurement pass
+    # measurement pass.  The cycle runs the samples as two halves on streams of their own
+    # (the plan's split: one half's exchange and launch edges overlap the other's sweep;
+    # the same results bit for bit)
     run = runtime.PTRun([ens], w["n_hb"], w["n_or"], mode="plain", pairing=0,
-                        tunings=None if fused_ok else [{"path": 3}])
+                        tunings=None if fused_ok else [{"path": 3}], split=split)
     run.capture()
     stream = torch.cuda.current_stream(dev)
     # exchange statistics over every replay of the cycle, read before the first one: a
@@ -885,8 +887,9 @@ def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True):
     return {"value": round(steps * upd_per_step / (elapsed * 1e9), 3),
             "acceptance_over": "the %d clock warm-up, %d warm-up and %d timed steps" % (n_clock, warmup, steps),
             "ms_per_step": round(elapsed * 1e3 / steps, 5),
-            "timing": {"timed": "%d replays of the captured cycle (hsg_plan_run), one graph launch per step"
-                                % steps,
+            "timing": {"timed": "%d replays of the captured cycle (hsg_plan_run: graphs of up to 16 cycles per "
+                                "launch%s)" % (steps, "; the samples as %d parts on streams of their own" % split
+                                               if split > 1 else ""),
                        "device_ms_per_step": round(device_ms / max(steps, 1), 5),
                        "clock_warmup": "%d untimed replays (%.2f s) before the %d warm-up steps"
                                        % (n_clock, clock_warmup_s, warmup)},
@@ -927,6 +930,8 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps of the uneven batch (five size classes, 424 MB of "
                          "spins) and print its JSON line")
+    ap.add_argument("--split", type=int, default=2,
+                    help="parts of the samples the captured cycle runs on streams of their own (1 = whole)")
     ap.add_argument("--unfused", action="store_true",
                     help="headline step with the sweep kernel and the measurement as two launches "
                          "(profiles the sweep kernel as the dominant one)")
@@ -967,7 +972,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     phase("headline: %s" % args.workload)
-    head = headline(torch, hsg, w, args.steps, args.warmup, args.clock_warmup, fused_ok=not args.unfused)
+    head = headline(torch, hsg, w, args.steps, args.warmup, args.clock_warmup, fused_ok=not args.unfused,
+                    split=args.split)
     line = {
         "metric": "site-updates/ns & HBM roofline %; accepted swaps per GPU-s vs plain PT",
         "value": head["value"], "unit": "site-updates/ns", "n_gpus": 1, "steps": args.steps,

@@ -296,9 +296,16 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
  *   "path", "block_threads", "replicas_per_block", "flags": hsg_tuning fields, one
  *          value or an array with one per ensemble
  *   "streams": 0 to capture all ensembles on one stream (default 1)
- *   "unroll": cycles per graph of the plan's second, unrolled form (default 8; runs of
- *             at least that many cycles launch it, so a graph launch is paid once per
- *             `unroll` cycles)
+ *   "split": k in [1, 16] (default 1): each ensemble of at least two samples runs as k
+ *            parts of consecutive samples, each on a capture stream of its own, so that
+ *            one part's exchange and launch edges overlap another's sweep; results are
+ *            those of the whole ensemble bit for bit.  Needs the plain exchange (or
+ *            none) and LDS-resident sweeps (L <= 16, path 0, 3 or 6), which use no
+ *            scratch
+ *   "unroll": the plan holds graphs of 1, 2, 4, ... cycles up to the largest power of
+ *             two <= unroll (default 16); a run of n cycles launches the longest graphs
+ *             that fit, at most about log2(n) launches, so that a graph launch (after
+ *             which the streams drain) is paid once per many cycles
  * Unknown keys and malformed values are refused (HSG_ERR_INVALID).  The plan copies the
  * descriptors: the caller's device buffers must stay allocated, and the descriptors'
  * pointers unchanged, until hsg_plan_destroy.  Creating a plan enqueues nothing on the

@@ -3,9 +3,10 @@
 // by hsg_plan_run.  Each ensemble's work is forked onto a capture stream of its own, so
 // the size classes of an uneven batch run concurrently in the graph; the whole cycle
 // is one graph launch.  Exchanges that alternate between even and odd pairs keep two
-// graphs (one per parity) and the plan remembers which parity comes next.  A second
-// pair of graphs holds `unroll` cycles each (default 8): long runs launch those, so
-// the per-launch cost of a graph is paid once per `unroll` cycles.
+// graphs (one per parity) and the plan remembers which parity comes next.  Graphs of
+// 2, 4, ... cycles (up to the largest power of two <= `unroll`, default 16) cover
+// longer runs with few launches, so the per-launch cost of a graph, and the drain of
+// its streams at its end, is paid once per many cycles.
 //
 // The cycle's settings come from a small JSON object (a flat set of keys whose values
 // are numbers, strings or arrays of numbers); unknown keys are refused.
@@ -43,7 +44,8 @@ struct Settings {
     int anneal_n_hb = -1, anneal_n_or = -1;
     int measure = 1;
     int streams = 1;
-    int unroll = 8;  // cycles per graph of the unrolled form (1: single-cycle graphs only)
+    int split = 1;   // parts of consecutive samples per ensemble, each on a stream of its own
+    int unroll = 16;  // the longest graph: the largest power of two <= unroll cycles
     double eps = 0.0;
     std::vector<double> eps_pairs;  // per pair of every ensemble, ensembles in order
     std::vector<int> path, block_threads, replicas_per_block, flags;  // one value or one per ensemble
@@ -176,6 +178,7 @@ hsg_status parse(const char* json, Settings& s) {
                 else if (key == "anneal_n_or") ok = as_int(v, s.anneal_n_or);
                 else if (key == "measure") ok = as_int(v, s.measure);
                 else if (key == "streams") ok = as_int(v, s.streams);
+                else if (key == "split") ok = as_int(v, s.split);
                 else if (key == "unroll") ok = as_int(v, s.unroll);
                 else if (key == "eps") {
                     if (v.size() == 1) s.eps = v[0];
@@ -211,10 +214,49 @@ struct Plan {
     int next_parity = 0;
     int device = 0;
     double* eps_dev = nullptr;  // per-pair cooling / heating parameters (library-owned)
-    // [0], [1]: one cycle starting with exchange parity 0 / 1; [2], [3]: `unroll` cycles
-    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    // [2 j + p]: 2^j cycles, the first with exchange parity p (p = 0 only unless the
+    // plan alternates), j < n_sizes
+    static constexpr int kMaxSizes = 9;
+    int n_sizes = 1;
+    hipGraphExec_t exec[2 * kMaxSizes] = {};
+    hipGraph_t graph[2 * kMaxSizes] = {};
 };
+
+// Samples [s0, s0 + h) of ensemble e as an ensemble of their own: the same arrays at
+// the samples' offsets (layouts of the header: spins [S][C][R][3][2][N/2], couplings
+// [S][3][2][N/2], per-slot arrays [S][C][R], per-chain [S][C], per-pair [S][C][R-1][2],
+// Q [S][R][3][3], chi [S][R]) and the stream offsets advanced, so that every random
+// number, and with it every result, is the one of the whole ensemble.  The parts of a
+// split plan use no scratch (the cycles allowed to split touch none).
+hsg_ensemble sub_ensemble(const hsg_ensemble& e, int s0, int h) {
+    hsg_ensemble p = e;
+    const size_t C = static_cast<size_t>(e.n_chains), R = static_cast<size_t>(e.n_temps);
+    const size_t N = static_cast<size_t>(e.L) * e.L * e.L, ts = e.precision == HSG_FP64 ? 8 : 4;
+    const size_t chain0 = static_cast<size_t>(s0) * C, slot0 = chain0 * R;
+    auto at = [](auto* ptr, size_t n) { return ptr ? ptr + n : ptr; };
+    p.n_samples = h;
+    p.sample_base = e.sample_base + static_cast<uint32_t>(s0);
+    p.chain_base = e.chain_base + static_cast<uint32_t>(chain0);
+    p.slot_base = e.slot_base + static_cast<uint32_t>(slot0);
+    p.spins = e.spins ? static_cast<void*>(static_cast<unsigned char*>(e.spins) + slot0 * 3 * N * ts) : nullptr;
+    p.couplings = e.couplings
+                      ? static_cast<void*>(static_cast<unsigned char*>(e.couplings) + static_cast<size_t>(s0) * 3 * N * ts)
+                      : nullptr;
+    p.temp_of_slot = at(e.temp_of_slot, slot0);
+    p.slot_of_temp = at(e.slot_of_temp, slot0);
+    p.energy = at(e.energy, slot0);
+    p.sweep_ctr = at(e.sweep_ctr, slot0);
+    p.swap_ctr = at(e.swap_ctr, chain0);
+    p.swap_stats = at(e.swap_stats, chain0 * (R - 1) * 2);
+    p.rt_state = at(e.rt_state, slot0);
+    p.rt_trips = at(e.rt_trips, slot0);
+    p.work = at(e.work, chain0 * (R - 1) * 2);
+    p.Q = at(e.Q, static_cast<size_t>(s0) * R * 9);
+    p.chi = at(e.chi, static_cast<size_t>(s0) * R);
+    p.e_temp = at(e.e_temp, slot0);
+    p.scratch = nullptr;
+    return p;
+}
 
 // One cycle of ensemble i on stream st: sweep and measurement, then the exchange.
 hsg_status enqueue_cycle(const Plan& pl, int i, int parity, hipStream_t st) {
@@ -316,7 +358,7 @@ void release(Plan* pl) {
     int cur = 0;
     const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != pl->device;
     if (switch_dev) (void)hipSetDevice(pl->device);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 2 * Plan::kMaxSizes; ++k) {
         if (pl->exec[k]) (void)hipGraphExecDestroy(pl->exec[k]);
         if (pl->graph[k]) (void)hipGraphDestroy(pl->graph[k]);
     }
@@ -349,6 +391,9 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
     };
     if (s.pairing < -1 || s.pairing > 2) return bad("pairing must be -1 (alternate), 0, 1 or 2");
     if (s.unroll < 1 || s.unroll > 256) return bad("unroll must be in [1, 256]");
+    if (s.split < 1 || s.split > 16) return bad("split must be in [1, 16]");
+    if (s.split > 1 && s.exchange != 0 && s.exchange != 4)
+        return bad("split needs the plain exchange or none (the other exchanges use the ensembles' scratch)");
     if (s.exchange == 1 && s.pairing >= 0) return bad("the annealed exchange alternates even and odd pairs (pairing -1)");
     if (s.n_hb < 0 || s.n_hb > 127 || s.n_or < 0 || s.n_hb + s.n_or < 1) return bad("need 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1");
     if (!(s.eps >= 0.0)) return bad("eps must be >= 0");
@@ -373,6 +418,32 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         pl->tune[i] = t;
         pl->tuned[i] = t.path != 0 || t.block_threads != 0 || t.replicas_per_block != 0 || t.flags != 0;
     }
+    if (s.split > 1) {
+        // each ensemble of at least two samples as `split` parts of consecutive samples
+        // (as equal as the count allows), each captured on a stream of its own: a
+        // part's exchange and the start and end of its launches overlap the other
+        // parts' sweeps.  Allowed for the LDS-resident sweeps (L <= 16), which, like the
+        // plain exchange, use no scratch.
+        std::vector<hsg_ensemble> parts;
+        std::vector<hsg_tuning> ptune;
+        std::vector<bool> ptuned;
+        for (int i = 0; i < n_ens; ++i) {
+            const hsg_ensemble& e = ens[i];
+            const int path = pl->tune[i].path;
+            if (e.L > 16 || (path != 0 && path != 3 && path != 6)) return bad("split needs LDS-resident sweeps (L <= 16; path 0, 3 or 6)");
+            const int k = e.n_samples < s.split ? (e.n_samples > 0 ? e.n_samples : 1) : s.split;
+            for (int q = 0; q < k; ++q) {
+                const int s0 = static_cast<int>(static_cast<long long>(e.n_samples) * q / k);
+                const int s1 = static_cast<int>(static_cast<long long>(e.n_samples) * (q + 1) / k);
+                parts.push_back(k > 1 ? sub_ensemble(e, s0, s1 - s0) : e);
+                ptune.push_back(pl->tune[i]);
+                ptuned.push_back(pl->tuned[i]);
+            }
+        }
+        pl->ens = parts;
+        pl->tune = ptune;
+        pl->tuned = ptuned;
+    }
     hipError_t err = hipGetDevice(&pl->device);
     if (err != hipSuccess) {
         delete pl;
@@ -388,11 +459,14 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
             return plan_fail(HSG_ERR_DEVICE, "plan: per-pair eps: %s", hipGetErrorString(err));
         }
     }
-    // the exchange parity of the first cycle is 0; alternating plans keep a second graph
-    r = capture(*pl, 0, 1, 0);
-    if (r == HSG_OK && pl->alternating) r = capture(*pl, 1, 1, 1);
-    if (r == HSG_OK && s.unroll > 1) r = capture(*pl, 0, s.unroll, 2);
-    if (r == HSG_OK && s.unroll > 1 && pl->alternating) r = capture(*pl, 1, s.unroll, 3);
+    // graphs of 1, 2, 4, ... cycles up to the largest power of two <= unroll, so that a
+    // run of n cycles is at most log2 graph launches (each launch drains the streams
+    // before the next can start); alternating plans keep one per starting parity
+    while (pl->n_sizes < Plan::kMaxSizes && (2 << (pl->n_sizes - 1)) <= s.unroll) ++pl->n_sizes;
+    for (int j = 0; j < pl->n_sizes && r == HSG_OK; ++j) {
+        r = capture(*pl, 0, 1 << j, 2 * j);
+        if (r == HSG_OK && pl->alternating) r = capture(*pl, 1, 1 << j, 2 * j + 1);
+    }
     if (r != HSG_OK) {
         release(pl);
         return r;
@@ -407,16 +481,15 @@ hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream) {
     if (n_cycles < 0) return plan_fail(HSG_ERR_INVALID, "plan: n_cycles must be >= 0");
     Plan* pl = static_cast<Plan*>(plan);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int U = pl->set.unroll;
     int left = n_cycles;
     while (left > 0) {
-        const bool big = U > 1 && left >= U;
-        const int g = (big ? 2 : 0) + (pl->alternating ? pl->next_parity : 0);
+        int j = pl->n_sizes - 1;  // the longest graph that fits what is left
+        while ((1 << j) > left) --j;
+        const int g = 2 * j + (pl->alternating ? pl->next_parity : 0);
         const hipError_t err = hipGraphLaunch(pl->exec[g], st);
         if (err != hipSuccess) return plan_fail(HSG_ERR_DEVICE, "plan run: %s", hipGetErrorString(err));
-        const int done = big ? U : 1;
-        if (pl->alternating) pl->next_parity ^= (done & 1);
-        left -= done;
+        if (pl->alternating) pl->next_parity ^= ((1 << j) & 1);
+        left -= 1 << j;
     }
     hsg::set_last_error("");
     return HSG_OK;

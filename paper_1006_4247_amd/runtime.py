@@ -33,10 +33,13 @@ class PTRun:
     tuning dict (or None) per ensemble.  concurrent: size classes one after another on
     the current stream (False), each on a stream of its own so that their kernels
     overlap (True), or whichever of the two runs the cycle faster ('auto', timed on
-    the run's own steps)."""
+    the run's own steps).  split: in captured cycles (plans), each ensemble runs as
+    `split` parts of consecutive samples on streams of their own, so that one part's
+    exchange and launch edges overlap another's sweep; the results are the same bit for
+    bit (plain exchange or none, L <= 16)."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
-                 series_len=0, tunings=None, anneal_sweep=None, eps=0.0, concurrent=False):
+                 series_len=0, tunings=None, anneal_sweep=None, eps=0.0, concurrent=False, split=1):
         if mode not in ("plain", "anneal", "decimate", "coolheat"):
             raise ValueError("mode must be 'plain', 'anneal', 'decimate' or 'coolheat'")
         # cooling / heating parameter: one number, R - 1 per-pair values shared by the
@@ -58,6 +61,9 @@ class PTRun:
             per = list(eps) if nested else [eps] * len(self.ens)
             self.eps_of = [e.eps_pairs_tensor(x) for e, x in zip(self.ens, per)]
         self.n_hb, self.n_or = n_hb, n_or
+        self.split = int(split)
+        if self.split < 1:
+            raise ValueError("split must be >= 1")
         self.mode = mode
         self.pairing = pairing
         self.measure = measure
@@ -183,7 +189,9 @@ class PTRun:
                 st["eps"] = float(self.eps)
             else:
                 st["eps"] = [float(v) for t in self.eps_of for v in t.detach().cpu().numpy()]
-        st["streams"] = int(self.concurrent)
+        st["streams"] = int(self.concurrent or self.split > 1)
+        if self.split > 1:
+            st["split"] = self.split
         if any(t is not None for t in self.tunings):
             for k in ("path", "block_threads", "replicas_per_block"):
                 st[k] = [int((t or {}).get(k, 0)) for t in self.tunings]

@@ -124,3 +124,46 @@ def test_plan_per_pair_eps_and_tuned_paths():
     for x, y in zip(_state(a), _state(b)):
         for name in x:
             assert np.array_equal(x[name], y[name]), name
+
+
+SPLIT_SHAPES = [(16, 5, 2, 6, "fp32"), (8, 3, 2, 4, "fp64"), (4, 1, 2, 3, "fp32")]
+
+
+@pytest.mark.parametrize("split", [2, 3, 16])
+@pytest.mark.parametrize("exchange", ["plain", "none"])
+def test_split_plan_equals_eager_cycles(split, exchange):
+    """A split plan runs each ensemble as parts of consecutive samples (uneven parts, more
+    parts asked for than samples, a one-sample ensemble left whole), each on a stream of
+    its own: n replayed cycles equal n eager cycles of the whole ensembles bit for bit."""
+    def batch():
+        out, sb, cb, qb = [], 0, 0, 0
+        for L, S, C, R, prec in SPLIT_SHAPES:
+            e = hsg.Ensemble(L, S, C, hsg.geometric_betas(1.0, 4.0, R), 0x9A13, precision=prec,
+                             sample_base=sb, chain_base=cb, slot_base=qb)
+            e.init_couplings()
+            e.init_spins()
+            sb, cb, qb = sb + S, cb + S * C, qb + S * C * R
+            out.append(e)
+        torch.cuda.synchronize()
+        return out
+    a, b = batch(), batch()
+    settings = {"exchange": exchange, "split": split, "unroll": 4}
+    descs = (_abi.HsgEnsemble * len(b))(*[e.desc for e in b])
+    plan = ctypes.c_void_p()
+    _abi.check(_abi.lib().hsg_plan_create(descs, len(b), json.dumps(settings).encode(), ctypes.byref(plan)))
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    try:
+        for n in (1, 9):
+            for _ in range(n):
+                for e in a:
+                    e.sweep_measure(1, 1, 3)
+                    if exchange == "plain":
+                        e.swap(0)
+            _abi.check(_abi.lib().hsg_plan_run(plan, n, stream))
+            for k, (x, y) in enumerate(zip(_state(a), _state(b))):
+                for name in x:
+                    assert np.array_equal(x[name], y[name]), (split, exchange, k, name, n)
+    finally:
+        _abi.lib().hsg_plan_destroy(plan)
+    for e in a + b:
+        e.check()
