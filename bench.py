@@ -788,8 +788,9 @@ _T0 = time.perf_counter()
 
 def headline(torch, hsg, w, steps, warmup, clock_warmup_s, fused_ok=True, split=2):
     """The workload's step (sweep of every replica, measurement, plain exchange of all
-    pairs ascending) as the library's captured cycle (a plan: one graph launch per step),
-    timed over exactly `steps` replays after `warmup` untimed ones; before those, the
+    pairs ascending) as the library's captured cycle (a plan: graphs of up to 16 cycles
+    per launch; the samples as `split` parts on streams of their own), timed over
+    exactly `steps` replays after `warmup` untimed ones; before those, the
     cycle is replayed for about `clock_warmup_s` seconds so that the chip runs at its
     steady clock.  The dominant kernel's average duration is then taken from HIP events
     around a batch of back-to-back sweep launches on the same stream."""
