@@ -633,9 +633,10 @@ def uneven_study(torch, hsg, steps, warm=20):
     (LDS-resident classes: the parity-1 half of every replica read and all of it written
     once per sweep, couplings once; streaming classes, one launch per half-sweep: per
     half-sweep the updated half read and written and the other half read, couplings once
-    per sample; wavefront: one read and one write per lattice sweep).  Three forms: the
+    per sample; wavefront: one read and one write per lattice sweep).  Four forms: the
     library's default kernels with the classes one after another, the same with each
-    class on its own stream, and the autotuner's kernels and order; and, for the sweeps
+    class on its own stream, the streaming classes one after another beside the
+    LDS-resident ones, and the autotuner's kernels and order; and, for the sweeps
     alone, one persistent launch over all classes (tuning path 5) against the classes'
     sweeps one after another."""
     import ctypes
@@ -646,8 +647,11 @@ def uneven_study(torch, hsg, steps, warm=20):
         e.init_spins()
     out = {"study": "uneven-batch", "chains": 2, "steps": steps,
            "data": "synthetic (Gaussian J_xy and random unit spins from Philox, seed %#x)" % UNEVEN["seed"]}
+    # the streaming classes (HBM-bound) one after another on one stream, so that each has
+    # the MALL to itself, and the LDS-resident classes (compute-bound) beside them on another
+    grouped = [1 if e.L <= 16 else 0 for e in ens]
     for key, tun, conc in (("default_kernels_in_sequence", None, False), ("default_kernels_concurrent", None, True),
-                           ("autotuned", "auto", "auto")):
+                           ("streaming_beside_resident", None, grouped), ("autotuned", "auto", "auto")):
         run = runtime.PTRun(ens, 1, 3, mode="plain", pairing=0, tunings=tun, concurrent=conc)
         run.step(warm)
         run.capture()
@@ -675,7 +679,7 @@ def uneven_study(torch, hsg, steps, warm=20):
             classes.append({"L": e.L, "samples": e.S, "temperatures": e.R, "tuning": t or "default",
                             "spin_MB": round(slots * 3 * N * 4 / 1e6, 1)})
         gbs = nbytes / dt / 1e9
-        out[key] = {"classes": classes, "concurrent": run.concurrent,
+        out[key] = {"classes": classes, "concurrent": run.concurrent if run.groups is None else run.groups,
                     "spin_MB_total": round(sum(c["spin_MB"] for c in classes), 1),
                     "site_updates_per_ns": round(upd / dt / 1e9, 2), "ms_per_step": round(dt / steps * 1e3, 4),
                     "sweep_algorithmic_hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}

@@ -296,6 +296,9 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
  *   "path", "block_threads", "replicas_per_block", "flags": hsg_tuning fields, one
  *          value or an array with one per ensemble
  *   "streams": 0 to capture all ensembles on one stream (default 1)
+ *   "stream": one capture-stream index in [0, n_ens) per ensemble: ensembles with the
+ *             same index run one after another on one stream, the streams side by side
+ *             (default: a stream per ensemble); not with "split"
  *   "split": k in [1, 16] (default 1): each ensemble of at least two samples runs as k
  *            parts of consecutive samples, each on a capture stream of its own, so that
  *            one part's exchange and launch edges overlap another's sweep; results are

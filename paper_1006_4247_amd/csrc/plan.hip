@@ -45,6 +45,7 @@ struct Settings {
     int measure = 1;
     int streams = 1;
     int split = 1;   // parts of consecutive samples per ensemble, each on a stream of its own
+    std::vector<int> stream_of;  // capture stream of each ensemble (default: one each)
     int unroll = 16;  // the longest graph: the largest power of two <= unroll cycles
     double eps = 0.0;
     std::vector<double> eps_pairs;  // per pair of every ensemble, ensembles in order
@@ -179,6 +180,7 @@ hsg_status parse(const char* json, Settings& s) {
                 else if (key == "measure") ok = as_int(v, s.measure);
                 else if (key == "streams") ok = as_int(v, s.streams);
                 else if (key == "split") ok = as_int(v, s.split);
+                else if (key == "stream") ok = as_ints(v, s.stream_of);
                 else if (key == "unroll") ok = as_int(v, s.unroll);
                 else if (key == "eps") {
                     if (v.size() == 1) s.eps = v[0];
@@ -210,6 +212,7 @@ struct Plan {
     Settings set;
     std::vector<hsg_tuning> tune;
     std::vector<bool> tuned;
+    std::vector<int> group;  // capture stream of each ensemble of the plan
     bool alternating = false;
     int next_parity = 0;
     int device = 0;
@@ -291,10 +294,13 @@ hsg_status enqueue_cycle(const Plan& pl, int i, int parity, hipStream_t st) {
 // (alternating from there for alternating plans), into pl.graph/exec[slot].
 hsg_status capture(Plan& pl, int parity, int n_cyc, int slot) {
     const int n = static_cast<int>(pl.ens.size());
-    const bool fork = pl.set.streams != 0 && n > 1;
+    int n_side = 0;
+    if (pl.set.streams != 0)
+        for (int g : pl.group) n_side = g + 1 > n_side ? g + 1 : n_side;
+    const bool fork = n_side > 1;
     hipStream_t cap = nullptr;
-    std::vector<hipStream_t> side(fork ? n : 0, nullptr);
-    std::vector<hipEvent_t> join(fork ? n : 0, nullptr);
+    std::vector<hipStream_t> side(fork ? n_side : 0, nullptr);
+    std::vector<hipEvent_t> join(fork ? n_side : 0, nullptr);
     hipEvent_t start = nullptr;
     hsg_status result = HSG_OK;
     hipError_t err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
@@ -308,14 +314,11 @@ hsg_status capture(Plan& pl, int parity, int n_cyc, int slot) {
         result = plan_fail(HSG_ERR_DEVICE, "plan capture setup: %s", hipGetErrorString(err));
     } else {
         if (fork) err = hipEventRecord(start, cap);
-        // each ensemble's cycles follow one another on its stream; the streams join at the end
+        for (size_t g = 0; g < side.size() && err == hipSuccess; ++g) err = hipStreamWaitEvent(side[g], start, 0);
+        // each ensemble's cycles follow one another on its stream (ensembles that share a
+        // stream one after another, in order); the streams join at the end
         for (int i = 0; i < n && err == hipSuccess && result == HSG_OK; ++i) {
-            hipStream_t st = cap;
-            if (fork) {
-                st = side[i];
-                err = hipStreamWaitEvent(st, start, 0);
-                if (err != hipSuccess) break;
-            }
+            hipStream_t st = fork ? side[pl.group[i]] : cap;
             int par = parity;
             for (int c = 0; c < n_cyc && result == HSG_OK; ++c) {
                 result = enqueue_cycle(pl, i, par, st);
@@ -326,10 +329,10 @@ hsg_status capture(Plan& pl, int parity, int n_cyc, int slot) {
                 plan_fail(result, "plan capture, ensemble %d: %s", i, why.c_str());
                 break;
             }
-            if (fork) {
-                err = hipEventRecord(join[i], st);
-                if (err == hipSuccess) err = hipStreamWaitEvent(cap, join[i], 0);
-            }
+        }
+        for (size_t g = 0; g < side.size() && err == hipSuccess && result == HSG_OK; ++g) {
+            err = hipEventRecord(join[g], side[g]);
+            if (err == hipSuccess) err = hipStreamWaitEvent(cap, join[g], 0);
         }
         hipGraph_t g = nullptr;
         const hipError_t end = hipStreamEndCapture(cap, &g);
@@ -443,6 +446,19 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         pl->ens = parts;
         pl->tune = ptune;
         pl->tuned = ptuned;
+    }
+    // capture streams: one per ensemble (and per part of a split ensemble), or the
+    // caller's grouping ("stream": one index per ensemble; ensembles of one group run one
+    // after another on one stream, the groups side by side)
+    if (!s.stream_of.empty()) {
+        if (s.split > 1) return bad("stream and split do not combine");
+        if (static_cast<int>(s.stream_of.size()) != n_ens) return bad("stream needs one index per ensemble");
+        for (int g : s.stream_of)
+            if (g < 0 || g >= n_ens) return bad("stream indices must be in [0, number of ensembles)");
+        pl->group = s.stream_of;
+    } else {
+        pl->group.resize(pl->ens.size());
+        for (size_t i = 0; i < pl->ens.size(); ++i) pl->group[i] = static_cast<int>(i);
     }
     hipError_t err = hipGetDevice(&pl->device);
     if (err != hipSuccess) {

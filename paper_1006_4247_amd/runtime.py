@@ -32,8 +32,9 @@ class PTRun:
     autotuner's fastest sweep variant per ensemble shape, cached per device), or one
     tuning dict (or None) per ensemble.  concurrent: size classes one after another on
     the current stream (False), each on a stream of its own so that their kernels
-    overlap (True), or whichever of the two runs the cycle faster ('auto', timed on
-    the run's own steps).  split: in captured cycles (plans), each ensemble runs as
+    overlap (True), whichever of the two runs the cycle faster ('auto', timed on
+    the run's own steps), or a list with one stream index per ensemble (the ensembles
+    of one index one after another on one stream, the streams side by side).  split: in captured cycles (plans), each ensemble runs as
     `split` parts of consecutive samples on streams of their own, so that one part's
     exchange and launch edges overlap another's sweep; the results are the same bit for
     bit (plain exchange or none, L <= 16)."""
@@ -76,10 +77,19 @@ class PTRun:
         self.anneal_sweep = anneal_sweep or (n_hb, n_or)
         dev = self.ens[0].device
         self.device = dev
-        if concurrent not in (False, True, "auto"):
-            raise ValueError("concurrent must be False, True or 'auto'")
+        # stream groups: a list with one index per ensemble puts the ensembles of one index
+        # one after another on one stream and the groups side by side
+        self.groups = None
+        if isinstance(concurrent, (list, tuple)):
+            if len(concurrent) != len(self.ens) or any(int(g) < 0 or int(g) >= len(self.ens) for g in concurrent):
+                raise ValueError("concurrent as a list needs one stream index in [0, n) per ensemble")
+            self.groups = [int(g) for g in concurrent]
+            concurrent = True
+        elif concurrent not in (False, True, "auto"):
+            raise ValueError("concurrent must be False, True, 'auto' or one stream index per ensemble")
         self.concurrent = bool(concurrent) and len(self.ens) > 1
-        self.streams = [torch.cuda.Stream(device=dev) for _ in self.ens] if len(self.ens) > 1 else []
+        n_streams = (max(self.groups) + 1) if self.groups else len(self.ens)
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)] if len(self.ens) > 1 else []
         self.parity = 0
         self.steps_done = 0
         self.graph = None
@@ -95,7 +105,9 @@ class PTRun:
         for e in self.ens:
             e.stream = None  # steps run on the current stream, or on self.streams when concurrent
         if concurrent == "auto" and len(self.ens) > 1 and not self.series_len:
-            self.concurrent = self._pick_concurrency()
+            choice = self._pick_concurrency()
+            self.groups = choice if isinstance(choice, list) else None
+            self.concurrent = bool(choice)
 
     # ------------------------------------------------------------ one step
     def _step_one(self, i, parity, slot):
@@ -126,20 +138,37 @@ class PTRun:
         cur = torch.cuda.current_stream(self.device)
         for s in self.streams:
             s.wait_stream(cur)
-        for i, s in enumerate(self.streams):
-            with torch.cuda.stream(s):
+        for i in range(len(self.ens)):
+            with torch.cuda.stream(self.streams[self.groups[i] if self.groups else i]):
                 fn(i)
         for s in self.streams:
             cur.wait_stream(s)
 
+    def kind_groups(self):
+        """Stream groups by kind: the streaming classes (HBM-bound) on stream 0, one after
+        another so that each has the MALL to itself, the LDS-resident classes
+        (compute-bound) beside them on stream 1; None if the batch has one kind only."""
+        res = []
+        for e, t in zip(self.ens, self.tunings):
+            path = (t or {}).get("path", 0)
+            res.append(e.L <= 16 if not path else path in (1, 3, 6))
+        if all(res) or not any(res):
+            return None
+        return [1 if r else 0 for r in res]
+
     def _pick_concurrency(self, steps=20):
         """Autotuning of the batch's order: time captured cycles with the size classes one
-        after another and with each on its own stream (real steps of the run, counted),
-        and keep the faster."""
+        after another, with each on its own stream, and (batches of both kinds) with the
+        streaming classes on one stream beside the LDS-resident ones (real steps of the
+        run, counted), and keep the fastest.  Returns the choice for `concurrent`."""
         import time
         best, best_t = False, None
-        for conc in (False, True):
-            self.concurrent = conc
+        candidates = [False, True]
+        if self.kind_groups() is not None:
+            candidates.append(self.kind_groups())
+        for conc in candidates:
+            self.groups = conc if isinstance(conc, list) else None
+            self.concurrent = bool(conc)
             self.capture()
             self.replay(2)
             self.synchronize()
@@ -190,6 +219,8 @@ class PTRun:
             else:
                 st["eps"] = [float(v) for t in self.eps_of for v in t.detach().cpu().numpy()]
         st["streams"] = int(self.concurrent or self.split > 1)
+        if self.groups and self.concurrent:
+            st["stream"] = list(self.groups)
         if self.split > 1:
             st["split"] = self.split
         if any(t is not None for t in self.tunings):

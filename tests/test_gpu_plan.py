@@ -167,3 +167,26 @@ def test_split_plan_equals_eager_cycles(split, exchange):
         _abi.lib().hsg_plan_destroy(plan)
     for e in a + b:
         e.check()
+
+
+@pytest.mark.parametrize("groups", [[1, 0, 1], [0, 0, 0], [2, 1, 0]])
+def test_stream_groups_equal_eager_cycles(groups):
+    """Ensembles grouped onto capture streams (the ensembles of one group one after
+    another, the groups side by side): replayed cycles equal eager cycles bit for bit."""
+    a, b = _batch(0x9A14), _batch(0x9A14)
+    settings = {"exchange": "plain", "stream": groups, "unroll": 4}
+    descs = (_abi.HsgEnsemble * len(b))(*[e.desc for e in b])
+    plan = ctypes.c_void_p()
+    _abi.check(_abi.lib().hsg_plan_create(descs, len(b), json.dumps(settings).encode(), ctypes.byref(plan)))
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    try:
+        for _ in range(7):
+            for e in a:
+                e.sweep_measure(1, 1, 3)
+                e.swap(0)
+        _abi.check(_abi.lib().hsg_plan_run(plan, 7, stream))
+        for k, (x, y) in enumerate(zip(_state(a), _state(b))):
+            for name in x:
+                assert np.array_equal(x[name], y[name]), (groups, k, name)
+    finally:
+        _abi.lib().hsg_plan_destroy(plan)

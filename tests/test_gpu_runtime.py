@@ -133,3 +133,33 @@ def test_concurrency_autotuning_keeps_the_chain():
     rb.step(3)
     ra.synchronize()
     _equal(a, b)
+
+
+def test_stream_groups_in_the_runtime():
+    """A batch of both kinds: the streaming class on one stream beside the LDS-resident
+    ones (eager steps and captured cycles) continues exactly like the classes one after
+    another; concurrent='auto' also times that grouping."""
+    def mixed():
+        ens = runtime.uneven_batch([8, 24, 12], [2, 1, 2], [4, 4, 5], SEED)
+        _init(ens)
+        return ens
+    a, b = mixed(), mixed()
+    ra = runtime.PTRun(a, concurrent=[1, 0, 1])
+    assert ra.kind_groups() == [1, 0, 1]
+    rb = runtime.PTRun(b)
+    ra.step(2)
+    rb.step(2)
+    ra.capture()
+    ra.replay(5)
+    rb.step(5)
+    ra.synchronize()
+    _equal(a, b)
+    c, d = mixed(), mixed()
+    rc = runtime.PTRun(c, concurrent="auto")
+    assert rc.groups in (None, [1, 0, 1])
+    rd = runtime.PTRun(d)
+    rd.step(rc.steps_done)
+    rc.step(3)
+    rd.step(3)
+    rc.synchronize()
+    _equal(c, d)
