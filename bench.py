@@ -445,7 +445,7 @@ STUDY_DEFAULT = ("standard", "decimation", "coolheat")
 
 
 def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, methods=STUDY_DEFAULT, n_temps=0,
-                       compact=False):
+                       compact=False, split=2):
     """Standard, decimated and cooling / heating tempering (or a subset, `methods`; with
     "coolheat_pairs", cooling / heating with its parameter tuned per pair; with
     "learned", annealed exchanges whose protocols the learned schedule picks to minimise
@@ -458,7 +458,8 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
     T_min (window c = 4), and, with standard tempering among the methods, the per-set
     speed-ups over it averaged over the sets (Table II), with their standard errors;
     per GPU-second they are divided by the relative GPU time of a cycle, timed from the
-    library's captured cycle of each method."""
+    library's captured cycle of each method (at L <= 16 with `split` > 1 the coupling
+    sets as that many parts on streams of their own, for every method alike)."""
     from paper_1006_4247_amd import analysis, runtime
     from paper_1006_4247_amd import schedule as sch
 
@@ -482,7 +483,7 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
 
     def cycle_ms(e, mode, eps, n=300, **kw):
         # GPU time per cycle from the library's captured cycle
-        run = runtime.PTRun([e], 1, n_or, mode=mode, eps=eps, **kw)
+        run = runtime.PTRun([e], 1, n_or, mode=mode, eps=eps, split=split if L <= 16 else 1, **kw)
         run.capture()
         run.replay(20)
         run.synchronize()
@@ -577,7 +578,9 @@ def paper_ladder_study(torch, hsg, L, S, cycles, equil, seed=0x100642470010, met
 
     out = {"study": "paper-ladder", "L": L, "coupling_sets": S, "chains": C, "temperatures": R,
            "T": [PAPER_T_MIN, PAPER_T_MAX], "sweep": "1 HB + %d OR" % n_or, "exchange": "all pairs ascending",
-           "cycles": cycles, "equilibration_cycles": equil, "data": "synthetic Gaussian coupling sets from Philox"}
+           "cycles": cycles, "equilibration_cycles": equil, "data": "synthetic Gaussian coupling sets from Philox",
+           "cycle_timing": "captured cycle" + (", the sets as %d parts on streams of their own" % split
+                                               if split > 1 and L <= 16 else ", the sets as one ensemble")}
     std = res.get("standard")
     for m, r in res.items():
         d = {"acceptance_per_set": q(r["acc_set"]), "acceptance_per_pair": q(r["acc_pair"]),
@@ -926,6 +929,8 @@ def main():
                     help="only run the study of standard / decimated / cooling-heating tempering on "
                          "the paper's ladder for L (16, 24 or 32) and print its JSON line")
     ap.add_argument("--study-sets", type=int, default=64, help="coupling sets of the paper-ladder study")
+    ap.add_argument("--study-split", type=int, default=2,
+                    help="parts of the coupling sets on streams of their own in the timed cycles (every method)")
     ap.add_argument("--study-cycles", type=int, nargs=2, default=[10000, 20000], metavar=("EQUIL", "MEASURE"),
                     help="equilibration and measurement cycles of the paper-ladder study")
     ap.add_argument("--study-methods", nargs="+", choices=STUDY_METHODS, default=list(STUDY_DEFAULT),
@@ -970,7 +975,8 @@ def main():
             sys.exit(2)
         print(json.dumps(paper_ladder_study(torch, hsg, args.paper_ladder, args.study_sets,
                                             args.study_cycles[1], args.study_cycles[0],
-                                            methods=tuple(args.study_methods), n_temps=args.study_temps)),
+                                            methods=tuple(args.study_methods), n_temps=args.study_temps,
+                                            split=args.study_split)),
               flush=True)
         return
     w = WORKLOADS[args.workload]

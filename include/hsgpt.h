@@ -302,9 +302,9 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
  *   "split": k in [1, 16] (default 1): each ensemble of at least two samples runs as k
  *            parts of consecutive samples, each on a capture stream of its own, so that
  *            one part's exchange and launch edges overlap another's sweep; results are
- *            those of the whole ensemble bit for bit.  Needs the plain exchange (or
- *            none) and LDS-resident sweeps (L <= 16, path 0, 3 or 6), which use no
- *            scratch
+ *            those of the whole ensemble bit for bit.  Needs LDS-resident sweeps
+ *            (L <= 16, path 0, 3 or 6); for the exchanges that use scratch the plan
+ *            allocates the parts' scratch itself (hsg_scratch_bytes of each part)
  *   "unroll": the plan holds graphs of 1, 2, 4, ... cycles up to the largest power of
  *             two <= unroll (default 16); a run of n cycles launches the longest graphs
  *             that fit, at most about log2(n) launches, so that a graph launch (after
@@ -313,8 +313,9 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
  * descriptors: the caller's device buffers must stay allocated, and the descriptors'
  * pointers unchanged, until hsg_plan_destroy.  Creating a plan enqueues nothing on the
  * caller's streams and changes no state; it allocates the graphs (and the per-pair eps
- * copy).  A plan is used from one host thread at a time, on the device it was created
- * on; runs on one plan must not overlap.  *plan receives an opaque handle. */
+ * copy, and the split parts' scratch).  A plan is used from one host thread at a time,
+ * on the device it was created on; runs on one plan must not overlap.  *plan receives
+ * an opaque handle. */
 hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tuning_json, void** plan);
 hsg_status hsg_plan_run(void* plan, int n_cycles, void* stream);
 hsg_status hsg_plan_destroy(void* plan);

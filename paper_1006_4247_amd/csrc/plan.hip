@@ -213,6 +213,9 @@ struct Plan {
     std::vector<hsg_tuning> tune;
     std::vector<bool> tuned;
     std::vector<int> group;  // capture stream of each ensemble of the plan
+    std::vector<size_t> eps_off;  // first per-pair eps of each ensemble of the plan
+    std::vector<bool> is_part;    // a part of a split ensemble (scratch: the plan's own)
+    void* part_scratch = nullptr;  // the parts' scratch (library-owned)
     bool alternating = false;
     int next_parity = 0;
     int device = 0;
@@ -229,8 +232,8 @@ struct Plan {
 // the samples' offsets (layouts of the header: spins [S][C][R][3][2][N/2], couplings
 // [S][3][2][N/2], per-slot arrays [S][C][R], per-chain [S][C], per-pair [S][C][R-1][2],
 // Q [S][R][3][3], chi [S][R]) and the stream offsets advanced, so that every random
-// number, and with it every result, is the one of the whole ensemble.  The parts of a
-// split plan use no scratch (the cycles allowed to split touch none).
+// number, and with it every result, is the one of the whole ensemble.  Its scratch is
+// set by the plan (exchanges keep only intermediate values there within a call).
 hsg_ensemble sub_ensemble(const hsg_ensemble& e, int s0, int h) {
     hsg_ensemble p = e;
     const size_t C = static_cast<size_t>(e.n_chains), R = static_cast<size_t>(e.n_temps);
@@ -280,11 +283,7 @@ hsg_status enqueue_cycle(const Plan& pl, int i, int parity, hipStream_t st) {
     case 1: return hsg_anneal_swap(e, 1, parity, s.anneal_n_hb, s.anneal_n_or, vs);
     case 2: return hsg_decimate_swap(e, 1, pairing, vs);
     case 3:
-        if (pl.eps_dev) {
-            size_t off = 0;
-            for (int k = 0; k < i; ++k) off += static_cast<size_t>(pl.ens[k].n_temps - 1);
-            return hsg_coolheat_swap_pairs(e, 1, pairing, pl.eps_dev + off, vs);
-        }
+        if (pl.eps_dev) return hsg_coolheat_swap_pairs(e, 1, pairing, pl.eps_dev + pl.eps_off[i], vs);
         return hsg_coolheat_swap(e, 1, pairing, s.eps, vs);
     default: return HSG_OK;
     }
@@ -366,6 +365,7 @@ void release(Plan* pl) {
         if (pl->graph[k]) (void)hipGraphDestroy(pl->graph[k]);
     }
     if (pl->eps_dev) (void)hipFree(pl->eps_dev);
+    if (pl->part_scratch) (void)hipFree(pl->part_scratch);
     if (switch_dev) (void)hipSetDevice(cur);
     delete pl;
 }
@@ -395,8 +395,6 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
     if (s.pairing < -1 || s.pairing > 2) return bad("pairing must be -1 (alternate), 0, 1 or 2");
     if (s.unroll < 1 || s.unroll > 256) return bad("unroll must be in [1, 256]");
     if (s.split < 1 || s.split > 16) return bad("split must be in [1, 16]");
-    if (s.split > 1 && s.exchange != 0 && s.exchange != 4)
-        return bad("split needs the plain exchange or none (the other exchanges use the ensembles' scratch)");
     if (s.exchange == 1 && s.pairing >= 0) return bad("the annealed exchange alternates even and odd pairs (pairing -1)");
     if (s.n_hb < 0 || s.n_hb > 127 || s.n_or < 0 || s.n_hb + s.n_or < 1) return bad("need 0 <= n_hb <= 127, n_or >= 0, n_hb + n_or >= 1");
     if (!(s.eps >= 0.0)) return bad("eps must be >= 0");
@@ -429,7 +427,9 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         // plain exchange, use no scratch.
         std::vector<hsg_ensemble> parts;
         std::vector<hsg_tuning> ptune;
-        std::vector<bool> ptuned;
+        std::vector<bool> ptuned, part;
+        std::vector<size_t> poff;
+        size_t off = 0;
         for (int i = 0; i < n_ens; ++i) {
             const hsg_ensemble& e = ens[i];
             const int path = pl->tune[i].path;
@@ -441,11 +441,23 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
                 parts.push_back(k > 1 ? sub_ensemble(e, s0, s1 - s0) : e);
                 ptune.push_back(pl->tune[i]);
                 ptuned.push_back(pl->tuned[i]);
+                part.push_back(k > 1);
+                poff.push_back(off);
             }
+            off += static_cast<size_t>(e.n_temps > 0 ? e.n_temps - 1 : 0);
         }
         pl->ens = parts;
         pl->tune = ptune;
         pl->tuned = ptuned;
+        pl->is_part = part;
+        pl->eps_off = poff;
+    } else {
+        size_t off = 0;
+        for (int i = 0; i < n_ens; ++i) {
+            pl->eps_off.push_back(off);
+            pl->is_part.push_back(false);
+            off += static_cast<size_t>(ens[i].n_temps > 0 ? ens[i].n_temps - 1 : 0);
+        }
     }
     // capture streams: one per ensemble (and per part of a split ensemble), or the
     // caller's grouping ("stream": one index per ensemble; ensembles of one group run one
@@ -473,6 +485,33 @@ hsg_status hsg_plan_create(const hsg_ensemble* ens, int n_ens, const char* tunin
         if (err != hipSuccess) {
             release(pl);
             return plan_fail(HSG_ERR_DEVICE, "plan: per-pair eps: %s", hipGetErrorString(err));
+        }
+    }
+    // the parts of split ensembles get scratch of their own (one library-owned buffer,
+    // cleared once) where the exchange uses scratch: the annealed exchange's candidates,
+    // the decimated exchange's partial sums, the cooling / heating exchange's candidates
+    // and flags, all of them intermediate values within one call
+    if (s.split > 1 && (s.exchange == 1 || s.exchange == 2 || s.exchange == 3)) {
+        size_t total = 0;
+        std::vector<size_t> at(pl->ens.size(), 0);
+        for (size_t i = 0; i < pl->ens.size(); ++i) {
+            if (!pl->is_part[i]) continue;
+            at[i] = total;
+            total += (hsg_scratch_bytes(&pl->ens[i]) + 255) & ~static_cast<size_t>(255);
+        }
+        if (total > 0) {
+            hipStream_t z = nullptr;
+            err = hipMalloc(&pl->part_scratch, total);
+            if (err == hipSuccess) err = hipStreamCreateWithFlags(&z, hipStreamNonBlocking);
+            if (err == hipSuccess) err = hipMemsetAsync(pl->part_scratch, 0, total, z);
+            if (err == hipSuccess) err = hipStreamSynchronize(z);
+            if (z) (void)hipStreamDestroy(z);
+            if (err != hipSuccess) {
+                release(pl);
+                return plan_fail(HSG_ERR_DEVICE, "plan: scratch of the split parts: %s", hipGetErrorString(err));
+            }
+            for (size_t i = 0; i < pl->ens.size(); ++i)
+                if (pl->is_part[i]) pl->ens[i].scratch = static_cast<unsigned char*>(pl->part_scratch) + at[i];
         }
     }
     // graphs of 1, 2, 4, ... cycles up to the largest power of two <= unroll, so that a

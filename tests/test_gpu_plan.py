@@ -127,38 +127,60 @@ def test_plan_per_pair_eps_and_tuned_paths():
 
 
 SPLIT_SHAPES = [(16, 5, 2, 6, "fp32"), (8, 3, 2, 4, "fp64"), (4, 1, 2, 3, "fp32")]
+SPLIT_EXCHANGES = ["plain", "none", "decimate", "coolheat", "coolheat_pairs", "anneal"]
 
 
 @pytest.mark.parametrize("split", [2, 3, 16])
-@pytest.mark.parametrize("exchange", ["plain", "none"])
+@pytest.mark.parametrize("exchange", SPLIT_EXCHANGES)
 def test_split_plan_equals_eager_cycles(split, exchange):
     """A split plan runs each ensemble as parts of consecutive samples (uneven parts, more
     parts asked for than samples, a one-sample ensemble left whole), each on a stream of
-    its own: n replayed cycles equal n eager cycles of the whole ensembles bit for bit."""
+    its own, the parts' scratch the plan's own: n replayed cycles equal n eager cycles of
+    the whole ensembles bit for bit, for every exchange."""
+    K_max = 3 if exchange == "anneal" else 0
+
     def batch():
         out, sb, cb, qb = [], 0, 0, 0
         for L, S, C, R, prec in SPLIT_SHAPES:
-            e = hsg.Ensemble(L, S, C, hsg.geometric_betas(1.0, 4.0, R), 0x9A13, precision=prec,
+            e = hsg.Ensemble(L, S, C, hsg.geometric_betas(1.0, 4.0, R), 0x9A13, precision=prec, K_max=K_max,
                              sample_base=sb, chain_base=cb, slot_base=qb)
             e.init_couplings()
             e.init_spins()
+            if K_max:
+                e.set_schedule(np.array([1, 3, 0, 2, 1][:R - 1], dtype=np.int32))
             sb, cb, qb = sb + S, cb + S * C, qb + S * C * R
             out.append(e)
         torch.cuda.synchronize()
         return out
     a, b = batch(), batch()
-    settings = {"exchange": exchange, "split": split, "unroll": 4}
+    eps_pairs = [list(np.linspace(0.002, 0.006, e.R - 1)) for e in a]
+    if exchange == "coolheat_pairs":
+        settings = {"exchange": "coolheat", "eps": [v for x in eps_pairs for v in x]}
+    elif exchange == "coolheat":
+        settings = {"exchange": "coolheat", "eps": 0.004}
+    else:
+        settings = {"exchange": exchange}
+    settings.update(split=split, unroll=4)
+    if exchange == "anneal":
+        settings.update(anneal_n_hb=1, anneal_n_or=1)
     descs = (_abi.HsgEnsemble * len(b))(*[e.desc for e in b])
     plan = ctypes.c_void_p()
     _abi.check(_abi.lib().hsg_plan_create(descs, len(b), json.dumps(settings).encode(), ctypes.byref(plan)))
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     try:
+        parity = 0
         for n in (1, 9):
             for _ in range(n):
-                for e in a:
-                    e.sweep_measure(1, 1, 3)
-                    if exchange == "plain":
-                        e.swap(0)
+                for k, e in enumerate(a):
+                    if exchange == "none":
+                        e.sweep_measure(1, 1, 3)
+                    elif exchange == "coolheat_pairs":
+                        e.sweep_measure(1, 1, 3)
+                        e.coolheat_swap(np.array(eps_pairs[k]), parity + 1)
+                    else:
+                        _eager_cycle(e, settings, parity)
+                if exchange != "plain" and exchange != "none":
+                    parity ^= 1
             _abi.check(_abi.lib().hsg_plan_run(plan, n, stream))
             for k, (x, y) in enumerate(zip(_state(a), _state(b))):
                 for name in x:

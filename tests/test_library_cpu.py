@@ -113,7 +113,7 @@ def test_plan_settings_are_validated_without_gpu():
            b'{"exchange": "anneal", "pairing": 0}', b'[1]', b'{"eps": [0.1, 0.2]}',
            b'{"n_hb": 0, "n_or": 0}', b'{"exchange": "coolheat", "eps": -1}', b'{"path": [1, 2]}',
            b'{"exchange": "plain"} x', b'{"split": 0}', b'{"split": 17}',
-           b'{"split": 2, "exchange": "decimate"}', b'{"split": 2, "exchange": "anneal"}',
+           b'{"split": 2, "path": 2}', b'{"split": 2, "path": 5}',
            b'{"stream": [1]}', b'{"stream": [0, 0]}', b'{"stream": [-1]}', b'{"stream": [0], "split": 2}']
     for js in bad:
         assert lib.hsg_plan_create(d, 1, js, ctypes.byref(plan)) == _abi.HSG_ERR_INVALID, js
