@@ -37,7 +37,7 @@ class PTRun:
     of one index one after another on one stream, the streams side by side).  split: in captured cycles (plans), each ensemble runs as
     `split` parts of consecutive samples on streams of their own, so that one part's
     exchange and launch edges overlap another's sweep; the results are the same bit for
-    bit (plain exchange or none, L <= 16)."""
+    bit (L <= 16)."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
                  series_len=0, tunings=None, anneal_sweep=None, eps=0.0, concurrent=False, split=1):
