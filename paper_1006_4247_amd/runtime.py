@@ -34,10 +34,10 @@ class PTRun:
     the current stream (False), each on a stream of its own so that their kernels
     overlap (True), whichever of the two runs the cycle faster ('auto', timed on
     the run's own steps), or a list with one stream index per ensemble (the ensembles
-    of one index one after another on one stream, the streams side by side).  split: in captured cycles (plans), each ensemble runs as
-    `split` parts of consecutive samples on streams of their own, so that one part's
-    exchange and launch edges overlap another's sweep; the results are the same bit for
-    bit (L <= 16)."""
+    of one index one after another on one stream, the streams side by side).  split:
+    in captured cycles (plans), each ensemble runs as `split` parts of consecutive
+    samples on streams of their own, so that one part's exchange and launch edges
+    overlap another's sweep; the results are the same bit for bit (L <= 16)."""
 
     def __init__(self, ensembles, n_hb=1, n_or=3, mode="plain", pairing=None, measure=True,
                  series_len=0, tunings=None, anneal_sweep=None, eps=0.0, concurrent=False, split=1):
