@@ -501,8 +501,22 @@ hipError_t launch_anneal_decide(const hsg_ensemble& e, int parity, hipStream_t s
     return hipGetLastError();
 }
 
+// Threads per measurement workgroup beyond L = 16.  The workgroups, one per (sample,
+// temperature), are then few (8 x 32 at L = 32) and each streams a replica pair of
+// 0.3-0.8 MB, so a workgroup needs many waves to keep enough loads in flight.  The
+// size depends on L alone, so a sample range measured on its own sums in the same order.
+constexpr int kMeasureThreadsLarge = 512;
+
 hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st) {
     const int blocks = e.n_samples * e.n_temps;
+    if (e.L > 16) {
+        constexpr int NT = kMeasureThreadsLarge;
+        if (e.precision == HSG_FP64)
+            hipLaunchKernelGGL((k_measure<double, NT>), dim3(blocks), dim3(NT), 0, st, e);
+        else
+            hipLaunchKernelGGL((k_measure<float, NT>), dim3(blocks), dim3(NT), 0, st, e);
+        return hipGetLastError();
+    }
     // one (sample, temperature) per 128-thread workgroup: 1536 of them at L = 16, 64 x 24
     // (measured 26.4 us per pass against 27.3 with 256 threads and 28.1 with 512)
     if (e.precision == HSG_FP64)

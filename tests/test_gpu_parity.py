@@ -249,8 +249,11 @@ def test_swap_parity_ladder_lengths(R):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_measure_parity(prec):
-    L, S, C, R = 4, 2, 2, 3
+@pytest.mark.parametrize("L", [4, 20, 24])
+def test_measure_parity(prec, L):
+    """Q, chi and e by temperature with a scrambled chain; beyond L = 16 the measurement
+    launches 512-thread workgroups, whose loop ends in a ragged tail at L = 20 and 24."""
+    S, C, R = 2, 2, 3
     gpu, ref = make_pair(L, S, C, _betas(R), SEED + 3, prec=prec)
     perm = np.array([2, 0, 1], dtype=np.int32)
     inv = np.argsort(perm).astype(np.int32)
