@@ -251,13 +251,6 @@ __global__ void __launch_bounds__(64) k_swap(hsg_ensemble e, int pairing) {
 // trips are those of k_swap bit for bit (the same operations on the same values).
 constexpr int kSwapWaveMaxR = 64;
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFll), l);
-    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 __global__ void __launch_bounds__(64) k_swap_wave(hsg_ensemble e, int pairing) {
     const int ch = blockIdx.x;
     const int lane = threadIdx.x;

@@ -296,10 +296,38 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // ---------------------------------------------------------------- reductions
+// One lane's binary64 value, as a wave-uniform value.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFll), lane);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// The binary64 value of another lane of the same row of 16, by a DPP lane pattern.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 64 lanes of a wave (all active), every lane ending with the same bits:
+// the butterfly that adds lane l and lane l ^ m for m = 1, 2, 4, 8, 16, 32 in turn.
+// After the steps m < k every aligned group of k lanes holds one value, so any pattern
+// that pairs each group with its neighbour group adds the same two values: within a row
+// of 16 lanes the pairs come from DPP moves (quad permutations [1,0,3,2] and [2,3,0,1],
+// then the half-row and row mirrors); across rows from one lane of each row, added as
+// (row 0 + row 1) + (row 2 + row 3).  No LDS round trip.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);   // l ^ 1
+    v += dpp_f64<0x4E>(v);   // l ^ 2
+    v += dpp_f64<0x141>(v);  // half-row mirror: quads 0 and 1 of each half-row
+    v += dpp_f64<0x140>(v);  // row mirror: the two half-rows of each row
+    const double r01 = readlane_f64(v, 0) + readlane_f64(v, 16);
+    const double r23 = readlane_f64(v, 32) + readlane_f64(v, 48);
+    return r01 + r23;
 }
 
 // Deterministic block sum: fixed butterfly inside each wave, then wave partials
