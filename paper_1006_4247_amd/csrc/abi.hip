@@ -394,6 +394,17 @@ hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, i
             if (err != hipSuccess) return device(err, "sweep and measure");
             continue;
         }
+        if (n_sweeps > 0 && !use_resident(ens[i], nullptr)) {
+            // streaming sweeps: the measurement adds up the last sweep's per-tile
+            // energies itself, in place of the sweep's own finishing pass
+            int n_tiles = 0;
+            err = hsg::launch_stream_sweeps(launch_copy(ens[i]), n_sweeps, n_hb, n_or, 0, 0, nullptr,
+                                            as_stream(stream), true, &n_tiles);
+            if (err != hipSuccess) return device(err, "sweep");
+            err = hsg::launch_measure_fin(ens[i], n_tiles, n_sweeps, as_stream(stream));
+            if (err != hipSuccess) return device(err, "measure");
+            continue;
+        }
         if (n_sweeps > 0) {
             s = hsg_sweep(&ens[i], 1, n_sweeps, n_hb, n_or, stream);
             if (s != HSG_OK) return s;

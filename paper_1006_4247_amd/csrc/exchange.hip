@@ -385,8 +385,12 @@ __global__ void k_anneal_copyback(hsg_ensemble e) {
 // ---------------------------------------------------------------- measurement
 // Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between chains 0 and 1 at temperature b,
 // chi = Q:Q / N (paper Sec. II); e = H/N by temperature.  Workgroup per (sample, b).
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e) {
+// FIN: first finish a streaming sweep whose last finishing pass was left out: the
+// energy of each slot it reads from the per-tile sums (n_tiles of them, in tile
+// order, as k_stream_finalize adds them), and sweep_ctr += ctr_add.  Every slot is one
+// (sample, chain, temperature), so each is finished by exactly one workgroup.
+template <typename T, int NT, bool FIN = false>
+__global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e, int n_tiles = 0, int ctr_add = 0) {
     constexpr int NW = NT / 64;
     __shared__ double red[9 * NW];
     const int N = e.L * e.L * e.L;
@@ -394,7 +398,19 @@ __global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e) {
     const int smp = blockIdx.x / R, b = blockIdx.x % R;
     for (int c = threadIdx.x; c < C; c += NT) {
         const int slot = (smp * C + c) * R + label(e.slot_of_temp[(smp * C + c) * R + b], R, e.guard);
-        e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = e.energy[slot] / static_cast<double>(N);
+        double H;
+        if (FIN) {
+            const ScratchLayout sl = scratch_layout(e);
+            const double* part = reinterpret_cast<const double*>(static_cast<const unsigned char*>(e.scratch) + sl.partial);
+            H = 0.0;
+            for (int t = 0; t < n_tiles; ++t) H += part[static_cast<size_t>(slot) * sl.max_tiles + t];
+            if (!isfinite(H)) atomicOr(e.guard, 1);
+            e.energy[slot] = H;
+            e.sweep_ctr[slot] += static_cast<uint32_t>(ctr_add);
+        } else {
+            H = e.energy[slot];
+        }
+        e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = H / static_cast<double>(N);
     }
     if (C < 2 || e.Q == nullptr) return;  // uniform over the block
     const int s1 = (smp * C + 0) * R + label(e.slot_of_temp[(smp * C + 0) * R + b], R, e.guard);
@@ -505,17 +521,34 @@ hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st) {
     if (e.L > 16) {
         constexpr int NT = kMeasureThreadsLarge;
         if (e.precision == HSG_FP64)
-            hipLaunchKernelGGL((k_measure<double, NT>), dim3(blocks), dim3(NT), 0, st, e);
+            hipLaunchKernelGGL((k_measure<double, NT>), dim3(blocks), dim3(NT), 0, st, e, 0, 0);
         else
-            hipLaunchKernelGGL((k_measure<float, NT>), dim3(blocks), dim3(NT), 0, st, e);
+            hipLaunchKernelGGL((k_measure<float, NT>), dim3(blocks), dim3(NT), 0, st, e, 0, 0);
         return hipGetLastError();
     }
     // one (sample, temperature) per 128-thread workgroup: 1536 of them at L = 16, 64 x 24
     // (measured 26.4 us per pass against 27.3 with 256 threads and 28.1 with 512)
     if (e.precision == HSG_FP64)
-        hipLaunchKernelGGL((k_measure<double, 128>), dim3(blocks), dim3(128), 0, st, e);
+        hipLaunchKernelGGL((k_measure<double, 128>), dim3(blocks), dim3(128), 0, st, e, 0, 0);
     else
-        hipLaunchKernelGGL((k_measure<float, 128>), dim3(blocks), dim3(128), 0, st, e);
+        hipLaunchKernelGGL((k_measure<float, 128>), dim3(blocks), dim3(128), 0, st, e, 0, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_fin(const hsg_ensemble& e, int n_tiles, int ctr_add, hipStream_t st) {
+    const int blocks = e.n_samples * e.n_temps;
+    if (e.L > 16) {
+        constexpr int NT = kMeasureThreadsLarge;
+        if (e.precision == HSG_FP64)
+            hipLaunchKernelGGL((k_measure<double, NT, true>), dim3(blocks), dim3(NT), 0, st, e, n_tiles, ctr_add);
+        else
+            hipLaunchKernelGGL((k_measure<float, NT, true>), dim3(blocks), dim3(NT), 0, st, e, n_tiles, ctr_add);
+    } else {
+        if (e.precision == HSG_FP64)
+            hipLaunchKernelGGL((k_measure<double, 128, true>), dim3(blocks), dim3(128), 0, st, e, n_tiles, ctr_add);
+        else
+            hipLaunchKernelGGL((k_measure<float, 128, true>), dim3(blocks), dim3(128), 0, st, e, n_tiles, ctr_add);
+    }
     return hipGetLastError();
 }
 

@@ -65,9 +65,12 @@ hipError_t launch_wave_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int
 
 // Streaming path: one launch per half-sweep, any even L.  The per-tile energy sums go
 // to `partial` ([slots][max_tiles] doubles), or to the ensemble's scratch if null.
+// defer_last: the last sweep's per-tile sums are left for launch_measure_fin to add up
+// (energies, sweep counters), which then must follow on the same stream; *n_tiles_out
+// (if given) receives the tiles per slot.
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
                                 int block_threads, int replicas_per_block, double* partial,
-                                hipStream_t st);
+                                hipStream_t st, bool defer_last = false, int* n_tiles_out = nullptr);
 // Capacity (doubles) of the library's own device array that serves as `partial` for
 // callers that cannot allocate, and its address on the current device.
 constexpr size_t kStaticPartialDoubles = size_t(1) << 19;  // 4 MiB
@@ -82,6 +85,10 @@ hipError_t launch_energy(const hsg_ensemble& e, double* out, hipStream_t st);
 hipError_t launch_swap(const hsg_ensemble& e, int pairing, hipStream_t st);
 hipError_t launch_anneal_decide(const hsg_ensemble& e, int parity, hipStream_t st);
 hipError_t launch_measure(const hsg_ensemble& e, hipStream_t st);
+// The measurement that also finishes a streaming sweep launched with defer_last: each
+// slot's energy from its n_tiles per-tile sums in the scratch (in tile order, as the
+// sweep's own finishing pass adds them), and sweep_ctr += ctr_add.
+hipError_t launch_measure_fin(const hsg_ensemble& e, int n_tiles, int ctr_add, hipStream_t st);
 hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st);
 // eps_pair: nullptr (eps for every pair) or a device array of n_temps - 1 parameters.
 hipError_t launch_coolheat(const hsg_ensemble& e, int pairing, double eps, const double* eps_pair, hipStream_t st);

@@ -169,7 +169,7 @@ static hipError_t half_prec(const hsg_ensemble& e, const StreamArgs& a, int gy, 
 // or in the caller's scratch if it is null.
 hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, int n_or,
                                 int block_threads, int replicas_per_block, double* partial,
-                                hipStream_t st) {
+                                hipStream_t st, bool defer_last, int* n_tiles_out) {
     const int nt = block_threads > 0 ? block_threads : 256;
     int rb = replicas_per_block > 0 ? replicas_per_block : 1;
     const int CR = e.n_chains * e.n_temps;
@@ -177,6 +177,7 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
     const int NQ = e.L * e.L * e.L / 4;
     StreamArgs a{};
     a.n_tiles = (NQ + nt - 1) / nt;
+    if (n_tiles_out) *n_tiles_out = a.n_tiles;
     a.partial = partial ? partial
                         : reinterpret_cast<double*>(static_cast<unsigned char*>(e.scratch) + scratch_layout(e).partial);
     const int n_slots = e.n_samples * CR;
@@ -194,6 +195,7 @@ hipError_t launch_stream_sweeps(const hsg_ensemble& e, int n_sweeps, int n_hb, i
             if (err != hipSuccess) return err;
         }
         const int last = (k == n_sweeps - 1);
+        if (last && defer_last) break;
         hipLaunchKernelGGL(k_stream_finalize, dim3((n_slots + 255) / 256), dim3(256), 0, st, e,
                            a.partial, a.n_tiles, 0, 0, k, last ? n_sweeps : 0);
         hipError_t err = hipGetLastError();

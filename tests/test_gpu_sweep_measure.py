@@ -128,7 +128,12 @@ def _assert_same(a, b, fused_energy_bitwise):
     ("fp32", 8, 1, 1),    # one chain: no overlap
     ("fp32", 8, 3, 2),    # three chains: Q of chains 0 and 1
     ("fp64", 16, 2, 1),
-    ("fp32", 20, 2, 1),   # streaming size
+    ("fp32", 20, 2, 1),   # streaming size: the measurement finishes the sweep's energies
+    ("fp32", 20, 2, 3),   # ... of the last of three sweeps
+    ("fp64", 18, 2, 2),
+    ("fp32", 18, 1, 1),   # ... with one chain (no overlap)
+    ("fp32", 20, 3, 1),
+    ("fp32", 20, 2, 0),   # no sweep: the measurement alone
     ("fp32", 8, 2, 0),    # no sweep: the measurement alone
 ])
 def test_sweep_measure_equals_sweep_then_measure(prec, L, C, n_sweeps):
