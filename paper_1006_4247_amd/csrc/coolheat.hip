@@ -752,7 +752,28 @@ __global__ void __launch_bounds__(NT) k_coolheat_cool_chain(hsg_ensemble e, ChEp
             cur = 1 - cur;
         }
     }
-    if (t == 0) coolheat_finish_chain(e, ch, R - 2, 1);
+    // finish the call as coolheat_finish_chain does (every pair attempted: no
+    // diagnostics to clear), each slot's round-trip state from its final temperature,
+    // the inverse of the labels in LDS, one thread per slot
+    __shared__ int s_tos[kChainMaxPairs + 1];
+    lds_barrier();
+    for (int r = t; r < R; r += NT) s_tos[r] = -1;
+    lds_barrier();
+    for (int i = t; i < R; i += NT) s_tos[s_sot[i]] = i;
+    lds_barrier();
+    if (t == 0) e.swap_ctr[ch] += 1u;
+    for (int r = t; r < R; r += NT) {
+        const int Tr = s_tos[r];
+        const size_t k = static_cast<size_t>(ch) * R + r;
+        int* rs = e.rt_state + k;
+        long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + k;
+        if (Tr == 0) {
+            if (*rs == 2) *rtt += 1;
+            *rs = 1;
+        } else if (Tr == R - 1) {
+            if (*rs == 1) *rs = 2;
+        }
+    }
 }
 
 template <typename T, int L, int NT, bool PREV, bool HEATALL = false>

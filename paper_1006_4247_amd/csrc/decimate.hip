@@ -625,6 +625,27 @@ __global__ void __launch_bounds__(kPfThreads) k_decimate_pf(hsg_ensemble e) {
         bp = ol;
         bn = ou;
     }
+    // finish the call as k_decimate_finish does (every pair attempted: no diagnostics to
+    // clear): the exchange counter, and each slot's round-trip state from its final
+    // temperature, the inverse of the labels in LDS
+    __shared__ int s_tos[kPfMaxPairs + 1];
+    for (int r = t; r < R; r += NT) s_tos[r] = -1;
+    lds_barrier();
+    for (int i = t; i < R; i += NT) s_tos[s_sot[i]] = i;
+    lds_barrier();
+    if (t == 0) e.swap_ctr[ch] = n + 1u;
+    for (int r = t; r < R; r += NT) {
+        const int T = s_tos[r];
+        const size_t k = static_cast<size_t>(ch) * R + r;
+        int* rs = e.rt_state + k;
+        long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + k;
+        if (T == 0) {
+            if (*rs == 2) *rtt += 1;
+            *rs = 1;
+        } else if (T == R - 1) {
+            if (*rs == 1) *rs = 2;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- split ascending pass
@@ -800,37 +821,38 @@ __global__ void __launch_bounds__(kDecThreads) k_dec_split_apply(hsg_ensemble e,
     }
 }
 
-// Per chain, after every pair: advance the exchange counter, update round trips
-// and clear the diagnostics of the pairs not attempted.
+// After every pair: advance the exchange counter, update round trips and clear the
+// diagnostics of the pairs not attempted.  One thread per (chain, slot): thread r of
+// a chain updates slot r's round-trip state from its final temperature, clears pair r
+// if the pairing left it out, and (r = 0) advances the chain's counter.
 // split_G > 0: the pass ran split over split_G workgroups per chain; the last pair's
-// energies are added up here.
+// energies are added up here (thread r = 0).
 __global__ void k_decimate_finish(hsg_ensemble e, int pairing, int split_G) {
     const int n_chains = e.n_samples * e.n_chains;
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n_chains) return;
     const int R = e.n_temps;
-    if (split_G > 0) dec_split_energies(e, ch, split_G, dec_split(e, ch, split_G));
-    if (e.work) {
-        for (int i = 0; i < R - 1; ++i) {
-            const bool sel = pairing == 0 || (pairing == 1 ? (i % 2) == 0 : (i % 2) == 1);
-            if (!sel) {
-                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2] = 0.0;
-                e.work[(static_cast<size_t>(ch) * (R - 1) + i) * 2 + 1] = -1.0;
-            }
+    const long long b = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= static_cast<long long>(n_chains) * R) return;
+    const int ch = static_cast<int>(b / R), r = static_cast<int>(b % R);
+    if (r == 0) {
+        if (split_G > 0) dec_split_energies(e, ch, split_G, dec_split(e, ch, split_G));
+        e.swap_ctr[ch] += 1u;
+    }
+    if (e.work && r < R - 1) {
+        const bool sel = pairing == 0 || (pairing == 1 ? (r % 2) == 0 : (r % 2) == 1);
+        if (!sel) {
+            e.work[(static_cast<size_t>(ch) * (R - 1) + r) * 2] = 0.0;
+            e.work[(static_cast<size_t>(ch) * (R - 1) + r) * 2 + 1] = -1.0;
         }
     }
-    e.swap_ctr[ch] += 1u;
-    int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
-    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
-    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
-    for (int r = 0; r < R; ++r) {
-        const int T = tos[r];
-        if (T == 0) {
-            if (rs[r] == 2) rtt[r] += 1;
-            rs[r] = 1;
-        } else if (T == R - 1) {
-            if (rs[r] == 1) rs[r] = 2;
-        }
+    const size_t k = static_cast<size_t>(ch) * R + r;
+    const int T = e.temp_of_slot[k];
+    int* rs = e.rt_state + k;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + k;
+    if (T == 0) {
+        if (*rs == 2) *rtt += 1;
+        *rs = 1;
+    } else if (T == R - 1) {
+        if (*rs == 1) *rs = 2;
     }
 }
 
@@ -845,7 +867,7 @@ static hipError_t go_decimate_nt(const hsg_ensemble& e, int pairing, int blocks,
 }
 
 template <typename T, int L>
-static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st, bool* finished) {
     if constexpr (std::is_same<T, float>::value && (L == 8 || L == 16)) {
         constexpr size_t lds = (3 * L * L * L + 4 * 3 * (L * L * L / 2)) * sizeof(float);
         if (pairing == 0 && e.n_temps - 1 <= kPfMaxPairs && lds <= max_block_lds()) {
@@ -853,6 +875,7 @@ static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks
             const hipError_t a = allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
             if (a != hipSuccess) return a;
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(kPfThreads), lds, st, e);
+            *finished = true;
             return hipGetLastError();
         }
     }
@@ -864,15 +887,15 @@ static hipError_t go_decimate_res(const hsg_ensemble& e, int pairing, int blocks
 // LDS-resident variant for L <= 16 (its two kept sublattices fit one workgroup's
 // LDS), the generic kernel otherwise.
 template <typename T>
-static hipError_t go_decimate(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st) {
+static hipError_t go_decimate(const hsg_ensemble& e, int pairing, int blocks, hipStream_t st, bool* finished) {
     switch (e.L) {
-        case 4: return go_decimate_res<T, 4>(e, pairing, blocks, st);
-        case 6: return go_decimate_res<T, 6>(e, pairing, blocks, st);
-        case 8: return go_decimate_res<T, 8>(e, pairing, blocks, st);
-        case 10: return go_decimate_res<T, 10>(e, pairing, blocks, st);
-        case 12: return go_decimate_res<T, 12>(e, pairing, blocks, st);
-        case 14: return go_decimate_res<T, 14>(e, pairing, blocks, st);
-        case 16: return go_decimate_res<T, 16>(e, pairing, blocks, st);
+        case 4: return go_decimate_res<T, 4>(e, pairing, blocks, st, finished);
+        case 6: return go_decimate_res<T, 6>(e, pairing, blocks, st, finished);
+        case 8: return go_decimate_res<T, 8>(e, pairing, blocks, st, finished);
+        case 10: return go_decimate_res<T, 10>(e, pairing, blocks, st, finished);
+        case 12: return go_decimate_res<T, 12>(e, pairing, blocks, st, finished);
+        case 14: return go_decimate_res<T, 14>(e, pairing, blocks, st, finished);
+        case 16: return go_decimate_res<T, 16>(e, pairing, blocks, st, finished);
         default:
             if (pairing == 0)  // binary64 with 512 threads (register budget, as above)
                 hipLaunchKernelGGL((k_decimate<T, sizeof(T) == 4 ? 1024 : 512>), dim3(blocks),
@@ -898,6 +921,11 @@ static int split_groups(const hsg_ensemble& e) {
     return G < 2 ? 1 : static_cast<int>(G);
 }
 
+static unsigned finish_blocks(const hsg_ensemble& e) {
+    const long long n = static_cast<long long>(e.n_samples) * e.n_chains * e.n_temps;
+    return static_cast<unsigned>((n + 255) / 256);
+}
+
 hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
     const int chains = e.n_samples * e.n_chains;
     const int R = e.n_temps;
@@ -915,7 +943,7 @@ hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
             const hipError_t err = hipGetLastError();
             if (err != hipSuccess) return err;
         }
-        hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing, G);
+        hipLaunchKernelGGL(k_decimate_finish, dim3(finish_blocks(e)), dim3(256), 0, st, e, pairing, G);
         return hipGetLastError();
     }
     int blocks = chains;
@@ -924,12 +952,14 @@ hipError_t launch_decimate(const hsg_ensemble& e, int pairing, hipStream_t st) {
         const int n_sel = (R - 1 - first + 1) / 2;
         blocks = chains * n_sel;
     }
+    bool finished = false;  // the staged ascending kernel finishes the call itself
     if (blocks > 0) {
-        hipError_t err = e.precision == HSG_FP64 ? go_decimate<double>(e, pairing, blocks, st)
-                                                 : go_decimate<float>(e, pairing, blocks, st);
+        hipError_t err = e.precision == HSG_FP64 ? go_decimate<double>(e, pairing, blocks, st, &finished)
+                                                 : go_decimate<float>(e, pairing, blocks, st, &finished);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(k_decimate_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e, pairing, 0);
+    if (finished) return hipSuccess;
+    hipLaunchKernelGGL(k_decimate_finish, dim3(finish_blocks(e)), dim3(256), 0, st, e, pairing, 0);
     return hipGetLastError();
 }
 
