@@ -386,7 +386,7 @@ __global__ void k_anneal_copyback(hsg_ensemble e) {
 // Q_ab = sum_x s^(0)_{a,x} s^(1)_{b,x} between chains 0 and 1 at temperature b,
 // chi = Q:Q / N (paper Sec. II); e = H/N by temperature.  Workgroup per (sample, b).
 // FIN: first finish a streaming sweep whose last finishing pass was left out: the
-// energy of each slot it reads from the per-tile sums (n_tiles of them, in tile
+// energy of each slot it reads from the per-tile sums (n_tiles of them, added in tile
 // order, as k_stream_finalize adds them), and sweep_ctr += ctr_add.  Every slot is one
 // (sample, chain, temperature), so each is finished by exactly one workgroup.
 template <typename T, int NT, bool FIN = false>
@@ -396,21 +396,33 @@ __global__ void __launch_bounds__(NT) k_measure(hsg_ensemble e, int n_tiles = 0,
     const int N = e.L * e.L * e.L;
     const int R = e.n_temps, C = e.n_chains;
     const int smp = blockIdx.x / R, b = blockIdx.x % R;
-    for (int c = threadIdx.x; c < C; c += NT) {
-        const int slot = (smp * C + c) * R + label(e.slot_of_temp[(smp * C + c) * R + b], R, e.guard);
-        double H;
-        if (FIN) {
-            const ScratchLayout sl = scratch_layout(e);
-            const double* part = reinterpret_cast<const double*>(static_cast<const unsigned char*>(e.scratch) + sl.partial);
-            H = 0.0;
-            for (int t = 0; t < n_tiles; ++t) H += part[static_cast<size_t>(slot) * sl.max_tiles + t];
-            if (!isfinite(H)) atomicOr(e.guard, 1);
-            e.energy[slot] = H;
-            e.sweep_ctr[slot] += static_cast<uint32_t>(ctr_add);
-        } else {
-            H = e.energy[slot];
+    if (FIN) {
+        // one wave per chain: its lanes load 64 per-tile sums at a time, which are then
+        // added one lane after another (the finishing pass's order)
+        const ScratchLayout sl = scratch_layout(e);
+        const double* part = reinterpret_cast<const double*>(static_cast<const unsigned char*>(e.scratch) + sl.partial);
+        const int lane = threadIdx.x & 63;
+        for (int c = threadIdx.x >> 6; c < C; c += NW) {
+            const int slot = (smp * C + c) * R + label(e.slot_of_temp[(smp * C + c) * R + b], R, e.guard);
+            const double* ps = part + static_cast<size_t>(slot) * sl.max_tiles;
+            double H = 0.0;
+            for (int t0 = 0; t0 < n_tiles; t0 += 64) {
+                const double v = t0 + lane < n_tiles ? ps[t0 + lane] : 0.0;
+                const int m = n_tiles - t0 < 64 ? n_tiles - t0 : 64;
+                for (int j = 0; j < m; ++j) H += readlane_f64(v, j);
+            }
+            if (lane == 0) {
+                if (!isfinite(H)) atomicOr(e.guard, 1);
+                e.energy[slot] = H;
+                e.sweep_ctr[slot] += static_cast<uint32_t>(ctr_add);
+                e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = H / static_cast<double>(N);
+            }
         }
-        e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = H / static_cast<double>(N);
+    } else {
+        for (int c = threadIdx.x; c < C; c += NT) {
+            const int slot = (smp * C + c) * R + label(e.slot_of_temp[(smp * C + c) * R + b], R, e.guard);
+            e.e_temp[(static_cast<size_t>(smp) * C + c) * R + b] = e.energy[slot] / static_cast<double>(N);
+        }
     }
     if (C < 2 || e.Q == nullptr) return;  // uniform over the block
     const int s1 = (smp * C + 0) * R + label(e.slot_of_temp[(smp * C + 0) * R + b], R, e.guard);
