@@ -267,8 +267,13 @@ hsg_status hsg_measure(const hsg_ensemble* ens, int n_ens, void* stream);
  * rounding order of their FP64 sums.  Ensembles of exactly two chains with L <= 10
  * (binary32) or L <= 12 (binary64) take one launch, in which a workgroup sweeps both
  * chains' replicas of a temperature and measures them from LDS (measured faster
- * there); other ensembles take the two launches.  Needs what both calls need;
- * n_sweeps = 0 measures only. */
+ * there); binary32 ones at L = 16 take one launch in which a workgroup sweeps the two
+ * replicas of a temperature in turn, the couplings loaded once, and then measures
+ * them.  On the streaming path (lattices whose replica does not fit one workgroup's
+ * LDS) the measurement also adds up the last sweep's per-tile energies, in place of
+ * the sweep's own finishing launch, in the same order (energies and counters bit for
+ * bit those of hsg_sweep).  Other ensembles take the two calls.  Needs what both
+ * calls need; n_sweeps = 0 measures only. */
 hsg_status hsg_sweep_measure(const hsg_ensemble* ens, int n_ens, int n_sweeps, int n_hb, int n_or,
                              void* stream);
 
