@@ -1010,6 +1010,20 @@ def main():
                                        "ms_per_step": h64["ms_per_step"],
                                        "sweep_kernel_avg_ms": h64["roofline"]["avg_launch_ms"],
                                        "kernel": h64["roofline"]["kernel"], "steps": max(args.steps, 200)}
+        # one GPU's share of the workload when it runs on N GPUs (64 / N samples each):
+        # the shards exchange nothing during the run, so a GPU's share at its real
+        # shape is what decides the job's rate; fewer samples per launch fill fewer CUs
+        phase("one GPU's share of the workload on 2, 4 and 8 GPUs")
+        shares = {}
+        for n in (2, 4, 8):
+            if w["S"] % n:
+                continue
+            hn = headline(torch, hsg, dict(w, S=w["S"] // n), max(args.steps, 200), args.warmup, 0.3)
+            shares[str(n)] = {"samples": w["S"] // n, "value": hn["value"], "unit": "site-updates/ns",
+                              "ms_per_step": hn["ms_per_step"],
+                              "sweep_kernel_avg_ms": hn["roofline"]["avg_launch_ms"],
+                              "steps": max(args.steps, 200)}
+        line["per_gpu_share"] = shares
         phase("uneven batch (five size classes, beyond the MALL)")
         line["uneven_batch"] = uneven_study(torch, hsg, args.uneven_steps)
         phase("learned schedule at L=32 (16 x 2 x 10)")
