@@ -1119,22 +1119,23 @@ __global__ void __launch_bounds__(kChThreads) k_ch_split_decide(hsg_ensemble e, 
 
 // Per chain, after the pass: exchange counter and round trips.
 __global__ void k_ch_split_finish(hsg_ensemble e) {
+    // one thread per (chain, slot): slot r's round-trip state from its temperature; the
+    // thread of slot 0 advances the chain's counter
     const int n_chains = e.n_samples * e.n_chains;
-    const int ch = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (ch >= n_chains) return;
     const int R = e.n_temps;
-    e.swap_ctr[ch] += 1u;
-    const int* tos = e.temp_of_slot + static_cast<size_t>(ch) * R;
-    int* rs = e.rt_state + static_cast<size_t>(ch) * R;
-    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + static_cast<size_t>(ch) * R;
-    for (int r = 0; r < R; ++r) {
-        const int Tr = tos[r];
-        if (Tr == 0) {
-            if (rs[r] == 2) rtt[r] += 1;
-            rs[r] = 1;
-        } else if (Tr == R - 1) {
-            if (rs[r] == 1) rs[r] = 2;
-        }
+    const long long b = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= static_cast<long long>(n_chains) * R) return;
+    const int ch = static_cast<int>(b / R), r = static_cast<int>(b % R);
+    if (r == 0) e.swap_ctr[ch] += 1u;
+    const size_t k = static_cast<size_t>(ch) * R + r;
+    const int Tr = e.temp_of_slot[k];
+    int* rs = e.rt_state + k;
+    long long* rtt = reinterpret_cast<long long*>(e.rt_trips) + k;
+    if (Tr == 0) {
+        if (*rs == 2) *rtt += 1;
+        *rs = 1;
+    } else if (Tr == R - 1) {
+        if (*rs == 1) *rs = 2;
     }
 }
 
@@ -1162,7 +1163,8 @@ static hipError_t coolheat_split_pass(const hsg_ensemble& e, const ChEps& ce, in
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_ch_split_decide<T>, dim3(chains * G), dim3(kChThreads), 0, st, e, R - 2, G);
-    hipLaunchKernelGGL(k_ch_split_finish, dim3((chains + 63) / 64), dim3(64), 0, st, e);
+    const long long n_fin = static_cast<long long>(chains) * R;
+    hipLaunchKernelGGL(k_ch_split_finish, dim3(static_cast<unsigned>((n_fin + 255) / 256)), dim3(256), 0, st, e);
     return hipGetLastError();
 }
 

@@ -167,6 +167,10 @@ def test_coolheat_ascending_fp32(L):
                 if clean:
                     full += 1
                     assert np.array_equal(st["temp_of_slot"][s, c], ref.temp_of_slot[s, c])
+                    # round trips: the chain kernel (L <= 16) and the split pass's
+                    # finishing launch update them, one thread per slot
+                    assert np.array_equal(st["rt_state"][s, c], ref.rt_state[s, c])
+                    assert np.array_equal(st["rt_trips"][s, c], ref.rt_trips[s, c])
                     assert np.abs(st["spins"][s, c] - ref.spins[s, c]).max() <= 3.0 * bar
         ref.set_state(spins=st["spins"].astype(np.float64))
         for k in ("temp_of_slot", "slot_of_temp", "stats", "rt_state", "rt_trips"):
